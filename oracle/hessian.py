@@ -1,0 +1,135 @@
+"""Oracle: the data-space Hessian in time and frequency (FP64).
+
+Test infrastructure only (see the package docstring).
+
+Forms computed here (all for one survey; receivers i, j; grid points x):
+
+* ``time_domain_blocks``: block (i, j) of Q without the penalty, as the sum over
+  x of products of lower-triangular Toeplitz matrices built from the Green
+  functions (Direct Hessian-inverse computation, block equation of the
+  Hessian).  Brute force, micro grids only.
+* ``alg2_literal``: the Fourier block-diagonal approximation exactly in the
+  order of the paper's algorithm for the Fourier block-diagonal Hessian:
+  weighting function W(m, n) = min(Nt - m, Nt - n); for i and j >= i form
+  G^{ij} = sum_x g^i g^{jT}; sum W o G^{ij} along descending diagonals into
+  q^{ij}_xi, xi = n - m; 2Nt-length transform with the paper's normalisation
+  qhat_k = (1/2Nt) sum_xi q_xi exp(+i 2 pi k xi / 2Nt); Hermitian fill.  Only on
+  frequencies that are bins of the 2Nt-point transform.
+* ``hessian_r1``: Hhat(w) = Ghat(w) Ghat(w)^H, Ghat the final DFT of each Green
+  function.  This is the algorithm with W replaced by a constant (the long-record
+  Toeplitz limit the paper invokes when it lets t grow), written with the
+  transfer-function normalisation (no 1/2Nt, and W = 1): Hhat = 2Nt qhat|_{W=1}.
+* ``hessian_r2``: the finite-record weighting kept exactly, evaluated without
+  the 2Nt transform as the time average of running-DFT Gram matrices:
+  Hhat_W(w) = (1/Nt) sum_{p=1}^{Nt} Ghat_p(w) Ghat_p(w)^H with Ghat_p the DFT
+  truncated after sample p.  Equals 2 qhat of the literal algorithm with W.
+
+Pins (tests/test_oracle_hessian.py): the Toeplitz blocks against S S^T built
+column by column from PDE solves; the diagonal-sum structure of Q; the literal
+algorithm against the diagonal of the 2Nt-point transform of the zero-embedded
+brute-force Q (computed with numpy's FFT); R1 and R2 against the literal
+algorithm (W = 1 and W as defined); Hermitian positive-definiteness.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def toeplitz_lower(v: np.ndarray) -> np.ndarray:
+    """T(v): lower-triangular Toeplitz matrix with first column v."""
+    n = len(v)
+    T = np.zeros((n, n))
+    for k in range(n):
+        T[k:, k] = v[: n - k]
+    return T
+
+
+def time_domain_blocks(gt: np.ndarray) -> np.ndarray:
+    """Q^{ij} = sum_x T(g^i(:, x)) T(g^j(:, x))^T for all i, j.
+
+    ``gt`` holds time samples ``[nr][nt][nsub]``.  Returns ``[nr][nr][nt][nt]``
+    (the penalty is not included).  Cost O(nr^2 nsub nt^3): micro sizes only.
+    """
+    nr, nt, nsub = gt.shape
+    T = np.zeros((nr, nsub, nt, nt))
+    for i in range(nr):
+        for x in range(nsub):
+            T[i, x] = toeplitz_lower(gt[i, :, x])
+    Q = np.zeros((nr, nr, nt, nt))
+    for i in range(nr):
+        for j in range(nr):
+            Q[i, j] = np.einsum("xab,xcb->ac", T[i], T[j])
+    return Q
+
+
+def time_domain_matrix(gt: np.ndarray, mu: float) -> np.ndarray:
+    """The full (nr nt) x (nr nt) Hessian Q = S S^T + mu I, receiver-major
+    (vec of the Nt x Nr gather stacks one receiver's trace after another)."""
+    nr, nt, _ = gt.shape
+    B = time_domain_blocks(gt)
+    Q = B.transpose(0, 2, 1, 3).reshape(nr * nt, nr * nt)
+    return Q + mu * np.eye(nr * nt)
+
+
+def weighting(nt: int) -> np.ndarray:
+    """W(m, n) = min(Nt - m, Nt - n), m, n = 0..Nt-1 (weighting function)."""
+    m = np.arange(nt)
+    return np.minimum(nt - m[:, None], nt - m[None, :]).astype(np.float64)
+
+
+def alg2_literal(gt: np.ndarray, bins, use_w: bool = True) -> np.ndarray:
+    """The Fourier block-diagonal Hessian, step by step as the paper's algorithm.
+
+    ``gt``: time samples ``[nr][Nt][nsub]`` (vector index m = 0..Nt-1 holds the
+    sample after m+1 steps).  ``bins``: indices k of the 2Nt-point transform.
+    Returns qhat ``[len(bins)][nr][nr]`` complex (paper normalisation, no
+    penalty).  ``use_w=False`` replaces W by ones.
+    """
+    nr, nt, _ = gt.shape
+    W = weighting(nt) if use_w else np.ones((nt, nt))
+    L = 2 * nt
+    out = np.zeros((len(bins), nr, nr), dtype=np.complex128)
+    for i in range(nr):
+        for j in range(i, nr):
+            Gij = gt[i] @ gt[j].T                       # [m][n] = sum_x g^i(m,x) g^j(n,x)
+            WG = W * Gij
+            q = np.zeros(L)                             # q[xi mod 2Nt], xi = n - m
+            for xi in range(-nt + 1, nt):
+                q[xi % L] = np.trace(WG, offset=xi)     # entries (m, m + xi)
+            # qhat_k = (1/2Nt) sum_xi q_xi exp(+i 2 pi k xi / 2Nt)
+            spec = np.fft.ifft(q)                       # = (1/L) sum q e^{+i2pi k xi/L}
+            for b, k in enumerate(bins):
+                out[b, i, j] = spec[k]
+                out[b, j, i] = np.conj(spec[k])
+    return out
+
+
+def hessian_r1(ghat: np.ndarray) -> np.ndarray:
+    """Hhat(w)[i][j] = sum_x ghat_i(w, x) conj(ghat_j(w, x)); ``ghat`` is
+    ``[nf][nr][nsub]`` complex.  Returns ``[nf][nr][nr]`` complex128."""
+    g = np.asarray(ghat, dtype=np.complex128)
+    return np.einsum("fix,fjx->fij", g, np.conj(g), optimize=True)
+
+
+def running_dft_gram(gt: np.ndarray, freqs_hz, dt: float) -> np.ndarray:
+    """(1/Nt) sum_{p=1}^{Nt} Ghat_p Ghat_p^H at each frequency (the R2 form).
+
+    Ghat_p(w, x) = sum_{n=1}^{p} g(n, x) exp(-i w n dt).  ``gt`` is
+    ``[nr][Nt][nsub]``.  Cost O(nf nr^2 nsub Nt): small sizes only.
+    """
+    nr, nt, nsub = gt.shape
+    w = 2.0 * math.pi * np.asarray(freqs_hz, dtype=np.float64)
+    out = np.zeros((len(w), nr, nr), dtype=np.complex128)
+    for f, wf in enumerate(w):
+        acc = np.zeros((nr, nsub), dtype=np.complex128)
+        for p in range(1, nt + 1):
+            acc += gt[:, p - 1, :] * np.exp(-1j * wf * p * dt)
+            out[f] += acc @ acc.conj().T
+    return out / nt
+
+
+def hessian_r2(gt: np.ndarray, freqs_hz, dt: float) -> np.ndarray:
+    """Finite-record (W-weighted) Hessian without penalty, ``[nf][nr][nr]``."""
+    return running_dft_gram(gt, freqs_hz, dt)

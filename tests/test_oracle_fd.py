@@ -1,0 +1,136 @@
+"""Pins of the oracle's finite-difference Green functions and DFT (CPU only).
+
+Each test checks the oracle against something other than itself: the 2D
+closed-form Green function, exactness of the stencil on polynomials, discrete
+reciprocity, energy conservation, numpy's FFT, and adjointness.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.special as sp
+
+import synth
+from oracle import fd
+
+ALPHA = 12.0  # damping of the DFT (1/s) so that the finite record is negligible
+
+
+def _hankel_errors(n, nb, h, dt, nt, freqs=(3.0, 6.0, 9.0), radii=(100.0, 200.0, 300.0)):
+    c = n // 2
+    s = synth.homogeneous(n=n, nb=nb, h=h, nt=nt, dt=dt, rec=((c, c),))
+    gt = fd.green_samples(s.velocity(), s.nb, s.h, s.dt, s.nt, s.rec_iz, s.rec_ix, 1)
+    t = np.arange(1, nt + 1) * dt
+    errs = []
+    for f in freqs:
+        w = 2.0 * math.pi * f
+        damp = np.exp(-(1j * w + ALPHA) * t)
+        for r in radii:
+            ir = int(round(r / h))
+            g = np.dot(damp, gt[0, :, c, c + ir]) / (h * h)
+            # outgoing 2D Green function of m u_tt - lap u = delta(x) delta(t) with the
+            # forward transform exp(-i w t): (lap + k^2) G = -delta, G = (-i/4) H0^(2)(k r)
+            k = (w - 1j * ALPHA) / 2000.0
+            ref = -0.25j * sp.hankel2(0, k * r)
+            errs.append(abs(g - ref) / abs(ref))
+    return np.array(errs)
+
+
+def test_green_matches_hankel_and_converges():
+    coarse = _hankel_errors(161, 30, 10.0, 1.0e-3, 1500)
+    assert coarse.max() < 2e-3, coarse
+    fine = _hankel_errors(321, 60, 5.0, 0.5e-3, 3000)
+    assert fine.max() < 6e-4, fine
+    # halving h and dt must cut the error by ~4 (2nd order in time dominates)
+    assert np.all(coarse / fine > 2.0), coarse / fine
+
+
+def test_laplacian_exact_on_quartic():
+    # the 4th-order stencil is exact for polynomials of degree <= 5
+    Z, X, h = 12, 14, 2.0
+    z = np.arange(Z)[:, None] * h
+    x = np.arange(X)[None, :] * h
+    u = z ** 4 - 3.0 * x ** 3 + z * x ** 2 + 7.0
+    lap = fd.laplacian(u, h)
+    exact = 12.0 * z ** 2 - 18.0 * x + 2.0 * z + 0.0 * x
+    np.testing.assert_allclose(lap[2:-2, 2:-2], exact[2:-2, 2:-2], rtol=1e-12, atol=1e-9)
+
+
+def test_reciprocity_tiny():
+    s = synth.tiny().with_(nt=300)
+    v = s.velocity()
+    recs = [0, 5, 11, 15]
+    gt = fd.green_samples(v, s.nb, s.h, s.dt, s.nt, [s.rec_iz[i] for i in recs],
+                          [s.rec_ix[i] for i in recs], 1)
+    scale = np.abs(gt).max()
+    for a, i in enumerate(recs):
+        for b, j in enumerate(recs):
+            gij = gt[a, :, s.rec_iz[j], s.rec_ix[j]]
+            gji = gt[b, :, s.rec_iz[i], s.rec_ix[i]]
+            assert np.abs(gij - gji).max() <= 1e-13 * scale
+
+
+def test_energy_conserved_without_sponge():
+    s = synth.micro(nz=40, nx=50, nb=0, nt=400)
+    med = fd.Medium(s.velocity(), 0, s.h, s.dt)
+    src = np.zeros((1,) + med.shape)
+    src[0, 10, 20] = 1.0
+    hist = []
+
+    def inject(n):
+        return src if n == 0 else None
+
+    prev = [np.zeros((1,) + med.shape)]
+
+    def record(n, u):
+        # E^{n-1/2} = sum (u^n - u^{n-1})^2 / kappa - sum u^n L4 u^{n-1}
+        up = prev[0]
+        if n >= 2:
+            e = np.sum((u - up) ** 2 / med.kappa) - np.sum(u * fd.laplacian(up, med.h))
+            hist.append(e)
+        prev[0] = u.copy()
+
+    fd.propagate(med, s.nt, 1, inject, record)
+    hist = np.array(hist)
+    assert hist[0] > 0
+    assert np.abs(hist - hist[0]).max() <= 1e-11 * hist[0]
+
+
+def test_dft_matches_fft_on_bins():
+    rng = np.random.default_rng(5)
+    nt, dt = 64, 2e-3
+    g = rng.standard_normal((3, nt, 7))
+    bins = [0, 1, 5, 17, 63, 64]
+    freqs = [k / (2 * nt * dt) for k in bins]
+    got = fd.dft(g, freqs, dt)
+    x = np.zeros((3, 2 * nt, 7))
+    x[:, 1:nt + 1] = g                      # sample n sits at time index n
+    ref = np.fft.fft(x, axis=1)[:, bins]    # [nr][k][x]
+    np.testing.assert_allclose(got, ref.transpose(1, 0, 2), rtol=1e-12, atol=1e-12)
+
+
+def test_forward_adjoint_are_transposes():
+    s = synth.micro(nz=16, nx=18, nb=4, nt=30, nr=3)
+    op = fd.ForwardOperator(s.velocity(), s.nb, s.h, s.dt, s.nt, s.rec_iz, s.rec_ix, 1)
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal((s.nt, op.nsub))
+    d = rng.standard_normal((op.nr, s.nt))
+    lhs = np.vdot(op.apply(f), d)
+    rhs = np.vdot(f, op.adjoint(d))
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1e-300) + 1e-300
+
+
+def test_forward_operator_reproduces_green_functions():
+    # S applied to a unit impulse at (step 0, subgrid point of receiver j) gives
+    # g_j at the receivers: the Green functions are the impulse responses of S.
+    s = synth.micro(nz=16, nx=18, nb=4, nt=30, nr=3)
+    v = s.velocity()
+    op = fd.ForwardOperator(v, s.nb, s.h, s.dt, s.nt, s.rec_iz, s.rec_ix, 1)
+    gt = fd.green_samples(v, s.nb, s.h, s.dt, s.nt, s.rec_iz, s.rec_ix, 1)
+    for j in range(op.nr):
+        f = np.zeros((s.nt, s.nz, s.nx))
+        f[0, s.rec_iz[j], s.rec_ix[j]] = 1.0
+        d = op.apply(f.reshape(s.nt, -1))
+        for i in range(op.nr):
+            np.testing.assert_allclose(d[i], gt[j, :, s.rec_iz[i], s.rec_ix[i]], rtol=1e-13,
+                                       atol=1e-15 * np.abs(gt).max())
