@@ -1,0 +1,208 @@
+#!/usr/bin/env python
+"""Benchmark of the data-space Hessian build and inversion on one MI355X.
+
+One step = one survey through the whole hot path with inputs resident in HBM:
+Green functions by FD with the on-the-fly DFT, Hessian contraction, penalty +
+Cholesky, and the multi-source deblur of all sources at all frequencies.
+
+Default workload: layered 1000 x 300 grid (h = 10 m, 40-cell sponge),
+200 receivers, nt = 4000 at 0.8 ms, 30 frequencies over 3-15 Hz, 200 sources,
+split-BF16 precision form.
+
+Prints one JSON line (see the repository's benchmark contract).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Hessian build+factor s/survey; multiplier solves/s; % HBM/MFMA roofline"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="layered_1000x300")
+    ap.add_argument("--precision", default="split_bf16", choices=["split_bf16", "plain_fp32"])
+    ap.add_argument("--nr-batch", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=300, help="FD steps in the CPU sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(s, fd_steps):
+    """Time the FP64 oracle on a bounded sample and scale it to one survey."""
+    import numpy as np
+
+    from oracle import fd, hessian, solve
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = os.cpu_count() or 1
+    v = s.velocity()
+    # FD + DFT of one Green function over fd_steps steps on the full grid
+    t0 = time.perf_counter()
+    gt = fd.green_samples(v, s.nb, s.h, s.dt, fd_steps, s.rec_iz[:1], s.rec_ix[:1], s.stride)
+    fd.dft(gt, s.freqs_hz, s.dt)
+    t_fd = time.perf_counter() - t0
+    del gt
+    # one frequency's Hessian at full size from seeded spectra
+    rng = np.random.default_rng(0)
+    G = rng.standard_normal((1, s.nr, s.nsub)) + 1j * rng.standard_normal((1, s.nr, s.nsub))
+    t0 = time.perf_counter()
+    H = hessian.hessian_r1(G)
+    t_h = time.perf_counter() - t0
+    # all Cholesky factorisations and solves at full size
+    Hs = np.repeat(H, s.nf, axis=0)
+    R = s.residuals().astype(np.complex128)
+    t0 = time.perf_counter()
+    L = solve.cholesky(solve.penalize(Hs, 1e-3 * float(np.real(H[0].trace()))))
+    t_c = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    solve.solve(L, R)
+    t_s = time.perf_counter() - t0
+    survey_s = t_fd / fd_steps * s.nt * s.nr + t_h * s.nf + t_c
+    return {
+        "value": survey_s,
+        "unit": "s/survey",
+        "cores": int(blas_threads),
+        "kind": "oracle",
+        "sample": (f"FP64 numpy oracle: 1 Green function x {fd_steps} steps of FD+DFT on the full "
+                   f"grid ({t_fd:.2f} s), 1 of {s.nf} Hessians at full size ({t_h:.2f} s), all "
+                   f"{s.nf} Cholesky factorisations ({t_c:.2f} s); scaled to {s.nr} Green functions "
+                   f"x {s.nt} steps and {s.nf} Hessians. Multi-source solve {t_s:.3f} s "
+                   f"({s.nf * s.ns / t_s:.0f} solves/s)"),
+        "solves_per_s": s.nf * s.ns / t_s,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
+              "described in DESIGN.md and not benchmarked", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2512_16642_amd import costs, ehi
+
+    s = synth.WORKLOADS[args.workload]()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    vel = torch.from_numpy(s.velocity()).to(dev)
+    R = torch.from_numpy(s.residuals()).to(dev)
+    X = torch.empty_like(R)
+    sv = ehi.survey_from(s, precision=args.precision, max_ns=s.ns, nr_batch=args.nr_batch)
+    print(f"# workload {s.name} precision {args.precision} workspace {sv.workspace_bytes / 1e9:.2f} GB",
+          file=sys.stderr, flush=True)
+
+    # mu = 1e-3 * max_w lambda_max(Hhat(w)) from a first build (not timed)
+    sv.build_green(vel)
+    sv.build_hessian()
+    mu = 1e-3 * sv.lambda_max()
+    for _ in range(args.warmup):
+        sv.build_green(vel)
+        sv.build_hessian()
+        sv.factor(mu)
+        sv.apply_multipliers(R, out=X)
+    torch.cuda.synchronize()
+    print(f"# warmup done, mu = {mu:.6e}", file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream()
+    stage = {"build_green": 0.0, "build_hessian": 0.0, "factor": 0.0, "apply": 0.0}
+    sv.read_profile()
+    sv.profile(True)
+    torch.cuda.synchronize()
+    t_wall0 = time.perf_counter()
+    for k in range(args.steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record(stream)
+        sv.build_green(vel)
+        ev[1].record(stream)
+        sv.build_hessian()
+        ev[2].record(stream)
+        sv.factor(mu)
+        ev[3].record(stream)
+        sv.apply_multipliers(R, out=X)
+        ev[4].record(stream)
+        ev[4].synchronize()
+        for i, key in enumerate(stage):
+            stage[key] += ev[i].elapsed_time(ev[i + 1])
+        print(f"# step {k} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall0
+    sv.profile(False)
+    prof = sv.read_profile()
+    K = args.steps
+    stage_ms = {k: v / K for k, v in stage.items()}
+    survey_s = (stage_ms["build_green"] + stage_ms["build_hessian"] + stage_ms["factor"]) / 1e3
+    solves_per_s = s.nf * s.ns / (stage_ms["apply"] / 1e3)
+
+    # roofline of the dominant kernel (the stencil step)
+    nrb = args.nr_batch if args.nr_batch > 0 else s.nr
+    step_ms, step_launches = prof["step"]
+    avg_step_s = step_ms / 1e3 / max(step_launches, 1)
+    bytes_launch = costs.stencil_bytes_per_launch(s.nz, s.nx, s.nb, s.stride, nrb)
+    achieved = bytes_launch / avg_step_s / 1e9
+    roof = {
+        "kernel": "k_step (stencil time step)",
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "avg_launch_us": round(avg_step_s * 1e6, 2),
+        "bytes_per_launch": bytes_launch,
+        "bytes_per_cell_update": costs.stencil_bytes_per_cell_update(s.nz, s.nx, s.nb, s.stride, nrb),
+    }
+    cell_updates = costs.stencil_cell_updates_per_survey(s.nz, s.nx, s.nb, s.nr, s.nt)
+    herk_flops = costs.herk_flops_per_survey(s.nz, s.nx, s.stride, s.nr, s.nf)
+    herk_ms = prof["herk"][0] / K
+    out = {
+        "metric": METRIC,
+        "value": round(survey_s, 6),
+        "unit": "s/survey",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_wall / K * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": s.name, "precision": args.precision, "nz": s.nz, "nx": s.nx,
+                   "nb": s.nb, "nr": s.nr, "nt": s.nt, "nf": s.nf, "ns": s.ns, "stride": s.stride,
+                   "nr_batch": nrb},
+        "solves_per_s": round(solves_per_s, 1),
+        "sources_per_s": round(s.ns / (stage_ms["apply"] / 1e3), 2),
+        "stage_ms": {k: round(v, 3) for k, v in stage_ms.items()},
+        "kernel_ms": {k: round(v[0] / K, 3) for k, v in prof.items()},
+        "gcell_updates_per_s": round(cell_updates / (prof["step"][0] / K / 1e3) / 1e9, 2),
+        "herk_tflops": round(herk_flops / (herk_ms / 1e3) / 1e12, 2) if herk_ms > 0 else None,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("# timing the oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_steps)
+    sv.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

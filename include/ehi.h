@@ -1,0 +1,206 @@
+/*
+ * ehi.h - data-space Hessian build and inversion on one MI355X (gfx950).
+ *
+ * Implements the direct inversion of the data-space Hessian of time-domain
+ * extended-source waveform inversion (Sonbolestan & Gholami, arXiv 2512.16642):
+ * the multipliers delta d^e = Q^{-1} delta d of the deblurring system, with
+ * Q = S S^T + mu I (Theory section, the Hessian definition and the deblurring
+ * system), solved one frequency at a time on the block-diagonal Fourier form
+ * (frequency-domain inversion).
+ *
+ * Pipeline (one survey = one model, one receiver set, one time axis):
+ *   ehi_build_green    Nr Green functions by 2D acoustic FD (one impulse source
+ *                      per receiver, block equation of the Hessian) with the DFT
+ *                      at the nf requested frequencies accumulated during the
+ *                      time loop; the time samples are never stored in full.
+ *   ehi_build_hessian  Hhat(w) = Ghat(w) Ghat(w)^H over the grid for every w
+ *                      (the Fourier diagonal of each block, taken in the long
+ *                      record limit where the finite-record weighting is a
+ *                      constant; computation of the Fourier diagonals).
+ *   ehi_factor         Qhat(w) = Hhat(w) + mu I, Cholesky Qhat = L L^H in FP64,
+ *                      kept resident (the paper inverts and stores each block).
+ *   ehi_apply_multipliers
+ *                      X(w) = Qhat(w)^{-1} R(w) for many sources at once.
+ *
+ * Conventions
+ *   - All device pointers are hipMalloc'd (or torch-allocated) memory on the
+ *     device that was current at ehi_create.  The library never allocates
+ *     device memory: every buffer lives in the caller's workspace or in the
+ *     caller's input/output arrays.
+ *   - "stream" arguments are hipStream_t values passed as void*; NULL is the
+ *     default stream.  Work is enqueued asynchronously; only ehi_factor and
+ *     ehi_lambda_max wait on the stream (to read back a status or a value).
+ *   - Complex arrays are interleaved (re, im): complex64 = 2 x float,
+ *     complex128 = 2 x double.
+ *   - Every entry point returns an ehi_status; on failure ehi_last_error()
+ *     gives a message (thread-local, valid until the next call on the thread).
+ *     Functions never throw and never abort.
+ *   - A survey handle is not thread-safe: calls on one handle must not overlap.
+ *     Different handles are independent.
+ */
+#ifndef EHI_H
+#define EHI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EHI_OK = 0,
+  EHI_EINVAL = 1,   /* bad argument or descriptor */
+  EHI_ENOMEM = 2,   /* workspace smaller than ehi_workspace_bytes() */
+  EHI_EHIP = 3,     /* a HIP runtime call failed (message names it) */
+  EHI_ENOTPD = 4,   /* Qhat(w) not positive definite; index reported */
+  EHI_ESTATE = 5    /* call out of order (e.g. factor before build_hessian) */
+} ehi_status;
+
+/* Arithmetic of the Hessian contraction, the factorisation and the solves. */
+typedef enum {
+  /* FP32 contraction, FP32 Cholesky, FP32 solves without refinement */
+  EHI_PREC_PLAIN_FP32 = 0,
+  /* split-BF16 (hi+lo) MFMA contraction with FP32 accumulation, FP64
+     Cholesky, FP32 triangular solves + 2 FP64 iterative-refinement steps */
+  EHI_PREC_SPLIT_BF16 = 1
+} ehi_precision;
+
+/*
+ * Survey descriptor.  Host memory; copied by ehi_create.
+ *   nz, nx    interior grid, row-major [nz][nx], z pointing down.  >= 4 each.
+ *   nb        absorbing layer width in cells on all four sides (>= 0).
+ *   h         grid spacing (m), dt time step (s); the FD scheme needs
+ *             vmax*dt/h <= sqrt(3/8) for stability (not checked: vmax is
+ *             only known on the device).
+ *   nt        number of time steps; samples u^1..u^nt enter the DFT.
+ *   stride    the Hessian contraction runs over interior cells (iz, ix) with
+ *             iz % stride == 0 and ix % stride == 0 (1 <= stride <= 8).
+ *   nr        receivers (1..1024); rec_iz/rec_ix are interior indices (host arrays of
+ *             nr entries), 0 <= rec_iz < nz, 0 <= rec_ix < nx.
+ *   nf        frequencies (1..64); freq_hz: host array of nf values >= 0 (Hz).  Any
+ *             frequencies are allowed (not only 2nt-point transform bins).
+ *   precision an ehi_precision value.
+ *   max_ns    largest number of sources one apply launch processes; larger
+ *             calls are split.  Sizes the refinement scratch.  >= 1.
+ *   nr_batch  receivers time-stepped together (0 = all).  Sizes the
+ *             wavefield buffers.
+ */
+typedef struct {
+  int32_t nz, nx, nb;
+  double h, dt;
+  int32_t nt;
+  int32_t stride;
+  int32_t nr;
+  const int32_t* rec_iz;
+  const int32_t* rec_ix;
+  int32_t nf;
+  const double* freq_hz;
+  int32_t precision;
+  int32_t max_ns;
+  int32_t nr_batch;
+} ehi_survey_desc;
+
+typedef struct ehi_survey ehi_survey;
+
+/* Bytes of device workspace the survey needs (256-byte aligned start
+ * required).  Returns 0 for an invalid descriptor (see ehi_last_error). */
+size_t ehi_workspace_bytes(const ehi_survey_desc* desc);
+
+/* Creates a survey handle over a caller-owned workspace of ws_bytes bytes at
+ * workspace_dev (device memory, 256-byte aligned, kept alive until
+ * ehi_destroy).  Copies the descriptor's host arrays.  Enqueues the twiddle
+ * table set-up (FP64 exp(-i w n dt) rounded to complex64, n = 1..nt) on
+ * stream and waits for it.  *out receives the handle. */
+ehi_status ehi_create(const ehi_survey_desc* desc, void* workspace_dev, size_t ws_bytes,
+                      void* stream, ehi_survey** out);
+
+/* Time-steps the nr Green functions through the velocity model vel_dev
+ * (device, float32 [nz][nx] in m/s, read-only, caller-owned, only read by work
+ * enqueued by this call) and accumulates
+ *   Ghat[f][r][x'] = sum_{n=1}^{nt} g_r(n, x') exp(-i 2 pi freq_hz[f] n dt)
+ * on the stride subgrid x' (interior only).  Medium set-up (sponge, padded
+ * coefficients) runs on the device in FP64 and is rounded to FP32 once.
+ * Asynchronous. */
+ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev);
+
+/* Hhat(w_f)[i][j] = sum_x' Ghat[f][i][x'] conj(Ghat[f][j][x']) for all f,
+ * Hermitian by construction (upper tiles computed, lower mirrored, imaginary
+ * part of the diagonal zero).  Requires ehi_build_green or
+ * ehi_load_green_dft first.  Asynchronous. */
+ehi_status ehi_build_hessian(ehi_survey* s);
+
+/* Qhat(w) = Hhat(w) + mu I (mu > 0, absolute), Cholesky factor of every
+ * frequency, resident in the workspace.  Waits for the stream.  On a
+ * non-positive pivot returns EHI_ENOTPD and stores the first failing
+ * frequency index in *bad_freq (if non-NULL; -1 on success). */
+ehi_status ehi_factor(ehi_survey* s, double mu, int32_t* bad_freq);
+
+/* X(w) = Qhat(w)^{-1} R(w) for ns sources: resid_dev and mult_dev are device
+ * complex64 arrays [nf][ns][nr] (frequency-major, one row of nr receiver
+ * values per source).  They may not alias.  Enqueued on stream (NULL = the
+ * survey's stream); asynchronous.  Requires a successful ehi_factor. */
+ehi_status ehi_apply_multipliers(ehi_survey* s, const void* resid_dev, void* mult_dev,
+                                 int32_t ns, void* stream);
+
+/* max over frequencies of the largest eigenvalue of Hhat(w) (power
+ * iteration in FP64), for choosing mu = eps * lambda_max.  Requires
+ * ehi_build_hessian.  Waits for the stream. */
+ehi_status ehi_lambda_max(ehi_survey* s, double* out);
+
+/* Copies Ghat, complex64 [nf][nr][nzs][nxs] (nzs = ceil(nz/stride),
+ * nxs = ceil(nx/stride)), to the device buffer out_dev.  Asynchronous. */
+ehi_status ehi_copy_green_dft(ehi_survey* s, void* out_dev);
+
+/* Replaces Ghat by the caller's complex64 [nf][nr][nzs][nxs] device array, so
+ * the later stages can be run on given spectra.  Asynchronous. */
+ehi_status ehi_load_green_dft(ehi_survey* s, const void* in_dev);
+
+/* Copies Hhat (no penalty), complex128 [nf][nr][nr] (full Hermitian), to
+ * out_dev.  Requires ehi_build_hessian.  Asynchronous. */
+ehi_status ehi_copy_hessian(ehi_survey* s, void* out_dev);
+
+/* Replaces Hhat by the caller's complex128 [nf][nr][nr] device array, which
+ * must be Hermitian (it is used as given).  Asynchronous. */
+ehi_status ehi_load_hessian(ehi_survey* s, const void* in_dev);
+
+/* Copies the Cholesky factors, complex128 [nf][nr][nr] lower-triangular
+ * (upper part zero), to out_dev.  Requires ehi_factor.  Asynchronous. */
+ehi_status ehi_copy_factor(ehi_survey* s, void* out_dev);
+
+/* Event-based timing of the kernels a survey launches.  Kinds: */
+enum {
+  EHI_PROF_SETUP = 0,   /* medium, twiddle and wavefield set-up */
+  EHI_PROF_STEP = 1,    /* Green-function time steps */
+  EHI_PROF_DFT = 2,     /* DFT accumulation of the staged samples */
+  EHI_PROF_HERK = 3,    /* Hessian contraction and its reduction */
+  EHI_PROF_FACTOR = 4,  /* penalty and Cholesky */
+  EHI_PROF_SOLVE = 5,   /* triangular solves and refinement */
+  EHI_PROF_KINDS = 8
+};
+
+/* enable != 0: from now on, every run of consecutive launches of one kind is
+ * bracketed by a pair of HIP events recorded on the stream it is launched
+ * on.  Events are host-side objects; no device memory is allocated.
+ * enable == 0 stops recording (recorded pairs are kept until read). */
+ehi_status ehi_profile_enable(ehi_survey* s, int enable);
+
+/* Waits for every recorded event, adds the elapsed milliseconds of each kind
+ * into ms[EHI_PROF_KINDS] and the number of kernel launches covered into
+ * launches[EHI_PROF_KINDS] (both zeroed first), then releases the events. */
+ehi_status ehi_profile_read(ehi_survey* s, double* ms, int64_t* launches);
+
+/* Releases the handle (not the workspace).  NULL is accepted. */
+ehi_status ehi_destroy(ehi_survey* s);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* ehi_last_error(void);
+
+/* Library version string. */
+const char* ehi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EHI_H */

@@ -1,0 +1,56 @@
+"""Algorithmic work and traffic of each kernel, per unit and per launch.
+
+These are the models against which the roofline fractions are reported; each
+states the minimum bytes (or flops) the kernel's schedule must move (or do),
+not what caches happen to save.
+
+Units:
+  stencil step   cell-update = one grid cell of the padded grid advanced one
+                 time step for one Green function
+  DFT chunk      sample-frequency = one subgrid sample entering one
+                 frequency's accumulator
+  Hessian        complex multiply-add of the contraction (upper triangle)
+"""
+from __future__ import annotations
+
+
+def padded_cells(nz, nx, nb):
+    return (nz + 2 * nb) * (nx + 2 * nb)
+
+
+def subgrid_points(nz, nx, stride):
+    return ((nz + stride - 1) // stride) * ((nx + stride - 1) // stride)
+
+
+def stencil_bytes_per_cell_update(nz, nx, nb, stride, nrb):
+    """Increment-form step: read u and w, write w and u_next (4 x 4 B); the two
+    coefficient planes (8 B per cell) are shared by the nrb receivers of a
+    launch; the subgrid sample (4 B) goes to the staging buffer."""
+    cells = padded_cells(nz, nx, nb)
+    sub = subgrid_points(nz, nx, stride)
+    return 16.0 + 8.0 / nrb + 4.0 * sub / cells
+
+
+def stencil_bytes_per_launch(nz, nx, nb, stride, nrb):
+    cells = padded_cells(nz, nx, nb) * nrb
+    return cells * stencil_bytes_per_cell_update(nz, nx, nb, stride, nrb)
+
+
+def stencil_cell_updates_per_survey(nz, nx, nb, nr, nt):
+    return padded_cells(nz, nx, nb) * nr * (nt - 1)
+
+
+def dft_flops_per_survey(nz, nx, stride, nr, nt, nf):
+    """4 real flops (2 FMAs) per sample-frequency, real sample x complex twiddle."""
+    return 4.0 * subgrid_points(nz, nx, stride) * nr * nt * nf
+
+
+def herk_flops_per_survey(nz, nx, stride, nr, nf):
+    """Upper triangle incl. diagonal of the complex contraction, 8 flops per
+    complex multiply-add."""
+    return 8.0 * nr * (nr + 1) / 2 * subgrid_points(nz, nx, stride) * nf
+
+
+def herk_bytes_per_survey(nz, nx, stride, nr, nf):
+    """Reading the complex64 spectra once."""
+    return 8.0 * subgrid_points(nz, nx, stride) * nr * nf

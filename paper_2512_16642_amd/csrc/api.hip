@@ -1,0 +1,490 @@
+// The C ABI of libehi (declared in include/ehi.h): descriptor validation,
+// workspace layout, state machine and the launch sequence of each stage.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "ehi_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+ehi_status fail(ehi_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+ehi_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return EHI_EHIP;
+}
+
+#define EHI_TRY(call, what)                        \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+bool validate(const ehi_survey_desc* d, std::string* why) {
+  auto bad = [&](const char* m) {
+    *why = m;
+    return false;
+  };
+  if (!d) return bad("descriptor is NULL");
+  if (d->nz < 4 || d->nx < 4) return bad("nz and nx must be >= 4");
+  if (d->nb < 0 || d->nb > 1024) return bad("nb must be in [0, 1024]");
+  if (!(d->h > 0) || !std::isfinite(d->h)) return bad("h must be positive and finite");
+  if (!(d->dt > 0) || !std::isfinite(d->dt)) return bad("dt must be positive and finite");
+  if (d->nt < 1) return bad("nt must be >= 1");
+  if (d->stride < 1 || d->stride > 8) return bad("stride must be in [1, 8]");
+  if (d->nr < 1 || d->nr > 1024) return bad("nr must be in [1, 1024]");
+  if (!d->rec_iz || !d->rec_ix) return bad("receiver arrays are NULL");
+  for (int r = 0; r < d->nr; ++r) {
+    if (d->rec_iz[r] < 0 || d->rec_iz[r] >= d->nz || d->rec_ix[r] < 0 || d->rec_ix[r] >= d->nx)
+      return bad("receiver outside the interior grid");
+  }
+  if (d->nf < 1 || d->nf > 64) return bad("nf must be in [1, 64]");
+  if (!d->freq_hz) return bad("frequency array is NULL");
+  for (int f = 0; f < d->nf; ++f)
+    if (!(d->freq_hz[f] >= 0) || !std::isfinite(d->freq_hz[f])) return bad("frequencies must be finite and >= 0");
+  if (d->precision != EHI_PREC_PLAIN_FP32 && d->precision != EHI_PREC_SPLIT_BF16)
+    return bad("unknown precision mode");
+  if (d->max_ns < 1 || d->max_ns > (1 << 20)) return bad("max_ns must be in [1, 2^20]");
+  if (d->nr_batch < 0) return bad("nr_batch must be >= 0");
+  long long Z = (long long)d->nz + 2LL * d->nb, X = (long long)d->nx + 2LL * d->nb;
+  if ((Z + 4) * (X + 4 + ehi::kRowAlign) > (1LL << 30)) return bad("grid too large");
+  return true;
+}
+
+ehi::Geometry make_geometry(const ehi_survey_desc* d) {
+  ehi::Geometry g{};
+  g.nz = d->nz;
+  g.nx = d->nx;
+  g.nb = d->nb;
+  g.Z = d->nz + 2 * d->nb;
+  g.X = d->nx + 2 * d->nb;
+  g.Zp = g.Z + 2 * ehi::kGhost;
+  g.Xp = (int)ehi::align_up((size_t)g.X + 2 * ehi::kGhost, ehi::kRowAlign);
+  g.stride = d->stride;
+  g.nzs = ehi::cdiv(d->nz, d->stride);
+  g.nxs = ehi::cdiv(d->nx, d->stride);
+  g.nsub = g.nzs * g.nxs;
+  g.nt = d->nt;
+  g.nr = d->nr;
+  g.nf = d->nf;
+  g.nrb = d->nr_batch > 0 ? std::min(d->nr_batch, d->nr) : d->nr;
+  g.max_ns = d->max_ns;
+  g.h = d->h;
+  g.dt = d->dt;
+  int ntile = ehi::cdiv(g.nr, ehi::kHerkTile);
+  int pairs = ntile * (ntile + 1) / 2;
+  int want = ehi::cdiv(2048, pairs * g.nf);
+  int kmax = std::max(1, g.nsub / 1024);
+  g.herk_split = std::max(1, std::min(want, std::min(ehi::kHerkSplitMax, kmax)));
+  return g;
+}
+
+ehi::Layout make_layout(const ehi::Geometry& g) {
+  ehi::Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = ehi::align_up(off + bytes, ehi::kAlign);
+    return o;
+  };
+  const size_t nn = (size_t)g.nr * g.nr;
+  L.freq = take(sizeof(double) * g.nf);
+  L.rec = take(sizeof(int32_t) * 2 * g.nr);
+  L.ca = take(sizeof(float) * g.plane());
+  L.ba = take(sizeof(float) * g.plane());
+  L.vmax = take(sizeof(uint32_t) * 4);
+  L.tw = take(sizeof(float2) * (size_t)g.nt * g.nf);
+  L.u0 = take(sizeof(float) * g.plane() * g.nrb);
+  L.u1 = take(sizeof(float) * g.plane() * g.nrb);
+  L.w = take(sizeof(float) * g.plane() * g.nrb);
+  L.stage = take(sizeof(float) * (size_t)g.nrb * ehi::kChunk * g.nsub);
+  L.ghat = take(sizeof(float2) * (size_t)g.nf * g.nr * g.nsub);
+  L.hpart = take(sizeof(float2) * (size_t)g.herk_split * g.nf * nn);
+  L.hhat = take(sizeof(double2) * g.nf * nn);
+  L.qhat = take(sizeof(double2) * g.nf * nn);
+  L.lfac = take(sizeof(double2) * g.nf * nn);
+  L.lfac32 = take(sizeof(float2) * g.nf * nn);
+  L.x64 = take(sizeof(double2) * (size_t)g.nf * g.max_ns * g.nr);
+  L.r32 = take(sizeof(float2) * (size_t)g.nf * g.max_ns * g.nr);
+  L.status = take(sizeof(int32_t) * (g.nf + 4));
+  L.eig = take(sizeof(double) * g.nf);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+namespace ehi {
+
+hipError_t Profiler::begin(int kind, hipStream_t st) {
+  if (!on) return hipSuccess;
+  if (open_kind == kind && open_stream == st) return hipSuccess;
+  hipError_t e = end();
+  if (e != hipSuccess) return e;
+  if ((e = hipEventCreate(&open_start)) != hipSuccess) return e;
+  if ((e = hipEventRecord(open_start, st)) != hipSuccess) return e;
+  open_kind = kind;
+  open_stream = st;
+  open_launches = 0;
+  return hipSuccess;
+}
+
+hipError_t Profiler::end() {
+  if (open_kind < 0) return hipSuccess;
+  hipEvent_t stop;
+  hipError_t e = hipEventCreate(&stop);
+  if (e == hipSuccess) e = hipEventRecord(stop, open_stream);
+  if (e == hipSuccess) recs.push_back(ProfRecord{open_kind, open_launches, open_start, stop});
+  open_kind = -1;
+  open_launches = 0;
+  open_start = nullptr;
+  return e;
+}
+
+}  // namespace ehi
+
+#define PROF(kind, st) EHI_TRY(s->prof.begin((kind), (st)), "profiler event")
+#define PROF_N(n) s->prof.count(n)
+#define PROF_END() EHI_TRY(s->prof.end(), "profiler event")
+
+extern "C" {
+
+const char* ehi_last_error(void) { return g_err.c_str(); }
+
+const char* ehi_version(void) { return "ehi 0.1 gfx950"; }
+
+size_t ehi_workspace_bytes(const ehi_survey_desc* desc) {
+  std::string why;
+  if (!validate(desc, &why)) {
+    g_err = why;
+    return 0;
+  }
+  return make_layout(make_geometry(desc)).total;
+}
+
+ehi_status ehi_create(const ehi_survey_desc* desc, void* workspace_dev, size_t ws_bytes,
+                      void* stream, ehi_survey** out) {
+  g_err.clear();
+  if (!out) return fail(EHI_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  if (!validate(desc, &why)) return fail(EHI_EINVAL, why);
+  if (!workspace_dev) return fail(EHI_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace_dev) % ehi::kAlign != 0)
+    return fail(EHI_EINVAL, "workspace must be 256-byte aligned");
+  ehi::Geometry g = make_geometry(desc);
+  ehi::Layout L = make_layout(g);
+  if (ws_bytes < L.total)
+    return fail(EHI_ENOMEM, "workspace has " + std::to_string(ws_bytes) + " bytes, needs " +
+                                std::to_string(L.total));
+  ehi_survey* s = new (std::nothrow) ehi_survey();
+  if (!s) return fail(EHI_ENOMEM, "host allocation failed");
+  s->g = g;
+  s->L = L;
+  s->precision = desc->precision;
+  s->rec_iz.assign(desc->rec_iz, desc->rec_iz + desc->nr);
+  s->rec_ix.assign(desc->rec_ix, desc->rec_ix + desc->nr);
+  s->freq.assign(desc->freq_hz, desc->freq_hz + desc->nf);
+  s->ws = static_cast<char*>(workspace_dev);
+  s->ws_bytes = ws_bytes;
+  s->stream = static_cast<hipStream_t>(stream);
+  s->state = ehi::State::Created;
+  s->mu = 0.0;
+  hipError_t e = hipGetDevice(&s->device);
+  if (e != hipSuccess) {
+    delete s;
+    return hip_fail(e, "hipGetDevice");
+  }
+  std::vector<int32_t> rec(2 * g.nr);
+  std::copy(s->rec_iz.begin(), s->rec_iz.end(), rec.begin());
+  std::copy(s->rec_ix.begin(), s->rec_ix.end(), rec.begin() + g.nr);
+  e = hipMemcpyAsync(s->ptr<double>(L.freq), s->freq.data(), sizeof(double) * g.nf,
+                     hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->ptr<int32_t>(L.rec), rec.data(), sizeof(int32_t) * 2 * g.nr,
+                       hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = ehi::launch_twiddles(g, s->ptr<double>(L.freq), s->ptr<float2>(L.tw), s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) {
+    delete s;
+    return hip_fail(e, "ehi_create set-up");
+  }
+  *out = s;
+  return EHI_OK;
+}
+
+ehi_status ehi_destroy(ehi_survey* s) {
+  if (!s) return EHI_OK;
+  s->prof.end();
+  for (auto& r : s->prof.recs) {
+    hipEventDestroy(r.start);
+    hipEventDestroy(r.stop);
+  }
+  delete s;
+  return EHI_OK;
+}
+
+ehi_status ehi_profile_enable(ehi_survey* s, int enable) {
+  g_err.clear();
+  if (!s) return fail(EHI_EINVAL, "survey is NULL");
+  if (!enable) PROF_END();
+  s->prof.on = enable != 0;
+  return EHI_OK;
+}
+
+ehi_status ehi_profile_read(ehi_survey* s, double* ms, int64_t* launches) {
+  g_err.clear();
+  if (!s || !ms || !launches) return fail(EHI_EINVAL, "NULL argument");
+  PROF_END();
+  for (int k = 0; k < EHI_PROF_KINDS; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  hipError_t first = hipSuccess;
+  for (auto& r : s->prof.recs) {
+    hipError_t e = hipEventSynchronize(r.stop);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, r.start, r.stop);
+    if (e != hipSuccess && first == hipSuccess) first = e;
+    if (r.kind >= 0 && r.kind < EHI_PROF_KINDS) {
+      ms[r.kind] += t;
+      launches[r.kind] += r.launches;
+    }
+    hipEventDestroy(r.start);
+    hipEventDestroy(r.stop);
+  }
+  s->prof.recs.clear();
+  if (first != hipSuccess) return hip_fail(first, "profile read");
+  return EHI_OK;
+}
+
+ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev) {
+  g_err.clear();
+  if (!s) return fail(EHI_EINVAL, "survey is NULL");
+  if (!vel_dev) return fail(EHI_EINVAL, "velocity is NULL");
+  const ehi::Geometry& g = s->g;
+  const ehi::Layout& L = s->L;
+  hipStream_t st = s->stream;
+  uint32_t* vmax = s->ptr<uint32_t>(L.vmax);
+  float* ca = s->ptr<float>(L.ca);
+  float* ba = s->ptr<float>(L.ba);
+  PROF(EHI_PROF_SETUP, st);
+  EHI_TRY(ehi::launch_vmax(vel_dev, g.nz * g.nx, vmax, st), "vmax");
+  EHI_TRY(ehi::launch_coefficients(g, vel_dev, vmax, ca, ba, st), "coefficients");
+  PROF_N(3);
+  const float2* tw = s->ptr<float2>(L.tw);
+  float2* ghat = s->ptr<float2>(L.ghat);
+  float* stage = s->ptr<float>(L.stage);
+  for (int r0 = 0; r0 < g.nr; r0 += g.nrb) {
+    const int nb_now = std::min(g.nrb, g.nr - r0);
+    float* ub[2] = {s->ptr<float>(L.u0), s->ptr<float>(L.u1)};
+    float* w = s->ptr<float>(L.w);
+    PROF(EHI_PROF_SETUP, st);
+    EHI_TRY(ehi::launch_wave_init(g, vel_dev, s->ptr<int32_t>(L.rec), r0, nb_now, ub[0], ub[1], w,
+                                  stage, st),
+            "wave init");
+    PROF_N(5);
+    int cur = 0;
+    for (int n = 1; n <= g.nt; ++n) {  // sample n is in ub[cur] and staging slot (n-1) % kChunk
+      const int slot = (n - 1) % ehi::kChunk;
+      if (slot == ehi::kChunk - 1 || n == g.nt) {
+        const int n0 = n - slot;
+        PROF(EHI_PROF_DFT, st);
+        EHI_TRY(ehi::launch_dft_chunk(g, stage, tw, n0, slot + 1, n0 == 1, r0, nb_now, ghat, st),
+                "dft chunk");
+        PROF_N(1);
+      }
+      if (n < g.nt) {
+        PROF(EHI_PROF_STEP, st);
+        EHI_TRY(ehi::launch_step(g, ca, ba, ub[cur], ub[1 - cur], w, stage, n % ehi::kChunk,
+                                 nb_now, st),
+                "time step");
+        PROF_N(1);
+        cur = 1 - cur;
+      }
+    }
+  }
+  PROF_END();
+  s->state = ehi::State::Green;
+  return EHI_OK;
+}
+
+ehi_status ehi_build_hessian(ehi_survey* s) {
+  g_err.clear();
+  if (!s) return fail(EHI_EINVAL, "survey is NULL");
+  if (s->state < ehi::State::Green) return fail(EHI_ESTATE, "build_hessian before build_green");
+  const ehi::Geometry& g = s->g;
+  const ehi::Layout& L = s->L;
+  float2* hpart = s->ptr<float2>(L.hpart);
+  PROF(EHI_PROF_HERK, s->stream);
+  EHI_TRY(ehi::launch_herk_fp32(g, s->ptr<float2>(L.ghat), hpart, s->stream), "herk");
+  EHI_TRY(ehi::launch_herk_reduce(g, hpart, s->ptr<double2>(L.hhat), s->stream), "herk reduce");
+  PROF_N(2);
+  PROF_END();
+  s->state = ehi::State::Hessian;
+  return EHI_OK;
+}
+
+ehi_status ehi_factor(ehi_survey* s, double mu, int32_t* bad_freq) {
+  g_err.clear();
+  if (bad_freq) *bad_freq = -1;
+  if (!s) return fail(EHI_EINVAL, "survey is NULL");
+  if (s->state < ehi::State::Hessian) return fail(EHI_ESTATE, "factor before build_hessian");
+  if (!(mu > 0) || !std::isfinite(mu)) return fail(EHI_EINVAL, "mu must be positive and finite");
+  const ehi::Geometry& g = s->g;
+  const ehi::Layout& L = s->L;
+  hipStream_t st = s->stream;
+  double2* qhat = s->ptr<double2>(L.qhat);
+  int32_t* status = s->ptr<int32_t>(L.status);
+  PROF(EHI_PROF_FACTOR, st);
+  EHI_TRY(ehi::launch_penalty(g, s->ptr<double2>(L.hhat), mu, qhat, st), "penalty");
+  PROF_N(2);
+  if (s->precision == EHI_PREC_SPLIT_BF16) {
+    EHI_TRY(ehi::launch_potrf_f64(g, qhat, s->ptr<double2>(L.lfac), s->ptr<float2>(L.lfac32),
+                                  status, st),
+            "potrf f64");
+  } else {
+    EHI_TRY(ehi::launch_potrf_f32(g, qhat, s->ptr<float2>(L.lfac32), status, st), "potrf f32");
+  }
+  PROF_END();
+  std::vector<int32_t> host(g.nf);
+  EHI_TRY(hipMemcpyAsync(host.data(), status, sizeof(int32_t) * g.nf, hipMemcpyDeviceToHost, st),
+          "status readback");
+  EHI_TRY(hipStreamSynchronize(st), "factor sync");
+  s->state = ehi::State::Hessian;
+  for (int f = 0; f < g.nf; ++f) {
+    if (host[f] != 0) {
+      if (bad_freq) *bad_freq = f;
+      return fail(EHI_ENOTPD, "Qhat not positive definite at frequency index " + std::to_string(f));
+    }
+  }
+  s->mu = mu;
+  s->state = ehi::State::Factored;
+  return EHI_OK;
+}
+
+ehi_status ehi_apply_multipliers(ehi_survey* s, const void* resid_dev, void* mult_dev, int32_t ns,
+                                 void* stream) {
+  g_err.clear();
+  if (!s) return fail(EHI_EINVAL, "survey is NULL");
+  if (s->state < ehi::State::Factored) return fail(EHI_ESTATE, "apply before a successful factor");
+  if (ns < 0) return fail(EHI_EINVAL, "ns must be >= 0");
+  if (ns == 0) return EHI_OK;
+  if (!resid_dev || !mult_dev) return fail(EHI_EINVAL, "residual or output is NULL");
+  if (resid_dev == mult_dev) return fail(EHI_EINVAL, "residual and output may not alias");
+  const ehi::Geometry& g = s->g;
+  const ehi::Layout& L = s->L;
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : s->stream;
+  const float2* R = static_cast<const float2*>(resid_dev);
+  float2* X = static_cast<float2*>(mult_dev);
+  const float2* l32 = s->ptr<float2>(L.lfac32);
+  double2* x64 = s->ptr<double2>(L.x64);
+  float2* r32 = s->ptr<float2>(L.r32);
+  PROF(EHI_PROF_SOLVE, st);
+  for (int s0 = 0; s0 < ns; s0 += g.max_ns) {
+    const int cnt = std::min(g.max_ns, ns - s0);
+    if (s->precision == EHI_PREC_PLAIN_FP32) {
+      EHI_TRY(ehi::launch_trsm(g, l32, R, ns, s0, X, ns, s0, cnt, ehi::kTrsmWorkOnly, x64, st), "trsm");
+      PROF_N(1);
+      continue;
+    }
+    EHI_TRY(ehi::launch_trsm(g, l32, R, ns, s0, r32, g.max_ns, 0, cnt, ehi::kTrsmStoreX64, x64, st),
+            "trsm");
+    for (int it = 0; it < 2; ++it) {
+      EHI_TRY(ehi::launch_residual(g, s->ptr<double2>(L.qhat), R, ns, s0, cnt, x64, r32, st),
+              "residual");
+      EHI_TRY(ehi::launch_trsm(g, l32, r32, g.max_ns, 0, r32, g.max_ns, 0, cnt, ehi::kTrsmAddX64,
+                               x64, st),
+              "trsm refine");
+    }
+    EHI_TRY(ehi::launch_x_out(g, x64, cnt, s0, X, ns, st), "x out");
+    PROF_N(6);
+  }
+  PROF_END();
+  return EHI_OK;
+}
+
+ehi_status ehi_lambda_max(ehi_survey* s, double* out) {
+  g_err.clear();
+  if (!s || !out) return fail(EHI_EINVAL, "NULL argument");
+  if (s->state < ehi::State::Hessian) return fail(EHI_ESTATE, "lambda_max before build_hessian");
+  const ehi::Geometry& g = s->g;
+  double* eig = s->ptr<double>(s->L.eig);
+  EHI_TRY(ehi::launch_power_iter(g, s->ptr<double2>(s->L.hhat), eig, 400, s->stream), "power iteration");
+  std::vector<double> host(g.nf);
+  EHI_TRY(hipMemcpyAsync(host.data(), eig, sizeof(double) * g.nf, hipMemcpyDeviceToHost, s->stream),
+          "eig readback");
+  EHI_TRY(hipStreamSynchronize(s->stream), "lambda sync");
+  *out = *std::max_element(host.begin(), host.end());
+  return EHI_OK;
+}
+
+ehi_status ehi_copy_green_dft(ehi_survey* s, void* out_dev) {
+  g_err.clear();
+  if (!s || !out_dev) return fail(EHI_EINVAL, "NULL argument");
+  if (s->state < ehi::State::Green) return fail(EHI_ESTATE, "no Green-function spectra yet");
+  size_t bytes = sizeof(float2) * (size_t)s->g.nf * s->g.nr * s->g.nsub;
+  EHI_TRY(hipMemcpyAsync(out_dev, s->ws + s->L.ghat, bytes, hipMemcpyDeviceToDevice, s->stream),
+          "copy green");
+  return EHI_OK;
+}
+
+ehi_status ehi_load_green_dft(ehi_survey* s, const void* in_dev) {
+  g_err.clear();
+  if (!s || !in_dev) return fail(EHI_EINVAL, "NULL argument");
+  size_t bytes = sizeof(float2) * (size_t)s->g.nf * s->g.nr * s->g.nsub;
+  EHI_TRY(hipMemcpyAsync(s->ws + s->L.ghat, in_dev, bytes, hipMemcpyDeviceToDevice, s->stream),
+          "load green");
+  s->state = ehi::State::Green;
+  return EHI_OK;
+}
+
+ehi_status ehi_copy_hessian(ehi_survey* s, void* out_dev) {
+  g_err.clear();
+  if (!s || !out_dev) return fail(EHI_EINVAL, "NULL argument");
+  if (s->state < ehi::State::Hessian) return fail(EHI_ESTATE, "no Hessian yet");
+  size_t bytes = sizeof(double2) * (size_t)s->g.nf * s->g.nr * s->g.nr;
+  EHI_TRY(hipMemcpyAsync(out_dev, s->ws + s->L.hhat, bytes, hipMemcpyDeviceToDevice, s->stream),
+          "copy hessian");
+  return EHI_OK;
+}
+
+ehi_status ehi_load_hessian(ehi_survey* s, const void* in_dev) {
+  g_err.clear();
+  if (!s || !in_dev) return fail(EHI_EINVAL, "NULL argument");
+  size_t bytes = sizeof(double2) * (size_t)s->g.nf * s->g.nr * s->g.nr;
+  EHI_TRY(hipMemcpyAsync(s->ws + s->L.hhat, in_dev, bytes, hipMemcpyDeviceToDevice, s->stream),
+          "load hessian");
+  s->state = ehi::State::Hessian;
+  return EHI_OK;
+}
+
+ehi_status ehi_copy_factor(ehi_survey* s, void* out_dev) {
+  g_err.clear();
+  if (!s || !out_dev) return fail(EHI_EINVAL, "NULL argument");
+  if (s->state < ehi::State::Factored) return fail(EHI_ESTATE, "no factor yet");
+  const size_t nn = (size_t)s->g.nf * s->g.nr * s->g.nr;
+  if (s->precision == EHI_PREC_SPLIT_BF16) {
+    EHI_TRY(hipMemcpyAsync(out_dev, s->ws + s->L.lfac, sizeof(double2) * nn, hipMemcpyDeviceToDevice,
+                           s->stream),
+            "copy factor");
+  } else {
+    EHI_TRY(ehi::launch_c128_from_c64(s->ptr<float2>(s->L.lfac32), static_cast<double2*>(out_dev), nn,
+                                      s->stream),
+            "copy factor");
+  }
+  return EHI_OK;
+}
+
+}  // extern "C"

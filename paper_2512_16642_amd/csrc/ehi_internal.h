@@ -1,0 +1,147 @@
+// Internal declarations of libehi: workspace layout, survey state, launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ehi.h"
+
+namespace ehi {
+
+// ---- fixed design constants -------------------------------------------------
+constexpr int kGhost = 2;        // zero ring around the padded grid (stencil radius)
+constexpr int kRowAlign = 64;    // padded row pitch is a multiple of 64 floats (256 B)
+constexpr int kChunk = 64;       // time samples per DFT chunk (staging depth)
+constexpr int kHerkTile = 32;    // Hessian output tile (rows = cols)
+constexpr int kHerkSplitMax = 64;  // max split-K partitions of the grid sum
+constexpr size_t kAlign = 256;
+
+__host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+__host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Geometry derived from the descriptor.
+struct Geometry {
+  int nz, nx, nb;
+  int Z, X;        // padded grid (interior + absorbing layer)
+  int Zp, Xp;      // allocated plane incl. ghost ring and row padding
+  int stride, nzs, nxs, nsub;
+  int nt, nr, nf, nrb, max_ns;
+  int herk_split;  // split-K partitions
+  double h, dt;
+  __host__ __device__ size_t plane() const { return (size_t)Zp * Xp; }
+};
+
+// Byte offsets of every buffer inside the caller's workspace.
+struct Layout {
+  size_t freq;      // double [nf]
+  size_t rec;       // int32 [2][nr]  (iz then ix, interior indices)
+  size_t ca;        // float [Zp][Xp]  kappa / (12 h^2 a)
+  size_t ba;        // float [Zp][Xp]  b / a
+  size_t vmax;      // uint32 [4]  max velocity bits
+  size_t tw;        // float2 [nt][nf] exp(-i w n dt), n = 1..nt
+  size_t u0, u1, w; // float [nrb][Zp][Xp]
+  size_t stage;     // float [nrb][kChunk][nsub]
+  size_t ghat;      // float2 [nf][nr][nsub]
+  size_t hpart;     // float2 [split][nf][nr][nr]
+  size_t hhat;      // double2 [nf][nr][nr]
+  size_t qhat;      // double2 [nf][nr][nr]   Hhat + mu I (Hermitian, full)
+  size_t lfac;      // double2 [nf][nr][nr]   lower Cholesky factor (FP64 mode)
+  size_t lfac32;    // float2 [nf][nr][nr]    complex64 copy (or the FP32 factor)
+  size_t x64;       // double2 [nf][max_ns][nr] refinement accumulator
+  size_t r32;       // float2 [nf][max_ns][nr]  refinement residual
+  size_t status;    // int32 [nf + 4]
+  size_t eig;       // double [nf]
+  size_t total;
+};
+
+enum class State : int { Created = 0, Green = 1, Hessian = 2, Factored = 3 };
+
+// Event pairs bracketing runs of launches of one kind (EHI_PROF_*).
+struct ProfRecord {
+  int kind;
+  int launches;
+  hipEvent_t start, stop;
+};
+
+struct Profiler {
+  bool on = false;
+  std::vector<ProfRecord> recs;
+  int open_kind = -1;
+  int open_launches = 0;
+  hipEvent_t open_start = nullptr;
+  hipStream_t open_stream = nullptr;
+  // start a run of `kind` on stream st (closes a run of another kind first)
+  hipError_t begin(int kind, hipStream_t st);
+  void count(int n = 1) { open_launches += n; }
+  hipError_t end();
+};
+
+}  // namespace ehi
+
+struct ehi_survey {
+  ehi::Geometry g;
+  ehi::Layout L;
+  int precision;
+  std::vector<int32_t> rec_iz, rec_ix;
+  std::vector<double> freq;
+  char* ws;
+  size_t ws_bytes;
+  hipStream_t stream;
+  int device;
+  ehi::State state;
+  double mu;
+  ehi::Profiler prof;
+  template <class T>
+  T* ptr(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace ehi {
+
+// ---- launchers (each returns hipGetLastError() of its launch) ----------------
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t st);
+hipError_t launch_vmax(const float* vel, int n, uint32_t* out_bits, hipStream_t st);
+hipError_t launch_coefficients(const Geometry& g, const float* vel, const uint32_t* vmax_bits,
+                               float* ca, float* ba, hipStream_t st);
+hipError_t launch_twiddles(const Geometry& g, const double* freq, float2* tw, hipStream_t st);
+hipError_t launch_wave_init(const Geometry& g, const float* vel, const int32_t* rec, int r0,
+                            int nrb_now, float* u0, float* u1, float* w, float* stage,
+                            hipStream_t st);
+hipError_t launch_step(const Geometry& g, const float* ca, const float* ba, const float* ucur,
+                       float* unext, float* w, float* stage, int slot, int nrb_now,
+                       hipStream_t st);
+hipError_t launch_dft_chunk(const Geometry& g, const float* stage, const float2* tw, int n0,
+                            int cnt, bool first, int r0, int nrb_now, float2* ghat,
+                            hipStream_t st);
+hipError_t launch_herk_fp32(const Geometry& g, const float2* ghat, float2* hpart, hipStream_t st);
+hipError_t launch_herk_reduce(const Geometry& g, const float2* hpart, double2* hhat,
+                              hipStream_t st);
+hipError_t launch_penalty(const Geometry& g, const double2* hhat, double mu, double2* qhat,
+                          hipStream_t st);
+hipError_t launch_potrf_f64(const Geometry& g, const double2* qhat, double2* lfac,
+                            float2* lfac32, int32_t* status, hipStream_t st);
+hipError_t launch_potrf_f32(const Geometry& g, const double2* qhat, float2* lfac32,
+                            int32_t* status, hipStream_t st);
+hipError_t launch_trsm(const Geometry& g, const float2* l32, const float2* rhs, int rhs_ld,
+                       int rhs_off, float2* work, int work_ld, int work_off, int cnt, int mode,
+                       double2* x64, hipStream_t st);
+hipError_t launch_residual(const Geometry& g, const double2* qhat, const float2* resid,
+                           int resid_ns, int s0, int ns, const double2* x64, float2* r32,
+                           hipStream_t st);
+hipError_t launch_x_out(const Geometry& g, const double2* x64, int ns, int s0, float2* out,
+                        int out_ns, hipStream_t st);
+hipError_t launch_power_iter(const Geometry& g, const double2* hhat, double* eig, int iters,
+                             hipStream_t st);
+hipError_t launch_c128_from_c64(const float2* in, double2* out, size_t n, hipStream_t st);
+hipError_t launch_c64_from_c128(const double2* in, float2* out, size_t n, hipStream_t st);
+
+// trsm modes: the solution stays in the work vector (complex64); StoreX64 and
+// AddX64 also write / accumulate it into the FP64 refinement accumulator.
+constexpr int kTrsmWorkOnly = 0;
+constexpr int kTrsmStoreX64 = 1;
+constexpr int kTrsmAddX64 = 2;
+
+}  // namespace ehi

@@ -1,0 +1,279 @@
+"""Python binding of libehi (include/ehi.h): argument marshalling only.
+
+Every stage runs in the HIP library; this module checks tensor shapes, dtypes
+and devices, passes raw device pointers and the current HIP stream, and turns
+status codes into exceptions.  PyTorch provides device memory (the survey
+workspace is one uint8 tensor) and streams.
+
+If the shared library is missing the import of the library fails loudly; there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libehi.so")
+
+EHI_OK, EHI_EINVAL, EHI_ENOMEM, EHI_EHIP, EHI_ENOTPD, EHI_ESTATE = range(6)
+PREC_PLAIN_FP32 = 0
+PREC_SPLIT_BF16 = 1
+_PREC = {"plain_fp32": PREC_PLAIN_FP32, "split_bf16": PREC_SPLIT_BF16}
+
+# every symbol declared in include/ehi.h
+SYMBOLS = (
+    "ehi_workspace_bytes", "ehi_create", "ehi_build_green", "ehi_build_hessian", "ehi_factor",
+    "ehi_apply_multipliers", "ehi_lambda_max", "ehi_copy_green_dft", "ehi_load_green_dft",
+    "ehi_copy_hessian", "ehi_load_hessian", "ehi_copy_factor", "ehi_destroy", "ehi_last_error",
+    "ehi_version", "ehi_profile_enable", "ehi_profile_read",
+)
+PROF_KINDS = ("setup", "step", "dft", "herk", "factor", "solve")
+_PROF_N = 8
+
+
+class EhiError(RuntimeError):
+    def __init__(self, status: int, msg: str, bad_freq: int = -1):
+        super().__init__(f"ehi status {status}: {msg}")
+        self.status = status
+        self.bad_freq = bad_freq
+
+
+class SurveyDesc(ctypes.Structure):
+    _fields_ = [
+        ("nz", ctypes.c_int32), ("nx", ctypes.c_int32), ("nb", ctypes.c_int32),
+        ("h", ctypes.c_double), ("dt", ctypes.c_double),
+        ("nt", ctypes.c_int32), ("stride", ctypes.c_int32), ("nr", ctypes.c_int32),
+        ("rec_iz", ctypes.POINTER(ctypes.c_int32)), ("rec_ix", ctypes.POINTER(ctypes.c_int32)),
+        ("nf", ctypes.c_int32), ("freq_hz", ctypes.POINTER(ctypes.c_double)),
+        ("precision", ctypes.c_int32), ("max_ns", ctypes.c_int32), ("nr_batch", ctypes.c_int32),
+    ]
+
+
+_lib_handle = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libehi.so (once).  Raises if it has not been built."""
+    global _lib_handle
+    if _lib_handle is not None:
+        return _lib_handle
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int
+    L.ehi_workspace_bytes.argtypes = [ctypes.POINTER(SurveyDesc)]
+    L.ehi_workspace_bytes.restype = ctypes.c_size_t
+    L.ehi_create.argtypes = [ctypes.POINTER(SurveyDesc), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.ehi_create.restype = st
+    L.ehi_build_green.argtypes = [vp, vp]
+    L.ehi_build_green.restype = st
+    L.ehi_build_hessian.argtypes = [vp]
+    L.ehi_build_hessian.restype = st
+    L.ehi_factor.argtypes = [vp, ctypes.c_double, ctypes.POINTER(i32)]
+    L.ehi_factor.restype = st
+    L.ehi_apply_multipliers.argtypes = [vp, vp, vp, i32, vp]
+    L.ehi_apply_multipliers.restype = st
+    L.ehi_lambda_max.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.ehi_lambda_max.restype = st
+    for name in ("ehi_copy_green_dft", "ehi_load_green_dft", "ehi_copy_hessian", "ehi_load_hessian",
+                 "ehi_copy_factor"):
+        getattr(L, name).argtypes = [vp, vp]
+        getattr(L, name).restype = st
+    L.ehi_profile_enable.argtypes = [vp, ctypes.c_int]
+    L.ehi_profile_enable.restype = st
+    L.ehi_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    L.ehi_profile_read.restype = st
+    L.ehi_destroy.argtypes = [vp]
+    L.ehi_destroy.restype = st
+    L.ehi_last_error.argtypes = []
+    L.ehi_last_error.restype = ctypes.c_char_p
+    L.ehi_version.argtypes = []
+    L.ehi_version.restype = ctypes.c_char_p
+    _lib_handle = L
+    return L
+
+
+def _check(status: int, bad_freq: int = -1):
+    if status != EHI_OK:
+        raise EhiError(status, lib().ehi_last_error().decode(), bad_freq)
+
+
+def _stream_ptr(stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _require(t: torch.Tensor, dtype, shape, name: str, device: torch.device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision, max_ns,
+              nr_batch):
+    riz = np.ascontiguousarray(rec_iz, dtype=np.int32)
+    rix = np.ascontiguousarray(rec_ix, dtype=np.int32)
+    fr = np.ascontiguousarray(freqs_hz, dtype=np.float64)
+    if riz.shape != rix.shape or riz.ndim != 1:
+        raise ValueError("rec_iz and rec_ix must be 1-D arrays of equal length")
+    prec = _PREC[precision] if isinstance(precision, str) else int(precision)
+    d = SurveyDesc(nz=nz, nx=nx, nb=nb, h=h, dt=dt, nt=nt, stride=stride, nr=len(riz),
+                   rec_iz=riz.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                   rec_ix=rix.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                   nf=len(fr), freq_hz=fr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                   precision=prec, max_ns=max_ns, nr_batch=nr_batch)
+    return d, (riz, rix, fr)   # keep the arrays alive with the descriptor
+
+
+def workspace_bytes(**kw) -> int:
+    d, keep = make_desc(**kw)
+    n = lib().ehi_workspace_bytes(ctypes.byref(d))
+    if n == 0:
+        raise EhiError(EHI_EINVAL, lib().ehi_last_error().decode())
+    return int(n)
+
+
+class Survey:
+    """One survey handle over a torch-allocated workspace on one GPU."""
+
+    def __init__(self, *, nz: int, nx: int, nb: int, h: float, dt: float, nt: int, stride: int,
+                 rec_iz: Sequence[int], rec_ix: Sequence[int], freqs_hz: Sequence[float],
+                 precision="split_bf16", max_ns: int = 256, nr_batch: int = 0,
+                 device=None, stream: Optional[torch.cuda.Stream] = None):
+        self._h = None
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.nz, self.nx, self.nb, self.nt, self.stride = nz, nx, nb, nt, stride
+        self.nr, self.nf = len(rec_ix), len(freqs_hz)
+        self.nzs = (nz + stride - 1) // stride
+        self.nxs = (nx + stride - 1) // stride
+        self.precision = precision
+        self.max_ns = max_ns
+        d, keep = make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision,
+                            max_ns, nr_batch)
+        L = lib()
+        nbytes = L.ehi_workspace_bytes(ctypes.byref(d))
+        if nbytes == 0:
+            raise EhiError(EHI_EINVAL, L.ehi_last_error().decode())
+        self.workspace_bytes = int(nbytes)
+        with torch.cuda.device(self.device):
+            raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-raw.data_ptr()) % 256
+            self._ws = raw
+            self._ws_ptr = raw.data_ptr() + off
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            h_out = ctypes.c_void_p()
+            _check(L.ehi_create(ctypes.byref(d), ctypes.c_void_p(self._ws_ptr), ctypes.c_size_t(nbytes),
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h_out)))
+        self._h = h_out
+
+    # -- stages ---------------------------------------------------------------
+    def build_green(self, vel: torch.Tensor):
+        _require(vel, torch.float32, (self.nz, self.nx), "vel", self.device)
+        self._vel = vel  # keep alive while the stream may still read it
+        _check(lib().ehi_build_green(self._h, ctypes.c_void_p(vel.data_ptr())))
+
+    def build_hessian(self):
+        _check(lib().ehi_build_hessian(self._h))
+
+    def factor(self, mu: float):
+        bad = ctypes.c_int32(-1)
+        st = lib().ehi_factor(self._h, ctypes.c_double(mu), ctypes.byref(bad))
+        _check(st, bad.value)
+
+    def apply_multipliers(self, resid: torch.Tensor, out: Optional[torch.Tensor] = None,
+                          stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+        if resid.dim() != 3:
+            raise ValueError("resid must be [nf][ns][nr]")
+        ns = resid.shape[1]
+        _require(resid, torch.complex64, (self.nf, ns, self.nr), "resid", self.device)
+        if out is None:
+            out = torch.empty_like(resid)
+        _require(out, torch.complex64, (self.nf, ns, self.nr), "out", self.device)
+        sp = 0 if stream is None else stream.cuda_stream
+        _check(lib().ehi_apply_multipliers(self._h, ctypes.c_void_p(resid.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr()), ns, ctypes.c_void_p(sp)))
+        return out
+
+    def lambda_max(self) -> float:
+        v = ctypes.c_double(0.0)
+        _check(lib().ehi_lambda_max(self._h, ctypes.byref(v)))
+        return float(v.value)
+
+    # -- stage inputs/outputs ------------------------------------------------------
+    def copy_green_dft(self) -> torch.Tensor:
+        out = torch.empty((self.nf, self.nr, self.nzs, self.nxs), dtype=torch.complex64, device=self.device)
+        _check(lib().ehi_copy_green_dft(self._h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def load_green_dft(self, g: torch.Tensor):
+        _require(g, torch.complex64, (self.nf, self.nr, self.nzs, self.nxs), "ghat", self.device)
+        self._ghat_in = g
+        _check(lib().ehi_load_green_dft(self._h, ctypes.c_void_p(g.data_ptr())))
+
+    def copy_hessian(self) -> torch.Tensor:
+        out = torch.empty((self.nf, self.nr, self.nr), dtype=torch.complex128, device=self.device)
+        _check(lib().ehi_copy_hessian(self._h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def load_hessian(self, H: torch.Tensor):
+        _require(H, torch.complex128, (self.nf, self.nr, self.nr), "hessian", self.device)
+        self._h_in = H
+        _check(lib().ehi_load_hessian(self._h, ctypes.c_void_p(H.data_ptr())))
+
+    def copy_factor(self) -> torch.Tensor:
+        out = torch.empty((self.nf, self.nr, self.nr), dtype=torch.complex128, device=self.device)
+        _check(lib().ehi_copy_factor(self._h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    # -- kernel timing -------------------------------------------------------------
+    def profile(self, enable: bool = True):
+        _check(lib().ehi_profile_enable(self._h, 1 if enable else 0))
+
+    def read_profile(self) -> dict:
+        """{kind: (milliseconds, launches)} of the runs recorded since the last read."""
+        ms = (ctypes.c_double * _PROF_N)()
+        nl = (ctypes.c_int64 * _PROF_N)()
+        _check(lib().ehi_profile_read(self._h, ms, nl))
+        return {k: (float(ms[i]), int(nl[i])) for i, k in enumerate(PROF_KINDS)}
+
+    def close(self):
+        if self._h is not None:
+            torch.cuda.synchronize(self.device)
+            lib().ehi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            if self._h is not None:
+                lib().ehi_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def survey_from(spec, precision="split_bf16", max_ns=None, nr_batch=0, **kw) -> Survey:
+    """Build a handle from any object with the survey attributes (nz, nx, nb, h,
+    dt, nt, stride, rec_iz, rec_ix, freqs_hz, ns)."""
+    return Survey(nz=spec.nz, nx=spec.nx, nb=spec.nb, h=spec.h, dt=spec.dt, nt=spec.nt,
+                  stride=spec.stride, rec_iz=spec.rec_iz, rec_ix=spec.rec_ix,
+                  freqs_hz=spec.freqs_hz, precision=precision,
+                  max_ns=max_ns if max_ns is not None else max(1, spec.ns),
+                  nr_batch=nr_batch, **kw)

@@ -1,0 +1,86 @@
+"""The C-ABI library loads, exports every declared symbol, and validates
+descriptors on the host (no GPU needed: no compute is called)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ehi.h")
+
+
+def _declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(ehi_[a-z_0-9]+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def ehi():
+    from paper_2512_16642_amd import ehi as mod
+    return mod
+
+
+def test_header_symbols_exported(ehi):
+    L = ehi.lib()
+    decl = _declared_symbols()
+    assert len(decl) >= 14, decl
+    for name in decl:
+        assert hasattr(L, name), name
+    assert set(decl) == set(ehi.SYMBOLS)
+
+
+def _desc_kw(**over):
+    kw = dict(nz=20, nx=30, nb=5, h=10.0, dt=1e-3, nt=50, stride=1, rec_iz=[1, 2], rec_ix=[3, 4],
+              freqs_hz=[5.0, 7.0], precision="split_bf16", max_ns=4, nr_batch=0)
+    kw.update(over)
+    return kw
+
+
+def test_workspace_bytes_valid(ehi):
+    n = ehi.workspace_bytes(**_desc_kw())
+    # at least the three wavefield planes and the Green-function spectra
+    Zp, Xp = 20 + 10 + 4, 64
+    assert n >= 3 * 2 * Zp * Xp * 4 + 2 * 2 * 20 * 30 * 8
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nz=2), dict(nb=-1), dict(h=0.0), dict(dt=-1.0), dict(nt=0), dict(stride=0), dict(stride=9),
+    dict(rec_iz=[1, 20]), dict(rec_ix=[-1, 4]), dict(freqs_hz=[]), dict(freqs_hz=[float("nan")]),
+    dict(precision=7), dict(max_ns=0), dict(nr_batch=-3),
+])
+def test_workspace_bytes_rejects(ehi, bad):
+    with pytest.raises(ehi.EhiError) as ei:
+        ehi.workspace_bytes(**_desc_kw(**bad))
+    assert ei.value.status == ehi.EHI_EINVAL
+    assert ehi.lib().ehi_last_error().decode()
+
+
+def test_workspace_grows_with_sizes(ehi):
+    a = ehi.workspace_bytes(**_desc_kw())
+    b = ehi.workspace_bytes(**_desc_kw(nt=500))
+    c = ehi.workspace_bytes(**_desc_kw(max_ns=400))
+    assert b > a and c > a
+
+
+def test_create_rejects_null_workspace(ehi):
+    d, keep = ehi.make_desc(**_desc_kw())
+    out = ctypes.c_void_p()
+    st = ehi.lib().ehi_create(ctypes.byref(d), None, 0, None, ctypes.byref(out))
+    assert st == ehi.EHI_EINVAL and not out.value
+
+
+def test_create_rejects_small_workspace(ehi):
+    d, keep = ehi.make_desc(**_desc_kw())
+    out = ctypes.c_void_p()
+    # a bogus aligned address: the size check fails before any device access
+    st = ehi.lib().ehi_create(ctypes.byref(d), ctypes.c_void_p(1 << 20), 16, None, ctypes.byref(out))
+    assert st == ehi.EHI_ENOMEM and not out.value
+
+
+def test_null_handle_calls_fail_cleanly(ehi):
+    L = ehi.lib()
+    assert L.ehi_build_hessian(None) == ehi.EHI_EINVAL
+    assert L.ehi_factor(None, ctypes.c_double(1.0), None) == ehi.EHI_EINVAL
+    assert L.ehi_destroy(None) == ehi.EHI_OK

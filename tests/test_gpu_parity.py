@@ -1,0 +1,223 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances, derived from the arithmetic of each stage:
+  * Green-function spectra: FP32 increment-form stepping (~1e-6 relative,
+    measured on FP32 emulations of the recurrence) plus FP32 chunked DFT sums:
+    5e-6 per frequency (relative Frobenius).
+  * Hessian from given spectra: FP32 products, two-level FP32 accumulation and
+    an FP64 reduction of the grid partitions: 2e-6.
+  * Factor + solve from a given Hessian, split-BF16 mode: FP64 Cholesky, FP32
+    solves refined twice in FP64, output rounded to complex64: 2e-6.
+  * End to end (split-BF16 mode): the multiplier target 1e-5.
+Inputs are the seeded synthetic surveys of ``synth``; the oracle sees the same
+float32 velocity and complex64 residuals, upcast.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import fd, hessian, solve
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def per_freq_rel(a, b):
+    return [rel(a[f], b[f]) for f in range(a.shape[0])]
+
+
+@pytest.fixture(scope="module")
+def ehi():
+    from paper_2512_16642_amd import ehi as mod
+    mod.lib()
+    return mod
+
+
+@pytest.fixture(scope="module")
+def tiny_ref():
+    s = synth.tiny()
+    v = s.velocity()
+    G = fd.green_dft(s, v)                       # [nf][nr][nsub] c128
+    H = hessian.hessian_r1(G)
+    mu = 1e-3 * solve.lambda_max(H)
+    R = s.residuals()
+    X = solve.multipliers(H, mu, R.astype(np.complex128))
+    return dict(s=s, v=v, G=G, H=H, mu=mu, R=R, X=X)
+
+
+def _gpu_green(ehi, s, v, precision="split_bf16", nr_batch=0):
+    sv = ehi.survey_from(s, precision=precision, nr_batch=nr_batch)
+    sv.build_green(torch.from_numpy(v).to(DEV))
+    G = sv.copy_green_dft().reshape(s.nf, s.nr, -1)
+    torch.cuda.synchronize()
+    return sv, G.cpu().numpy()
+
+
+def test_green_dft_tiny(ehi, tiny_ref):
+    s = tiny_ref["s"]
+    sv, G = _gpu_green(ehi, s, tiny_ref["v"])
+    errs = per_freq_rel(G, tiny_ref["G"])
+    print("ghat rel err per freq", errs)
+    assert max(errs) < 5e-6
+
+
+def test_green_dft_ragged_stride2(ehi):
+    s = synth.ragged()
+    v = s.velocity()
+    ref = fd.green_dft(s, v)
+    sv, G = _gpu_green(ehi, s, v)
+    errs = per_freq_rel(G, ref)
+    print("ragged ghat rel err", errs)
+    assert max(errs) < 5e-6
+
+
+def test_green_receiver_batches_identical(ehi):
+    s = synth.ragged()
+    v = s.velocity()
+    _, G_all = _gpu_green(ehi, s, v)
+    _, G_b2 = _gpu_green(ehi, s, v, nr_batch=2)
+    np.testing.assert_array_equal(G_all, G_b2)
+
+
+def test_green_single_step_and_chunk_edges(ehi):
+    # nt = 1 (only the impulse sample), nt = 64 and 65 (DFT chunk edge)
+    base = synth.ragged(nt=1)
+    for nt in (1, 64, 65):
+        s = base.with_(nt=nt)
+        v = s.velocity()
+        ref = fd.green_dft(s, v)
+        _, G = _gpu_green(ehi, s, v)
+        assert max(per_freq_rel(G, ref)) < 5e-6, nt
+
+
+def test_hessian_from_given_spectra(ehi, tiny_ref):
+    s = tiny_ref["s"]
+    G64 = tiny_ref["G"].astype(np.complex64)
+    ref = hessian.hessian_r1(G64.astype(np.complex128))
+    for prec in ("split_bf16", "plain_fp32"):
+        sv = ehi.survey_from(s, precision=prec)
+        sv.load_green_dft(torch.from_numpy(G64.reshape(s.nf, s.nr, s.nzs, s.nxs)).to(DEV))
+        sv.build_hessian()
+        H = sv.copy_hessian().cpu().numpy()
+        errs = per_freq_rel(H, ref)
+        print(prec, "hessian rel err", errs)
+        assert max(errs) < 2e-6
+        for f in range(s.nf):
+            np.testing.assert_array_equal(H[f], H[f].conj().T)
+            assert np.all(np.diag(H[f]).imag == 0) and np.all(np.diag(H[f]).real > 0)
+
+
+def test_factor_and_solve_from_given_hessian(ehi, tiny_ref):
+    s = tiny_ref["s"]
+    H = tiny_ref["H"]
+    mu = tiny_ref["mu"]
+    R = tiny_ref["R"]
+    Lref = solve.cholesky(solve.penalize(H, mu))
+    Xref = tiny_ref["X"]
+    sv = ehi.survey_from(s, precision="split_bf16")
+    sv.load_hessian(torch.from_numpy(H).to(DEV))
+    sv.factor(mu)
+    Lg = sv.copy_factor().cpu().numpy()
+    assert max(per_freq_rel(Lg, Lref)) < 1e-12
+    X = sv.apply_multipliers(torch.from_numpy(R).to(DEV)).cpu().numpy()
+    errs = per_freq_rel(X, Xref)
+    print("split mode solve rel err", errs)
+    assert max(errs) < 2e-6
+    # plain FP32 mode: FP32 Cholesky and solves, error ~ cond(Qhat) * 2^-24
+    sp = ehi.survey_from(s, precision="plain_fp32")
+    sp.load_hessian(torch.from_numpy(H).to(DEV))
+    sp.factor(mu)
+    Xp = sp.apply_multipliers(torch.from_numpy(R).to(DEV)).cpu().numpy()
+    errs_p = per_freq_rel(Xp, Xref)
+    print("plain mode solve rel err", errs_p)
+    assert max(errs_p) < 1e-2
+
+
+def test_end_to_end_tiny(ehi, tiny_ref):
+    s = tiny_ref["s"]
+    sv = ehi.survey_from(s, precision="split_bf16")
+    sv.build_green(torch.from_numpy(tiny_ref["v"]).to(DEV))
+    sv.build_hessian()
+    sv.factor(tiny_ref["mu"])
+    X = sv.apply_multipliers(torch.from_numpy(tiny_ref["R"]).to(DEV)).cpu().numpy()
+    errs = per_freq_rel(X, tiny_ref["X"])
+    print("end-to-end multipliers rel err per freq", errs)
+    assert max(errs) < 1e-5
+
+
+def test_lambda_max(ehi, tiny_ref):
+    s = tiny_ref["s"]
+    sv = ehi.survey_from(s)
+    sv.load_hessian(torch.from_numpy(tiny_ref["H"]).to(DEV))
+    lam = sv.lambda_max()
+    ref = solve.lambda_max(tiny_ref["H"])
+    assert abs(lam - ref) <= 1e-9 * ref
+
+
+def test_apply_source_chunks_and_zero(ehi, tiny_ref):
+    # more sources than max_ns: processed in chunks; ns = 0 is a no-op
+    s = tiny_ref["s"]
+    sv = ehi.survey_from(s, precision="split_bf16", max_ns=3)
+    sv.load_hessian(torch.from_numpy(tiny_ref["H"]).to(DEV))
+    sv.factor(tiny_ref["mu"])
+    X = sv.apply_multipliers(torch.from_numpy(tiny_ref["R"]).to(DEV)).cpu().numpy()
+    assert max(per_freq_rel(X, tiny_ref["X"])) < 2e-6
+    empty = torch.zeros((s.nf, 0, s.nr), dtype=torch.complex64, device=DEV)
+    sv.apply_multipliers(empty)
+
+
+def test_deterministic(ehi, tiny_ref):
+    s = tiny_ref["s"]
+    outs = []
+    for _ in range(2):
+        sv = ehi.survey_from(s)
+        sv.build_green(torch.from_numpy(tiny_ref["v"]).to(DEV))
+        sv.build_hessian()
+        sv.factor(tiny_ref["mu"])
+        outs.append(sv.apply_multipliers(torch.from_numpy(tiny_ref["R"]).to(DEV)).cpu().numpy())
+    np.testing.assert_array_equal(outs[0], outs[1])
+
+
+def test_error_paths(ehi, tiny_ref):
+    s = tiny_ref["s"]
+    sv = ehi.survey_from(s)
+    with pytest.raises(ehi.EhiError) as e:
+        sv.build_hessian()
+    assert e.value.status == ehi.EHI_ESTATE
+    with pytest.raises(ehi.EhiError) as e:
+        sv.factor(1.0)
+    assert e.value.status == ehi.EHI_ESTATE
+    R = torch.from_numpy(tiny_ref["R"]).to(DEV)
+    with pytest.raises(ehi.EhiError) as e:
+        sv.apply_multipliers(R)
+    assert e.value.status == ehi.EHI_ESTATE
+    # not positive definite: -I at frequency 2, small mu
+    H = np.array(tiny_ref["H"])
+    H[2] = -np.eye(s.nr)
+    sv.load_hessian(torch.from_numpy(H).to(DEV))
+    with pytest.raises(ehi.EhiError) as e:
+        sv.factor(1e-3)
+    assert e.value.status == ehi.EHI_ENOTPD and e.value.bad_freq == 2
+    with pytest.raises(ehi.EhiError) as e:
+        sv.apply_multipliers(R)
+    assert e.value.status == ehi.EHI_ESTATE
+    with pytest.raises(ehi.EhiError) as e:
+        sv.factor(-1.0)
+    assert e.value.status == ehi.EHI_EINVAL
+    sv.load_hessian(torch.from_numpy(tiny_ref["H"]).to(DEV))
+    sv.factor(tiny_ref["mu"])
+    with pytest.raises(ehi.EhiError) as e:
+        ehi._check(ehi.lib().ehi_apply_multipliers(sv._h, R.data_ptr(), R.data_ptr(), s.ns, None))
+    assert e.value.status == ehi.EHI_EINVAL
+    with pytest.raises(ValueError):
+        sv.apply_multipliers(R[:, :, :3].contiguous())
+    with pytest.raises(TypeError):
+        sv.apply_multipliers(R.to(torch.complex128))
