@@ -24,6 +24,10 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
 
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
 def rel(a, b):
     a = np.asarray(a)
     b = np.asarray(b)
@@ -55,7 +59,7 @@ def tiny_ref():
 
 def _gpu_green(ehi, s, v, precision="split_bf16", nr_batch=0):
     sv = ehi.survey_from(s, precision=precision, nr_batch=nr_batch)
-    sv.build_green(torch.from_numpy(v).to(DEV))
+    sv.build_green(dev(v))
     G = sv.copy_green_dft().reshape(s.nf, s.nr, -1)
     torch.cuda.synchronize()
     return sv, G.cpu().numpy()
@@ -100,11 +104,11 @@ def test_green_single_step_and_chunk_edges(ehi):
 
 def test_hessian_from_given_spectra(ehi, tiny_ref):
     s = tiny_ref["s"]
-    G64 = tiny_ref["G"].astype(np.complex64)
+    G64 = np.ascontiguousarray(tiny_ref["G"].astype(np.complex64))
     ref = hessian.hessian_r1(G64.astype(np.complex128))
     for prec in ("split_bf16", "plain_fp32"):
         sv = ehi.survey_from(s, precision=prec)
-        sv.load_green_dft(torch.from_numpy(G64.reshape(s.nf, s.nr, s.nzs, s.nxs)).to(DEV))
+        sv.load_green_dft(dev(G64.reshape(s.nf, s.nr, s.nzs, s.nxs)))
         sv.build_hessian()
         H = sv.copy_hessian().cpu().numpy()
         errs = per_freq_rel(H, ref)
@@ -123,19 +127,19 @@ def test_factor_and_solve_from_given_hessian(ehi, tiny_ref):
     Lref = solve.cholesky(solve.penalize(H, mu))
     Xref = tiny_ref["X"]
     sv = ehi.survey_from(s, precision="split_bf16")
-    sv.load_hessian(torch.from_numpy(H).to(DEV))
+    sv.load_hessian(dev(H))
     sv.factor(mu)
     Lg = sv.copy_factor().cpu().numpy()
     assert max(per_freq_rel(Lg, Lref)) < 1e-12
-    X = sv.apply_multipliers(torch.from_numpy(R).to(DEV)).cpu().numpy()
+    X = sv.apply_multipliers(dev(R)).cpu().numpy()
     errs = per_freq_rel(X, Xref)
     print("split mode solve rel err", errs)
     assert max(errs) < 2e-6
     # plain FP32 mode: FP32 Cholesky and solves, error ~ cond(Qhat) * 2^-24
     sp = ehi.survey_from(s, precision="plain_fp32")
-    sp.load_hessian(torch.from_numpy(H).to(DEV))
+    sp.load_hessian(dev(H))
     sp.factor(mu)
-    Xp = sp.apply_multipliers(torch.from_numpy(R).to(DEV)).cpu().numpy()
+    Xp = sp.apply_multipliers(dev(R)).cpu().numpy()
     errs_p = per_freq_rel(Xp, Xref)
     print("plain mode solve rel err", errs_p)
     assert max(errs_p) < 1e-2
@@ -144,10 +148,10 @@ def test_factor_and_solve_from_given_hessian(ehi, tiny_ref):
 def test_end_to_end_tiny(ehi, tiny_ref):
     s = tiny_ref["s"]
     sv = ehi.survey_from(s, precision="split_bf16")
-    sv.build_green(torch.from_numpy(tiny_ref["v"]).to(DEV))
+    sv.build_green(dev(tiny_ref["v"]))
     sv.build_hessian()
     sv.factor(tiny_ref["mu"])
-    X = sv.apply_multipliers(torch.from_numpy(tiny_ref["R"]).to(DEV)).cpu().numpy()
+    X = sv.apply_multipliers(dev(tiny_ref["R"])).cpu().numpy()
     errs = per_freq_rel(X, tiny_ref["X"])
     print("end-to-end multipliers rel err per freq", errs)
     assert max(errs) < 1e-5
@@ -156,7 +160,7 @@ def test_end_to_end_tiny(ehi, tiny_ref):
 def test_lambda_max(ehi, tiny_ref):
     s = tiny_ref["s"]
     sv = ehi.survey_from(s)
-    sv.load_hessian(torch.from_numpy(tiny_ref["H"]).to(DEV))
+    sv.load_hessian(dev(tiny_ref["H"]))
     lam = sv.lambda_max()
     ref = solve.lambda_max(tiny_ref["H"])
     assert abs(lam - ref) <= 1e-9 * ref
@@ -166,9 +170,9 @@ def test_apply_source_chunks_and_zero(ehi, tiny_ref):
     # more sources than max_ns: processed in chunks; ns = 0 is a no-op
     s = tiny_ref["s"]
     sv = ehi.survey_from(s, precision="split_bf16", max_ns=3)
-    sv.load_hessian(torch.from_numpy(tiny_ref["H"]).to(DEV))
+    sv.load_hessian(dev(tiny_ref["H"]))
     sv.factor(tiny_ref["mu"])
-    X = sv.apply_multipliers(torch.from_numpy(tiny_ref["R"]).to(DEV)).cpu().numpy()
+    X = sv.apply_multipliers(dev(tiny_ref["R"])).cpu().numpy()
     assert max(per_freq_rel(X, tiny_ref["X"])) < 2e-6
     empty = torch.zeros((s.nf, 0, s.nr), dtype=torch.complex64, device=DEV)
     sv.apply_multipliers(empty)
@@ -179,10 +183,10 @@ def test_deterministic(ehi, tiny_ref):
     outs = []
     for _ in range(2):
         sv = ehi.survey_from(s)
-        sv.build_green(torch.from_numpy(tiny_ref["v"]).to(DEV))
+        sv.build_green(dev(tiny_ref["v"]))
         sv.build_hessian()
         sv.factor(tiny_ref["mu"])
-        outs.append(sv.apply_multipliers(torch.from_numpy(tiny_ref["R"]).to(DEV)).cpu().numpy())
+        outs.append(sv.apply_multipliers(dev(tiny_ref["R"])).cpu().numpy())
     np.testing.assert_array_equal(outs[0], outs[1])
 
 
@@ -195,14 +199,14 @@ def test_error_paths(ehi, tiny_ref):
     with pytest.raises(ehi.EhiError) as e:
         sv.factor(1.0)
     assert e.value.status == ehi.EHI_ESTATE
-    R = torch.from_numpy(tiny_ref["R"]).to(DEV)
+    R = dev(tiny_ref["R"])
     with pytest.raises(ehi.EhiError) as e:
         sv.apply_multipliers(R)
     assert e.value.status == ehi.EHI_ESTATE
     # not positive definite: -I at frequency 2, small mu
     H = np.array(tiny_ref["H"])
     H[2] = -np.eye(s.nr)
-    sv.load_hessian(torch.from_numpy(H).to(DEV))
+    sv.load_hessian(dev(H))
     with pytest.raises(ehi.EhiError) as e:
         sv.factor(1e-3)
     assert e.value.status == ehi.EHI_ENOTPD and e.value.bad_freq == 2
@@ -212,7 +216,7 @@ def test_error_paths(ehi, tiny_ref):
     with pytest.raises(ehi.EhiError) as e:
         sv.factor(-1.0)
     assert e.value.status == ehi.EHI_EINVAL
-    sv.load_hessian(torch.from_numpy(tiny_ref["H"]).to(DEV))
+    sv.load_hessian(dev(tiny_ref["H"]))
     sv.factor(tiny_ref["mu"])
     with pytest.raises(ehi.EhiError) as e:
         ehi._check(ehi.lib().ehi_apply_multipliers(sv._h, R.data_ptr(), R.data_ptr(), s.ns, None))
