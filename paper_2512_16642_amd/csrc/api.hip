@@ -87,6 +87,7 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   int want = ehi::cdiv(2048, pairs * g.nf);
   int kmax = std::max(1, g.nsub / 1024);
   g.herk_split = std::max(1, std::min(want, std::min(ehi::kHerkSplitMax, kmax)));
+  g.tblock = 4;
   return g;
 }
 
@@ -107,7 +108,8 @@ ehi::Layout make_layout(const ehi::Geometry& g) {
   L.tw = take(sizeof(float2) * (size_t)g.nt * g.nf);
   L.u0 = take(sizeof(float) * g.plane() * g.nrb);
   L.u1 = take(sizeof(float) * g.plane() * g.nrb);
-  L.w = take(sizeof(float) * g.plane() * g.nrb);
+  L.w0 = take(sizeof(float) * g.plane() * g.nrb);
+  L.w1 = take(sizeof(float) * g.plane() * g.nrb);
   L.stage = take(sizeof(float) * (size_t)g.nrb * ehi::kChunk * g.nsub);
   L.ghat = take(sizeof(float2) * (size_t)g.nf * g.nr * g.nsub);
   L.hpart = take(sizeof(float2) * (size_t)g.herk_split * g.nf * nn);
@@ -289,30 +291,33 @@ ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev) {
   for (int r0 = 0; r0 < g.nr; r0 += g.nrb) {
     const int nb_now = std::min(g.nrb, g.nr - r0);
     float* ub[2] = {s->ptr<float>(L.u0), s->ptr<float>(L.u1)};
-    float* w = s->ptr<float>(L.w);
+    float* wb[2] = {s->ptr<float>(L.w0), s->ptr<float>(L.w1)};
     PROF(EHI_PROF_SETUP, st);
-    EHI_TRY(ehi::launch_wave_init(g, vel_dev, s->ptr<int32_t>(L.rec), r0, nb_now, ub[0], ub[1], w,
+    EHI_TRY(ehi::launch_wave_init(g, vel_dev, s->ptr<int32_t>(L.rec), r0, nb_now, ub[0], wb[0],
                                   stage, st),
             "wave init");
-    PROF_N(5);
+    PROF_N(4);
+    // sample n_cur sits in (ub[cur], wb[cur]) and in staging slot (n_cur - 1) % kChunk
     int cur = 0;
-    for (int n = 1; n <= g.nt; ++n) {  // sample n is in ub[cur] and staging slot (n-1) % kChunk
-      const int slot = (n - 1) % ehi::kChunk;
-      if (slot == ehi::kChunk - 1 || n == g.nt) {
-        const int n0 = n - slot;
+    int n_cur = 1;
+    for (;;) {
+      if (n_cur % ehi::kChunk == 0 || n_cur == g.nt) {
+        const int n0 = (n_cur - 1) / ehi::kChunk * ehi::kChunk + 1;
         PROF(EHI_PROF_DFT, st);
-        EHI_TRY(ehi::launch_dft_chunk(g, stage, tw, n0, slot + 1, n0 == 1, r0, nb_now, ghat, st),
+        EHI_TRY(ehi::launch_dft_chunk(g, stage, tw, n0, n_cur - n0 + 1, n0 == 1, r0, nb_now, ghat, st),
                 "dft chunk");
         PROF_N(1);
       }
-      if (n < g.nt) {
-        PROF(EHI_PROF_STEP, st);
-        EHI_TRY(ehi::launch_step(g, ca, ba, ub[cur], ub[1 - cur], w, stage, n % ehi::kChunk,
-                                 nb_now, st),
-                "time step");
-        PROF_N(1);
-        cur = 1 - cur;
-      }
+      if (n_cur == g.nt) break;
+      // advance to the next multiple of tblock (never past the chunk end: tblock | kChunk)
+      const int target = std::min(g.nt, (n_cur / g.tblock + 1) * g.tblock);
+      PROF(EHI_PROF_STEP, st);
+      EHI_TRY(ehi::launch_march(g, ca, ba, ub[cur], wb[cur], ub[1 - cur], wb[1 - cur], stage,
+                                n_cur % ehi::kChunk, target - n_cur, nb_now, st),
+              "time steps");
+      PROF_N(1);
+      cur = 1 - cur;
+      n_cur = target;
     }
   }
   PROF_END();

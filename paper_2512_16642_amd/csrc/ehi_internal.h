@@ -31,6 +31,7 @@ struct Geometry {
   int stride, nzs, nxs, nsub;
   int nt, nr, nf, nrb, max_ns;
   int herk_split;  // split-K partitions
+  int tblock;      // time levels per marching launch (2, 4 or 8; divides kChunk)
   double h, dt;
   __host__ __device__ size_t plane() const { return (size_t)Zp * Xp; }
 };
@@ -43,7 +44,8 @@ struct Layout {
   size_t ba;        // float [Zp][Xp]  b / a
   size_t vmax;      // uint32 [4]  max velocity bits
   size_t tw;        // float2 [nt][nf] exp(-i w n dt), n = 1..nt
-  size_t u0, u1, w; // float [nrb][Zp][Xp]
+  size_t u0, u1;    // float [nrb][Zp][Xp]  (ping-pong)
+  size_t w0, w1;    // float [nrb][Zp][Xp]  (ping-pong)
   size_t stage;     // float [nrb][kChunk][nsub]
   size_t ghat;      // float2 [nf][nr][nsub]
   size_t hpart;     // float2 [split][nf][nr][nr]
@@ -108,11 +110,11 @@ hipError_t launch_coefficients(const Geometry& g, const float* vel, const uint32
                                float* ca, float* ba, hipStream_t st);
 hipError_t launch_twiddles(const Geometry& g, const double* freq, float2* tw, hipStream_t st);
 hipError_t launch_wave_init(const Geometry& g, const float* vel, const int32_t* rec, int r0,
-                            int nrb_now, float* u0, float* u1, float* w, float* stage,
-                            hipStream_t st);
-hipError_t launch_step(const Geometry& g, const float* ca, const float* ba, const float* ucur,
-                       float* unext, float* w, float* stage, int slot, int nrb_now,
-                       hipStream_t st);
+                            int nrb_now, float* u0, float* w0, float* stage, hipStream_t st);
+int march_bands(const Geometry& g);
+hipError_t launch_march(const Geometry& g, const float* ca, const float* ba, const float* uin,
+                        const float* win, float* uout, float* wout, float* stage, int slot0,
+                        int nlev, int nrb_now, hipStream_t st);
 hipError_t launch_dft_chunk(const Geometry& g, const float* stage, const float2* tw, int n0,
                             int cnt, bool first, int r0, int nrb_now, float2* ghat,
                             hipStream_t st);

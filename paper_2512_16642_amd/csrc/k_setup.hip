@@ -116,6 +116,13 @@ __global__ void k_wave_init_point(Geometry g, const float* __restrict__ vel,
   }
 }
 
+// Zero staging slot 0 of every receiver of the batch (sample 1).
+__global__ void k_zero_slot0(float* __restrict__ stage, size_t nsub, size_t pitch, int nrb) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int r = blockIdx.y;
+  if (i < nsub && r < nrb) stage[(size_t)r * pitch + i] = 0.f;
+}
+
 __global__ void k_c128_from_c64(const float2* __restrict__ in, double2* __restrict__ out, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = make_double2((double)in[i].x, (double)in[i].y);
@@ -160,16 +167,15 @@ hipError_t launch_twiddles(const Geometry& g, const double* freq, float2* tw, hi
 }
 
 hipError_t launch_wave_init(const Geometry& g, const float* vel, const int32_t* rec, int r0,
-                            int nrb_now, float* u0, float* u1, float* w, float* stage,
-                            hipStream_t st) {
+                            int nrb_now, float* u0, float* w, float* stage, hipStream_t st) {
   size_t nplane = (size_t)nrb_now * g.plane();
   hipError_t e;
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(u0), 0u, nplane, st)) != hipSuccess) return e;
-  if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(u1), 0u, nplane, st)) != hipSuccess) return e;
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(w), 0u, nplane, st)) != hipSuccess) return e;
-  if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(stage), 0u,
-                           (size_t)nrb_now * kChunk * g.nsub, st)) != hipSuccess)
-    return e;
+  // slot 0 of the staging buffer holds sample 1: zero except at the receiver
+  hipLaunchKernelGGL(k_zero_slot0, dim3(cdiv(g.nsub, 256), nrb_now), dim3(256), 0, st, stage,
+                     (size_t)g.nsub, (size_t)kChunk * g.nsub, nrb_now);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_wave_init_point, dim3(cdiv(nrb_now, 64)), dim3(64), 0, st, g, vel, rec, r0,
                      nrb_now, u0, w, stage);
   return hipGetLastError();
