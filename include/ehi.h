@@ -69,7 +69,7 @@ typedef enum {
 /*
  * Survey descriptor.  Host memory; copied by ehi_create.
  *   nz, nx    interior grid, row-major [nz][nx], z pointing down.  >= 4 each.
- *   nb        absorbing layer width in cells on all four sides (>= 0).
+ *   nb        absorbing layer width in cells on all four sides (0..512).
  *   h         grid spacing (m), dt time step (s); the FD scheme needs
  *             vmax*dt/h <= sqrt(3/8) for stability (not checked: vmax is
  *             only known on the device).

@@ -38,7 +38,7 @@ bool validate(const ehi_survey_desc* d, std::string* why) {
   };
   if (!d) return bad("descriptor is NULL");
   if (d->nz < 4 || d->nx < 4) return bad("nz and nx must be >= 4");
-  if (d->nb < 0 || d->nb > 1024) return bad("nb must be in [0, 1024]");
+  if (d->nb < 0 || d->nb > ehi::kMaxSponge) return bad("nb must be in [0, 512]");
   if (!(d->h > 0) || !std::isfinite(d->h)) return bad("h must be positive and finite");
   if (!(d->dt > 0) || !std::isfinite(d->dt)) return bad("dt must be positive and finite");
   if (d->nt < 1) return bad("nt must be >= 1");
@@ -75,6 +75,8 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   g.nzs = ehi::cdiv(d->nz, d->stride);
   g.nxs = ehi::cdiv(d->nx, d->stride);
   g.nsub = g.nzs * g.nxs;
+  g.nsub_p = (int)ehi::align_up((size_t)g.nsub, 256);  // the DFT reads whole 256-point blocks
+  g.chunk = 256;
   g.nt = d->nt;
   g.nr = d->nr;
   g.nf = d->nf;
@@ -88,6 +90,7 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   int kmax = std::max(1, g.nsub / 1024);
   g.herk_split = std::max(1, std::min(want, std::min(ehi::kHerkSplitMax, kmax)));
   g.tblock = 4;
+  g.seg_rows = 64;
   return g;
 }
 
@@ -103,14 +106,14 @@ ehi::Layout make_layout(const ehi::Geometry& g) {
   L.freq = take(sizeof(double) * g.nf);
   L.rec = take(sizeof(int32_t) * 2 * g.nr);
   L.ca = take(sizeof(float) * g.plane());
-  L.ba = take(sizeof(float) * g.plane());
+  L.bd = take(sizeof(float) * (ehi::kMaxSponge + 1));
   L.vmax = take(sizeof(uint32_t) * 4);
   L.tw = take(sizeof(float2) * (size_t)g.nt * g.nf);
   L.u0 = take(sizeof(float) * g.plane() * g.nrb);
   L.u1 = take(sizeof(float) * g.plane() * g.nrb);
   L.w0 = take(sizeof(float) * g.plane() * g.nrb);
   L.w1 = take(sizeof(float) * g.plane() * g.nrb);
-  L.stage = take(sizeof(float) * (size_t)g.nrb * ehi::kChunk * g.nsub);
+  L.stage = take(sizeof(float) * (size_t)g.nrb * g.chunk * g.nsub_p);
   L.ghat = take(sizeof(float2) * (size_t)g.nf * g.nr * g.nsub);
   L.hpart = take(sizeof(float2) * (size_t)g.herk_split * g.nf * nn);
   L.hhat = take(sizeof(double2) * g.nf * nn);
@@ -280,10 +283,10 @@ ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev) {
   hipStream_t st = s->stream;
   uint32_t* vmax = s->ptr<uint32_t>(L.vmax);
   float* ca = s->ptr<float>(L.ca);
-  float* ba = s->ptr<float>(L.ba);
+  float* bd = s->ptr<float>(L.bd);
   PROF(EHI_PROF_SETUP, st);
   EHI_TRY(ehi::launch_vmax(vel_dev, g.nz * g.nx, vmax, st), "vmax");
-  EHI_TRY(ehi::launch_coefficients(g, vel_dev, vmax, ca, ba, st), "coefficients");
+  EHI_TRY(ehi::launch_coefficients(g, vel_dev, vmax, ca, bd, st), "coefficients");
   PROF_N(3);
   const float2* tw = s->ptr<float2>(L.tw);
   float2* ghat = s->ptr<float2>(L.ghat);
@@ -297,23 +300,23 @@ ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev) {
                                   stage, st),
             "wave init");
     PROF_N(4);
-    // sample n_cur sits in (ub[cur], wb[cur]) and in staging slot (n_cur - 1) % kChunk
+    // sample n_cur sits in (ub[cur], wb[cur]) and in staging slot (n_cur - 1) % chunk
     int cur = 0;
     int n_cur = 1;
     for (;;) {
-      if (n_cur % ehi::kChunk == 0 || n_cur == g.nt) {
-        const int n0 = (n_cur - 1) / ehi::kChunk * ehi::kChunk + 1;
+      if (n_cur % g.chunk == 0 || n_cur == g.nt) {
+        const int n0 = (n_cur - 1) / g.chunk * g.chunk + 1;
         PROF(EHI_PROF_DFT, st);
         EHI_TRY(ehi::launch_dft_chunk(g, stage, tw, n0, n_cur - n0 + 1, n0 == 1, r0, nb_now, ghat, st),
                 "dft chunk");
         PROF_N(1);
       }
       if (n_cur == g.nt) break;
-      // advance to the next multiple of tblock (never past the chunk end: tblock | kChunk)
+      // advance to the next multiple of tblock (never past the chunk end: tblock | chunk)
       const int target = std::min(g.nt, (n_cur / g.tblock + 1) * g.tblock);
       PROF(EHI_PROF_STEP, st);
-      EHI_TRY(ehi::launch_march(g, ca, ba, ub[cur], wb[cur], ub[1 - cur], wb[1 - cur], stage,
-                                n_cur % ehi::kChunk, target - n_cur, nb_now, st),
+      EHI_TRY(ehi::launch_march(g, ca, bd, ub[cur], wb[cur], ub[1 - cur], wb[1 - cur], stage,
+                                n_cur % g.chunk, target - n_cur, nb_now, st),
               "time steps");
       PROF_N(1);
       cur = 1 - cur;

@@ -15,7 +15,7 @@ namespace ehi {
 // ---- fixed design constants -------------------------------------------------
 constexpr int kGhost = 2;        // zero ring around the padded grid (stencil radius)
 constexpr int kRowAlign = 64;    // padded row pitch is a multiple of 64 floats (256 B)
-constexpr int kChunk = 64;       // time samples per DFT chunk (staging depth)
+constexpr int kMaxSponge = 512;  // largest absorbing-layer width (cells)
 constexpr int kHerkTile = 32;    // Hessian output tile (rows = cols)
 constexpr int kHerkSplitMax = 64;  // max split-K partitions of the grid sum
 constexpr size_t kAlign = 256;
@@ -29,9 +29,12 @@ struct Geometry {
   int Z, X;        // padded grid (interior + absorbing layer)
   int Zp, Xp;      // allocated plane incl. ghost ring and row padding
   int stride, nzs, nxs, nsub;
+  int nsub_p;      // staging row pitch (nsub rounded up to 256)
+  int chunk;       // time samples per DFT chunk (staging depth; multiple of 4 and tblock)
   int nt, nr, nf, nrb, max_ns;
   int herk_split;  // split-K partitions
-  int tblock;      // time levels per marching launch (2, 4 or 8; divides kChunk)
+  int tblock;      // time levels per marching launch (2, 4 or 8; divides chunk)
+  int seg_rows;    // output rows per marching segment
   double h, dt;
   __host__ __device__ size_t plane() const { return (size_t)Zp * Xp; }
 };
@@ -41,12 +44,12 @@ struct Layout {
   size_t freq;      // double [nf]
   size_t rec;       // int32 [2][nr]  (iz then ix, interior indices)
   size_t ca;        // float [Zp][Xp]  kappa / (12 h^2 a)
-  size_t ba;        // float [Zp][Xp]  b / a
+  size_t bd;        // float [kMaxSponge + 1]  b / a by distance into the layer
   size_t vmax;      // uint32 [4]  max velocity bits
   size_t tw;        // float2 [nt][nf] exp(-i w n dt), n = 1..nt
   size_t u0, u1;    // float [nrb][Zp][Xp]  (ping-pong)
   size_t w0, w1;    // float [nrb][Zp][Xp]  (ping-pong)
-  size_t stage;     // float [nrb][kChunk][nsub]
+  size_t stage;     // float [nrb][chunk][nsub_p]
   size_t ghat;      // float2 [nf][nr][nsub]
   size_t hpart;     // float2 [split][nf][nr][nr]
   size_t hhat;      // double2 [nf][nr][nr]
@@ -107,12 +110,12 @@ namespace ehi {
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t st);
 hipError_t launch_vmax(const float* vel, int n, uint32_t* out_bits, hipStream_t st);
 hipError_t launch_coefficients(const Geometry& g, const float* vel, const uint32_t* vmax_bits,
-                               float* ca, float* ba, hipStream_t st);
+                               float* ca, float* bd, hipStream_t st);
 hipError_t launch_twiddles(const Geometry& g, const double* freq, float2* tw, hipStream_t st);
 hipError_t launch_wave_init(const Geometry& g, const float* vel, const int32_t* rec, int r0,
                             int nrb_now, float* u0, float* w0, float* stage, hipStream_t st);
 int march_bands(const Geometry& g);
-hipError_t launch_march(const Geometry& g, const float* ca, const float* ba, const float* uin,
+hipError_t launch_march(const Geometry& g, const float* ca, const float* bd, const float* uin,
                         const float* win, float* uout, float* wout, float* stage, int slot0,
                         int nlev, int nrb_now, hipStream_t st);
 hipError_t launch_dft_chunk(const Geometry& g, const float* stage, const float2* tw, int n0,

@@ -4,6 +4,7 @@
 // batch and is negligible next to the time loop.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "ehi_internal.h"
@@ -39,24 +40,36 @@ __global__ void k_vmax(const float* __restrict__ vel, int n, uint32_t* __restric
   if (threadIdx.x == 0) atomicMax(out, red[0]);
 }
 
-// Padded-grid coefficients of the increment-form recurrence
+// Coefficients of the increment-form recurrence
 //   w^{n+1} = (b/a) w^n + kappa/(12 h^2 a) * L12 u^n ,  u^{n+1} = u^n + w^{n+1}
 // with L12 the 4th-order Laplacian scaled by 12 h^2 (integer weights
 // -1, 16, -30 per axis), kappa = v^2 dt^2, a = 1 + eta dt/2, b = 1 - eta dt/2,
 // eta = eta_max (d/nb)^2, eta_max = 3 vmax ln(1000) / (2 nb h), d the cell
-// distance into the absorbing layer.  Computed in FP64, rounded once.
-// Ghost cells get 0 so the field there stays 0.
+// distance into the absorbing layer.  Computed in FP64, rounded once:
+// ca[cell] = kappa / (12 h^2 a) on the padded plane (0 on the ghost ring) and
+// bd[d] = b / a for d = 0..nb (b/a depends on d only).
+__device__ inline double sponge_eta(const Geometry& g, double vmax, int d) {
+  if (g.nb <= 0 || d <= 0) return 0.0;
+  double emax = 3.0 * vmax * log(1000.0) / (2.0 * g.nb * g.h);
+  double r = (double)d / g.nb;
+  return emax * r * r;
+}
+
 __global__ void k_coefficients(Geometry g, const float* __restrict__ vel,
                                const uint32_t* __restrict__ vmax_bits, float* __restrict__ ca,
-                               float* __restrict__ ba) {
+                               float* __restrict__ bd) {
   int px = blockIdx.x * blockDim.x + threadIdx.x;  // plane column
   int pz = blockIdx.y;                             // plane row
+  const double vmax = (double)__uint_as_float(vmax_bits[0]);
+  if (pz == 0 && px <= g.nb) {
+    double eta = sponge_eta(g, vmax, px);
+    bd[px] = (float)((1.0 - eta * g.dt * 0.5) / (1.0 + eta * g.dt * 0.5));
+  }
   if (px >= g.Xp || pz >= g.Zp) return;
   size_t o = (size_t)pz * g.Xp + px;
   int iz = pz - kGhost, ix = px - kGhost;  // padded-grid indices
   if (iz < 0 || iz >= g.Z || ix < 0 || ix >= g.X) {
     ca[o] = 0.f;
-    ba[o] = 0.f;
     return;
   }
   int jz = min(max(iz - g.nb, 0), g.nz - 1);
@@ -64,19 +77,10 @@ __global__ void k_coefficients(Geometry g, const float* __restrict__ vel,
   double v = (double)vel[(size_t)jz * g.nx + jx];
   int dz = max(max(g.nb - iz, iz - (g.nb + g.nz - 1)), 0);
   int dx = max(max(g.nb - ix, ix - (g.nb + g.nx - 1)), 0);
-  int d = max(dz, dx);
-  double eta = 0.0;
-  if (g.nb > 0 && d > 0) {
-    double vmax = (double)__uint_as_float(vmax_bits[0]);
-    double emax = 3.0 * vmax * log(1000.0) / (2.0 * g.nb * g.h);
-    double r = (double)d / g.nb;
-    eta = emax * r * r;
-  }
+  double eta = sponge_eta(g, vmax, max(dz, dx));
   double a = 1.0 + eta * g.dt * 0.5;
-  double b = 1.0 - eta * g.dt * 0.5;
   double kappa = v * v * g.dt * g.dt;
   ca[o] = (float)(kappa / (12.0 * g.h * g.h * a));
-  ba[o] = (float)(b / a);
 }
 
 // tw[n-1][f] = exp(-i 2 pi f_hz n dt), n = 1..nt, evaluated in FP64.
@@ -111,7 +115,7 @@ __global__ void k_wave_init_point(Geometry g, const float* __restrict__ vel,
   u0[o] = val;
   w[o] = val;
   if (iz % g.stride == 0 && ix % g.stride == 0) {
-    size_t so = ((size_t)r * kChunk + 0) * g.nsub + (size_t)(iz / g.stride) * g.nxs + ix / g.stride;
+    size_t so = (size_t)r * g.chunk * g.nsub_p + (size_t)(iz / g.stride) * g.nxs + ix / g.stride;
     stage[so] = val;
   }
 }
@@ -153,9 +157,9 @@ hipError_t launch_vmax(const float* vel, int n, uint32_t* out_bits, hipStream_t 
 }
 
 hipError_t launch_coefficients(const Geometry& g, const float* vel, const uint32_t* vmax_bits,
-                               float* ca, float* ba, hipStream_t st) {
-  dim3 grid(cdiv(g.Xp, 256), g.Zp);
-  hipLaunchKernelGGL(k_coefficients, grid, dim3(256), 0, st, g, vel, vmax_bits, ca, ba);
+                               float* ca, float* bd, hipStream_t st) {
+  dim3 grid(cdiv(std::max(g.Xp, g.nb + 1), 256), g.Zp);
+  hipLaunchKernelGGL(k_coefficients, grid, dim3(256), 0, st, g, vel, vmax_bits, ca, bd);
   return hipGetLastError();
 }
 
@@ -174,7 +178,7 @@ hipError_t launch_wave_init(const Geometry& g, const float* vel, const int32_t* 
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(w), 0u, nplane, st)) != hipSuccess) return e;
   // slot 0 of the staging buffer holds sample 1: zero except at the receiver
   hipLaunchKernelGGL(k_zero_slot0, dim3(cdiv(g.nsub, 256), nrb_now), dim3(256), 0, st, stage,
-                     (size_t)g.nsub, (size_t)kChunk * g.nsub, nrb_now);
+                     (size_t)g.nsub, (size_t)g.chunk * g.nsub_p, nrb_now);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_wave_init_point, dim3(cdiv(nrb_now, 64)), dim3(64), 0, st, g, vel, rec, r0,
                      nrb_now, u0, w, stage);
