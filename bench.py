@@ -152,14 +152,18 @@ def main():
     survey_s = (stage_ms["build_green"] + stage_ms["build_hessian"] + stage_ms["factor"]) / 1e3
     solves_per_s = s.nf * s.ns / (stage_ms["apply"] / 1e3)
 
-    # roofline of the dominant kernel (the stencil step)
+    # roofline of the dominant kernel (the marching stencil)
     nrb = args.nr_batch if args.nr_batch > 0 else s.nr
+    tblock = int(os.environ.get("EHI_TBLOCK", "4"))
     step_ms, step_launches = prof["step"]
+    cell_updates = costs.stencil_cell_updates_per_survey(s.nz, s.nx, s.nb, s.nr, s.nt)
+    bpc = costs.stencil_bytes_per_cell_update(s.nz, s.nx, s.nb, s.stride, nrb, tblock)
+    bytes_total = bpc * cell_updates * K
     avg_step_s = step_ms / 1e3 / max(step_launches, 1)
-    bytes_launch = costs.stencil_bytes_per_launch(s.nz, s.nx, s.nb, s.stride, nrb)
+    bytes_launch = bytes_total / max(step_launches, 1)
     achieved = bytes_launch / avg_step_s / 1e9
     roof = {
-        "kernel": "k_step (stencil time step)",
+        "kernel": f"k_march<{tblock}> (stencil, {tblock} time levels per launch)",
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
@@ -167,10 +171,12 @@ def main():
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": None,
         "avg_launch_us": round(avg_step_s * 1e6, 2),
-        "bytes_per_launch": bytes_launch,
-        "bytes_per_cell_update": costs.stencil_bytes_per_cell_update(s.nz, s.nx, s.nb, s.stride, nrb),
+        "bytes_per_launch": round(bytes_launch),
+        "bytes_per_cell_update": round(bpc, 4),
     }
-    cell_updates = costs.stencil_cell_updates_per_survey(s.nz, s.nx, s.nb, s.nr, s.nt)
+    dft_ms = prof["dft"][0] / K
+    dft_bytes = costs.dft_bytes_per_survey(s.nz, s.nx, s.stride, s.nr, s.nt, s.nf, 256)
+    dft_flops = costs.dft_flops_per_survey(s.nz, s.nx, s.stride, s.nr, s.nt, s.nf)
     herk_flops = costs.herk_flops_per_survey(s.nz, s.nx, s.stride, s.nr, s.nf)
     herk_ms = prof["herk"][0] / K
     out = {
@@ -195,6 +201,8 @@ def main():
         "kernel_ms": {k: round(v[0] / K, 3) for k, v in prof.items()},
         "gcell_updates_per_s": round(cell_updates / (prof["step"][0] / K / 1e3) / 1e9, 2),
         "herk_tflops": round(herk_flops / (herk_ms / 1e3) / 1e12, 2) if herk_ms > 0 else None,
+        "dft_gbs": round(dft_bytes / (dft_ms / 1e3) / 1e9, 1) if dft_ms > 0 else None,
+        "dft_tflops": round(dft_flops / (dft_ms / 1e3) / 1e12, 2) if dft_ms > 0 else None,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

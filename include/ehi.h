@@ -75,7 +75,7 @@ typedef enum {
  *             only known on the device).
  *   nt        number of time steps; samples u^1..u^nt enter the DFT.
  *   stride    the Hessian contraction runs over interior cells (iz, ix) with
- *             iz % stride == 0 and ix % stride == 0 (1 <= stride <= 8).
+ *             iz % stride == 0 and ix % stride == 0 (stride 1, 2, 4 or 8).
  *   nr        receivers (1..1024); rec_iz/rec_ix are interior indices (host arrays of
  *             nr entries), 0 <= rec_iz < nz, 0 <= rec_ix < nx.
  *   nf        frequencies (1..64); freq_hz: host array of nf values >= 0 (Hz).  Any

@@ -22,22 +22,26 @@ def subgrid_points(nz, nx, stride):
     return ((nz + stride - 1) // stride) * ((nx + stride - 1) // stride)
 
 
-def stencil_bytes_per_cell_update(nz, nx, nb, stride, nrb):
-    """Increment-form step: read u and w, write w and u_next (4 x 4 B); the two
-    coefficient planes (8 B per cell) are shared by the nrb receivers of a
-    launch; the subgrid sample (4 B) goes to the staging buffer."""
+def stencil_bytes_per_cell_update(nz, nx, nb, stride, nrb, tblock):
+    """Marching step of tblock levels: u and w read once and written once per
+    launch (16 B per cell), the coefficient plane read once per launch and
+    shared by the nrb receivers (4 B per cell), and every level's subgrid sample
+    (4 B) written to the staging buffer."""
     cells = padded_cells(nz, nx, nb)
     sub = subgrid_points(nz, nx, stride)
-    return 16.0 + 8.0 / nrb + 4.0 * sub / cells
-
-
-def stencil_bytes_per_launch(nz, nx, nb, stride, nrb):
-    cells = padded_cells(nz, nx, nb) * nrb
-    return cells * stencil_bytes_per_cell_update(nz, nx, nb, stride, nrb)
+    return (16.0 + 4.0 / nrb) / tblock + 4.0 * sub / cells
 
 
 def stencil_cell_updates_per_survey(nz, nx, nb, nr, nt):
     return padded_cells(nz, nx, nb) * nr * (nt - 1)
+
+
+def dft_bytes_per_survey(nz, nx, stride, nr, nt, nf, chunk):
+    """Staged samples read once (4 B each) and the complex64 accumulators read
+    and written once per chunk."""
+    sub = subgrid_points(nz, nx, stride)
+    nchunk = -(-nt // chunk)
+    return 4.0 * sub * nr * nt + 16.0 * sub * nr * nf * nchunk
 
 
 def dft_flops_per_survey(nz, nx, stride, nr, nt, nf):

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -42,7 +43,8 @@ bool validate(const ehi_survey_desc* d, std::string* why) {
   if (!(d->h > 0) || !std::isfinite(d->h)) return bad("h must be positive and finite");
   if (!(d->dt > 0) || !std::isfinite(d->dt)) return bad("dt must be positive and finite");
   if (d->nt < 1) return bad("nt must be >= 1");
-  if (d->stride < 1 || d->stride > 8) return bad("stride must be in [1, 8]");
+  if (d->stride != 1 && d->stride != 2 && d->stride != 4 && d->stride != 8)
+    return bad("stride must be 1, 2, 4 or 8");
   if (d->nr < 1 || d->nr > 1024) return bad("nr must be in [1, 1024]");
   if (!d->rec_iz || !d->rec_ix) return bad("receiver arrays are NULL");
   for (int r = 0; r < d->nr; ++r) {
@@ -72,6 +74,7 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   g.Zp = g.Z + 2 * ehi::kGhost;
   g.Xp = (int)ehi::align_up((size_t)g.X + 2 * ehi::kGhost, ehi::kRowAlign);
   g.stride = d->stride;
+  g.sshift = d->stride == 1 ? 0 : d->stride == 2 ? 1 : d->stride == 4 ? 2 : 3;
   g.nzs = ehi::cdiv(d->nz, d->stride);
   g.nxs = ehi::cdiv(d->nx, d->stride);
   g.nsub = g.nzs * g.nxs;
@@ -91,6 +94,20 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   g.herk_split = std::max(1, std::min(want, std::min(ehi::kHerkSplitMax, kmax)));
   g.tblock = 4;
   g.seg_rows = 64;
+  g.rpt = 2;
+  // tuning overrides (launch shapes only; results do not depend on them)
+  if (const char* e = std::getenv("EHI_TBLOCK")) {
+    int v = std::atoi(e);
+    if (v == 4 || v == 8) g.tblock = v;
+  }
+  if (const char* e = std::getenv("EHI_RPT")) {
+    int v = std::atoi(e);
+    if (v == 1 || v == 2) g.rpt = v;
+  }
+  if (const char* e = std::getenv("EHI_SEG_ROWS")) {
+    int v = std::atoi(e);
+    if (v >= 16 && v <= 4096) g.seg_rows = v;
+  }
   return g;
 }
 

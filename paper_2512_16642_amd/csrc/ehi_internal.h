@@ -28,13 +28,14 @@ struct Geometry {
   int nz, nx, nb;
   int Z, X;        // padded grid (interior + absorbing layer)
   int Zp, Xp;      // allocated plane incl. ghost ring and row padding
-  int stride, nzs, nxs, nsub;
+  int stride, sshift, nzs, nxs, nsub;  // stride = 1 << sshift
   int nsub_p;      // staging row pitch (nsub rounded up to 256)
   int chunk;       // time samples per DFT chunk (staging depth; multiple of 4 and tblock)
   int nt, nr, nf, nrb, max_ns;
   int herk_split;  // split-K partitions
   int tblock;      // time levels per marching launch (2, 4 or 8; divides chunk)
   int seg_rows;    // output rows per marching segment
+  int rpt;         // receivers per thread in the marching kernel (1 or 2)
   double h, dt;
   __host__ __device__ size_t plane() const { return (size_t)Zp * Xp; }
 };

@@ -26,13 +26,6 @@ namespace {
 
 constexpr int kBand = 256;  // columns per workgroup (one per thread)
 
-template <int N>
-__device__ __forceinline__ void push(float (&a)[N], float v) {
-#pragma unroll
-  for (int i = 0; i < N - 1; ++i) a[i] = a[i + 1];
-  a[N - 1] = v;
-}
-
 // Increment-form recurrence (per cell, FP32):
 //   w <- ba * w + ca * (16 (u_{z-1} + u_{z+1} + u_{x-1} + u_{x+1})
 //                        - (u_{z-2} + u_{z+2} + u_{x-2} + u_{x+2}) - 60 u)
@@ -45,22 +38,153 @@ __device__ __forceinline__ void push(float (&a)[N], float v) {
 // can advance fewer than T steps.  Level t's sample (n_in + t) is written to
 // staging slot slot0 + t - 1 on the stride subgrid.
 //
-// Grid: (bands, row segments, receivers).  A segment owns output rows
-// [z0, z1) and starts marching 2T rows above z0: level t is exact on rows
-// >= z0 - 2T + 2t, so every level is exact on the owned rows.
-template <int T>
+// Grid: (bands, row segments, receiver groups of R).  A segment owns output
+// rows [z0, z1) and starts marching 2T rows above z0: level t is exact on rows
+// >= z0 - 2T + 2t, so every level is exact on the owned rows.  A thread carries
+// R receivers of the same column, which share the coefficients and all index
+// and control work.
+template <int T, int R>
+struct March {
+  static constexpr int B = kBand - 4 * T;  // output columns per band
+  static constexpr int CR = 2 * T + 2;     // rows of the ca ring (reuse distance 2T + 1 barriers)
+  static constexpr int W = kBand + 4;      // LDS row incl. two zero columns per side
+
+  struct Shared {
+    float lu[2][R][T][W];
+    float lc[CR][kBand];
+    float lb[kMaxSponge + 1];
+  };
+
+  // per-thread state
+  float uw[R][T][5];  // uw[j][t]: level-t rows q-2..q+2 for the level-(t+1) update of row q
+  float wd[R][T][3];  // wd[j][t]: level-t w of rows q..q+2
+  float pu[R][3], pw[R][3], pc[3];  // two-row prefetch queue of level-0 inputs
+
+  template <int N>
+  __device__ __forceinline__ static void push(float (&a)[N], float v) {
+#pragma unroll
+    for (int i = 0; i < N - 1; ++i) a[i] = a[i + 1];
+    a[N - 1] = v;
+  }
+
+  // One marched row k; BUF is (k - kb) & 1.  Row, level and receiver
+  // conditions are uniform across the workgroup (scalar branches); per-lane
+  // conditions are folded into precomputed masks.  Columns outside the grid
+  // carry ca = 0 and zero fields, so they stay exactly zero without masking.
+  template <int BUF>
+  __device__ __forceinline__ void row(Shared& sh, const Geometry& g, int k, int ring, int tid,
+                                      bool colv, bool own, bool lane_stg, int dxs, int sx, int z0,
+                                      int z1, int nlev, int slot0, const float* const (&ui)[R],
+                                      const float* const (&wi)[R], const float* cap,
+                                      float* const (&uo)[R], float* const (&wo)[R],
+                                      float* const (&st)[R], int nrv) {
+    const int Z = g.Z;
+    const size_t P = g.Xp;
+    {  // prefetch row k + 2 (addresses are clamped in range; invalid lanes select 0)
+      const int rowp = k + 2;
+      if (rowp >= 0 && rowp < Z) {
+        const size_t o = (size_t)(rowp + kGhost) * P;
+        const float cv = cap[o];
+        pc[2] = colv ? cv : 0.f;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          const float uv = ui[j][o], wv = wi[j][o];
+          pu[j][2] = colv ? uv : 0.f;
+          pw[j][2] = colv ? wv : 0.f;
+        }
+      } else {
+        pc[2] = 0.f;
+#pragma unroll
+        for (int j = 0; j < R; ++j) pu[j][2] = pw[j][2] = 0.f;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      push(uw[j][0], pu[j][0]);
+      push(wd[j][0], pw[j][0]);
+      sh.lu[BUF][j][0][tid + 2] = uw[j][0][2];
+#pragma unroll
+      for (int t = 1; t < T; ++t) sh.lu[BUF][j][t][tid + 2] = uw[j][t][3];
+    }
+    sh.lc[ring][tid] = pc[0];
+    __syncthreads();
+#pragma unroll
+    for (int t = 1; t <= T; ++t) {
+      const int q = k - 2 * t;
+      float un[R], wn[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) un[j] = wn[j] = 0.f;
+      if (q >= 0 && q < Z) {
+        if (t <= nlev) {
+          int slot = ring - 2 * t;
+          if (slot < 0) slot += CR;
+          const float a = sh.lc[slot][tid];
+          const int dzs = max(max(g.nb - q, q - (g.nb + g.nz - 1)), 0);
+          const float bq = sh.lb[max(dzs, dxs)];
+#pragma unroll
+          for (int j = 0; j < R; ++j) {
+            const float* L = sh.lu[BUF][j][t - 1];
+            const float cen = uw[j][t - 1][2];
+            const float n1 = (L[tid + 1] + L[tid + 3]) + (uw[j][t - 1][1] + uw[j][t - 1][3]);
+            const float n2 = (L[tid] + L[tid + 4]) + (uw[j][t - 1][0] + uw[j][t - 1][4]);
+            const float lap = 16.f * n1 - n2 - 60.f * cen;
+            wn[j] = bq * wd[j][t - 1][0] + a * lap;
+            un[j] = cen + wn[j];
+          }
+          const int jz = q - g.nb;
+          if (q >= z0 && q < z1 && jz >= 0 && jz < g.nz && (jz & (g.stride - 1)) == 0) {
+            const size_t so = (size_t)(slot0 + t - 1) * g.nsub_p + (size_t)(jz >> g.sshift) * g.nxs + sx;
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+              if (j < nrv && lane_stg) st[j][so] = un[j];
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < R; ++j) {
+            un[j] = uw[j][t - 1][2];
+            wn[j] = wd[j][t - 1][0];
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if (t < T) {
+          push(uw[j][t], un[j]);
+          push(wd[j][t], wn[j]);
+        }
+      }
+      if (t == T && q >= z0 && q < z1) {
+        const size_t o = (size_t)(q + kGhost) * P;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          if (j < nrv && own) {
+            uo[j][o] = un[j];
+            wo[j][o] = wn[j];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      pu[j][0] = pu[j][1];
+      pw[j][0] = pw[j][1];
+      pu[j][1] = pu[j][2];
+      pw[j][1] = pw[j][2];
+    }
+    pc[0] = pc[1];
+    pc[1] = pc[2];
+  }
+};
+
+template <int T, int R>
 __global__ void __launch_bounds__(kBand)
     k_march(Geometry g, const float* __restrict__ ca, const float* __restrict__ bd,
             const float* __restrict__ uin, const float* __restrict__ win, float* __restrict__ uout,
-            float* __restrict__ wout, float* __restrict__ stage, int slot0, int nlev) {
-  constexpr int B = kBand - 4 * T;  // output columns per band
-  constexpr int CR = 2 * T + 2;     // rows of the ca ring (reuse distance 2T + 1 barriers)
-  __shared__ float lu[2][T][kBand + 4];
-  __shared__ float lc[CR][kBand];
-  __shared__ float lb[kMaxSponge + 1];
+            float* __restrict__ wout, float* __restrict__ stage, int slot0, int nlev, int nrb_now) {
+  using M = March<T, R>;
+  __shared__ typename M::Shared sh;
   const int tid = threadIdx.x;
-  const int r = blockIdx.z;
-  const int x0 = blockIdx.x * B - 2 * T;  // padded-grid column of thread 0
+  const int x0 = blockIdx.x * M::B - 2 * T;  // padded-grid column of thread 0
   const int c = x0 + tid;
   const bool colv = (c >= 0 && c < g.X);
   const bool own = (tid >= 2 * T && tid < kBand - 2 * T && colv);
@@ -68,114 +192,81 @@ __global__ void __launch_bounds__(kBand)
   const int z0 = blockIdx.y * g.seg_rows;
   const int z1 = min(Z, z0 + g.seg_rows);
   const int kb = z0 - 2 * T;
-  const int P = g.Xp;
   const size_t plane = g.plane();
-  const float* ui = uin + (size_t)r * plane;
-  const float* wi = win + (size_t)r * plane;
-  float* uo = uout + (size_t)r * plane;
-  float* wo = wout + (size_t)r * plane;
-  float* st = stage + (size_t)r * g.chunk * g.nsub_p;
+  // column offset inside a plane row, clamped into the grid so every load is in range
+  const size_t cofs = (size_t)(min(max(c, 0), g.X - 1) + kGhost);
+  const int nrv = min(R, nrb_now - (int)blockIdx.z * R);  // valid receivers of this group
+  const float* ui[R];
+  const float* wi[R];
+  float* uo[R];
+  float* wo[R];
+  float* st[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int rr = j < nrv ? (int)blockIdx.z * R + j : 0;
+    ui[j] = uin + (size_t)rr * plane + cofs;
+    wi[j] = win + (size_t)rr * plane + cofs;
+    uo[j] = uout + (size_t)rr * plane + cofs;
+    wo[j] = wout + (size_t)rr * plane + cofs;
+    st[j] = stage + (size_t)rr * g.chunk * g.nsub_p;
+  }
+  const float* cap = ca + cofs;
   const int jx = c - g.nb;
-  const int sx = (jx >= 0 && jx < g.nx && (jx % g.stride) == 0) ? jx / g.stride : -1;
+  const int sx = (jx >= 0 && jx < g.nx && (jx & (g.stride - 1)) == 0) ? (jx >> g.sshift) : 0;
+  const bool lane_stg = own && jx >= 0 && jx < g.nx && (jx & (g.stride - 1)) == 0;
   const int dxs = max(max(g.nb - c, c - (g.nb + g.nx - 1)), 0);  // sponge distance in x
 
   if (tid < 2) {
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int t = 0; t < T; ++t) {
-        lu[b][t][tid] = 0.f;
-        lu[b][t][kBand + 2 + tid] = 0.f;
-      }
+      for (int j = 0; j < R; ++j)
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          sh.lu[b][j][t][tid] = 0.f;
+          sh.lu[b][j][t][kBand + 2 + tid] = 0.f;
+        }
   }
-  for (int i = tid; i <= g.nb; i += kBand) lb[i] = bd[i];
+#pragma unroll
+  for (int i = 0; i < M::CR; ++i) sh.lc[i][tid] = 0.f;
+  for (int i = tid; i <= g.nb; i += kBand) sh.lb[i] = bd[i];
 
-  float uw[T][5];  // uw[t]: level-t rows q-2..q+2 for the level-(t+1) update of row q
-  float wd[T][3];  // wd[t]: level-t w of rows q..q+2
+  M m;
 #pragma unroll
-  for (int t = 0; t < T; ++t) {
+  for (int j = 0; j < R; ++j)
 #pragma unroll
-    for (int i = 0; i < 5; ++i) uw[t][i] = 0.f;
+    for (int t = 0; t < T; ++t) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) wd[t][i] = 0.f;
-  }
-  // two-row prefetch queue of level-0 inputs
-  float pu[3], pw[3], pc[3];
+      for (int i = 0; i < 5; ++i) m.uw[j][t][i] = 0.f;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) m.wd[j][t][i] = 0.f;
+    }
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    const int row = kb + i;
-    pu[i] = pw[i] = pc[i] = 0.f;
-    if (colv && row >= 0 && row < Z) {
-      const size_t o = (size_t)(row + kGhost) * P + (c + kGhost);
-      pu[i] = ui[o];
-      pw[i] = wi[o];
-      pc[i] = ca[o];
+    const int rowp = kb + i;
+    const bool ok = colv && rowp >= 0 && rowp < Z;
+    const size_t o = (size_t)(min(max(rowp, 0), Z - 1) + kGhost) * g.Xp;
+    const float cv = cap[o];
+    m.pc[i] = ok ? cv : 0.f;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const float uv = ui[j][o], wv = wi[j][o];
+      m.pu[j][i] = ok ? uv : 0.f;
+      m.pw[j][i] = ok ? wv : 0.f;
     }
   }
 
-  int ring = 0;  // (k - kb) % CR
   const int ke = z1 + 2 * T;
-  for (int k = kb; k < ke; ++k) {
-    {
-      const int row = k + 2;
-      pu[2] = pw[2] = pc[2] = 0.f;
-      if (colv && row >= 0 && row < Z) {
-        const size_t o = (size_t)(row + kGhost) * P + (c + kGhost);
-        pu[2] = ui[o];
-        pw[2] = wi[o];
-        pc[2] = ca[o];
-      }
+  int ring = 0;  // (k - kb) % CR
+  for (int k = kb; k < ke; k += 2) {
+    m.template row<0>(sh, g, k, ring, tid, colv, own, lane_stg, dxs, sx, z0, z1, nlev, slot0, ui, wi,
+                      cap, uo, wo, st, nrv);
+    ring = (ring + 1 == M::CR) ? 0 : ring + 1;
+    if (k + 1 < ke) {
+      m.template row<1>(sh, g, k + 1, ring, tid, colv, own, lane_stg, dxs, sx, z0, z1, nlev, slot0,
+                        ui, wi, cap, uo, wo, st, nrv);
+      ring = (ring + 1 == M::CR) ? 0 : ring + 1;
     }
-    push(uw[0], pu[0]);
-    push(wd[0], pw[0]);
-    lc[ring][tid] = pc[0];
-    const int buf = (k - kb) & 1;
-    lu[buf][0][tid + 2] = uw[0][2];
-#pragma unroll
-    for (int t = 1; t < T; ++t) lu[buf][t][tid + 2] = uw[t][3];
-    __syncthreads();
-#pragma unroll
-    for (int t = 1; t <= T; ++t) {
-      const int q = k - 2 * t;
-      float un = 0.f, wn = 0.f;
-      if (colv && q >= 0 && q < Z) {
-        const float cen = uw[t - 1][2];
-        if (t <= nlev) {
-          const float* L = lu[buf][t - 1];
-          const float n1 = (L[tid + 1] + L[tid + 3]) + (uw[t - 1][1] + uw[t - 1][3]);
-          const float n2 = (L[tid] + L[tid + 4]) + (uw[t - 1][0] + uw[t - 1][4]);
-          const float lap = 16.f * n1 - n2 - 60.f * cen;
-          int slot = ring - 2 * t;
-          if (slot < 0) slot += CR;
-          const int dzs = max(max(g.nb - q, q - (g.nb + g.nz - 1)), 0);
-          const float bq = lb[max(dzs, dxs)];
-          wn = bq * wd[t - 1][0] + lc[slot][tid] * lap;
-          un = cen + wn;
-          const int jz = q - g.nb;
-          if (own && sx >= 0 && q >= z0 && q < z1 && jz >= 0 && jz < g.nz && (jz % g.stride) == 0) {
-            st[(size_t)(slot0 + t - 1) * g.nsub_p + (size_t)(jz / g.stride) * g.nxs + sx] = un;
-          }
-        } else {
-          un = cen;
-          wn = wd[t - 1][0];
-        }
-      }
-      if (t < T) {
-        push(uw[t], un);
-        push(wd[t], wn);
-      } else if (own && q >= z0 && q < z1) {
-        const size_t o = (size_t)(q + kGhost) * P + (c + kGhost);
-        uo[o] = un;
-        wo[o] = wn;
-      }
-    }
-    pu[0] = pu[1];
-    pw[0] = pw[1];
-    pc[0] = pc[1];
-    pu[1] = pu[2];
-    pw[1] = pw[2];
-    pc[1] = pc[2];
-    ring = (ring + 1 == CR) ? 0 : ring + 1;
   }
 }
 
@@ -268,24 +359,19 @@ hipError_t launch_march(const Geometry& g, const float* ca, const float* bd, con
                         const float* win, float* uout, float* wout, float* stage, int slot0,
                         int nlev, int nrb_now, hipStream_t st) {
   if (g.nb > kMaxSponge) return hipErrorInvalidValue;
-  dim3 grid(march_bands(g), cdiv(g.Z, g.seg_rows), nrb_now);
-  switch (g.tblock) {
-    case 2:
-      hipLaunchKernelGGL(k_march<2>, grid, dim3(kBand), 0, st, g, ca, bd, uin, win, uout, wout,
-                         stage, slot0, nlev);
-      break;
-    case 4:
-      hipLaunchKernelGGL(k_march<4>, grid, dim3(kBand), 0, st, g, ca, bd, uin, win, uout, wout,
-                         stage, slot0, nlev);
-      break;
-    case 8:
-      hipLaunchKernelGGL(k_march<8>, grid, dim3(kBand), 0, st, g, ca, bd, uin, win, uout, wout,
-                         stage, slot0, nlev);
-      break;
-    default:
-      return hipErrorInvalidValue;
+  dim3 grid(march_bands(g), cdiv(g.Z, g.seg_rows), cdiv(nrb_now, g.rpt));
+#define EHI_MARCH(TT, RR)                                                                     \
+  if (g.tblock == TT && g.rpt == RR) {                                                        \
+    hipLaunchKernelGGL((k_march<TT, RR>), grid, dim3(kBand), 0, st, g, ca, bd, uin, win, uout, \
+                       wout, stage, slot0, nlev, nrb_now);                                    \
+    return hipGetLastError();                                                                 \
   }
-  return hipGetLastError();
+  EHI_MARCH(4, 1)
+  EHI_MARCH(4, 2)
+  EHI_MARCH(8, 1)
+  EHI_MARCH(8, 2)
+#undef EHI_MARCH
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_dft_chunk(const Geometry& g, const float* stage, const float2* tw, int n0,

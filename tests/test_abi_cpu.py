@@ -47,6 +47,7 @@ def test_workspace_bytes_valid(ehi):
 
 @pytest.mark.parametrize("bad", [
     dict(nz=2), dict(nb=-1), dict(h=0.0), dict(dt=-1.0), dict(nt=0), dict(stride=0), dict(stride=9),
+    dict(stride=3), dict(nb=513),
     dict(rec_iz=[1, 20]), dict(rec_ix=[-1, 4]), dict(freqs_hz=[]), dict(freqs_hz=[float("nan")]),
     dict(precision=7), dict(max_ns=0), dict(nr_batch=-3),
 ])
