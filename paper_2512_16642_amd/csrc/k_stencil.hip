@@ -38,235 +38,206 @@ constexpr int kBand = 256;  // columns per workgroup (one per thread)
 // can advance fewer than T steps.  Level t's sample (n_in + t) is written to
 // staging slot slot0 + t - 1 on the stride subgrid.
 //
-// Grid: (bands, row segments, receiver groups of R).  A segment owns output
-// rows [z0, z1) and starts marching 2T rows above z0: level t is exact on rows
-// >= z0 - 2T + 2t, so every level is exact on the owned rows.  A thread carries
-// R receivers of the same column, which share the coefficients and all index
-// and control work.
-template <int T, int R>
-struct March {
+// Grid: (bands, row segments, receivers).  A segment owns output rows
+// [z0, z1) and starts marching 2T rows above z0: level t is exact on rows
+// >= z0 - 2T + 2t, so every level is exact on the owned rows.
+//
+// Pipeline: iteration i ingests level-0 rows rho = 2i, 2i+1 (rho counts rows
+// from the segment start kb = z0 - 2T) and level t computes rows 2i - 2t and
+// 2i - 2t + 1.  Level t needs level t-1 rows rho-2..rho+2 (its own column,
+// registers) and the x-neighbours of level t-1 rows 2i - 2t, 2i - 2t + 1, which
+// were produced in iteration i-1 and are published in LDS before the barrier.
+// Per level, rows live in 6-slot register rings (slot = rho mod 6); ca in a
+// 12-slot ring (slot = rho mod 12).  The iteration loop is unrolled by 6 so
+// every ring slot and the LDS buffer index are compile-time constants.
+// Row properties (inside the grid, owned by the segment, distance into the
+// absorbing layer, staging offset) are tabulated once per workgroup in LDS,
+// so the unrolled body carries almost no scalar control.
+constexpr int kMaxSegRows = 256;
+
+template <int T, bool FULL>
+struct March2 {
   static constexpr int B = kBand - 4 * T;  // output columns per band
-  static constexpr int CR = 2 * T + 2;     // rows of the ca ring (reuse distance 2T + 1 barriers)
   static constexpr int W = kBand + 4;      // LDS row incl. two zero columns per side
+  static constexpr int NRT = kMaxSegRows + 6 * T + 8;  // row-table entries (index rho + 2T)
 
   struct Shared {
-    float lu[2][R][T][W];
-    float lc[CR][kBand];
+    float lu[2][T][2][W];  // [buffer][level feeding level+1][row of the pair][column]
     float lb[kMaxSponge + 1];
+    int rinfo[NRT];  // bit 0: row inside the grid, bits 8..: distance into the top/bottom layer
+    int rown[NRT];   // padded-grid row offset (q + ghost) * pitch if the segment owns the row, else -1
+    int rsub[NRT];   // staging row offset (jz >> shift) * nxs if the owned row is on the subgrid, else -1
   };
 
-  // per-thread state
-  float uw[R][T][5];  // uw[j][t]: level-t rows q-2..q+2 for the level-(t+1) update of row q
-  float wd[R][T][3];  // wd[j][t]: level-t w of rows q..q+2
-  float pu[R][3], pw[R][3], pc[3];  // two-row prefetch queue of level-0 inputs
+  float U[T][6];   // level-t rows, slot = rho mod 6
+  float Wr[T][6];  // level-t w
+  float CA[12];    // ingested ca rows, slot = rho mod 12
+  float pu[2][2], pw[2][2], pc[2][2];  // prefetch sets [set][row of pair]
 
-  template <int N>
-  __device__ __forceinline__ static void push(float (&a)[N], float v) {
+  struct Ctx {
+    const float* ui;
+    const float* wi;
+    const float* cap;
+    float* uo;
+    float* wo;
+    float* st;  // staging base of this receiver and column (slot 0)
+    int tid, kb, Z, P, nlev, dxs, nsub_p;
+    bool colv, own, lane_stg;
+  };
+
+  __device__ __forceinline__ void load_pair(const Ctx& x, int rho, int set) {
 #pragma unroll
-    for (int i = 0; i < N - 1; ++i) a[i] = a[i + 1];
-    a[N - 1] = v;
+    for (int h = 0; h < 2; ++h) {
+      const int q = min(max(x.kb + rho + h, 0), x.Z - 1);  // clamped: always in range
+      const bool ok = x.colv && (x.kb + rho + h) >= 0 && (x.kb + rho + h) < x.Z;
+      const int o = (q + kGhost) * x.P;
+      const float u = x.ui[o], w = x.wi[o], c = x.cap[o];
+      pu[set][h] = ok ? u : 0.f;
+      pw[set][h] = ok ? w : 0.f;
+      pc[set][h] = ok ? c : 0.f;
+    }
   }
 
-  // One marched row k; BUF is (k - kb) & 1.  Row, level and receiver
-  // conditions are uniform across the workgroup (scalar branches); per-lane
-  // conditions are folded into precomputed masks.  Columns outside the grid
-  // carry ca = 0 and zero fields, so they stay exactly zero without masking.
-  template <int BUF>
-  __device__ __forceinline__ void row(Shared& sh, const Geometry& g, int k, int ring, int tid,
-                                      bool colv, bool own, bool lane_stg, int dxs, int sx, int z0,
-                                      int z1, int nlev, int slot0, const float* const (&ui)[R],
-                                      const float* const (&wi)[R], const float* cap,
-                                      float* const (&uo)[R], float* const (&wo)[R],
-                                      float* const (&st)[R], int nrv) {
-    const int Z = g.Z;
-    const size_t P = g.Xp;
-    {  // prefetch row k + 2 (addresses are clamped in range; invalid lanes select 0)
-      const int rowp = k + 2;
-      if (rowp >= 0 && rowp < Z) {
-        const size_t o = (size_t)(rowp + kGhost) * P;
-        const float cv = cap[o];
-        pc[2] = colv ? cv : 0.f;
+  template <int PH>  // PH = i mod 6
+  __device__ __forceinline__ void iter(Shared& sh, const Ctx& x, int i) {
+    constexpr int BUF = PH & 1;
+    constexpr int S0 = (2 * PH) % 6;   // ring slot of row 2i
+    constexpr int C0 = (2 * PH) % 12;  // ca slot of row 2i
+    constexpr int SET = PH & 1;
+    U[0][S0] = pu[SET][0];
+    U[0][S0 + 1] = pu[SET][1];
+    Wr[0][S0] = pw[SET][0];
+    Wr[0][S0 + 1] = pw[SET][1];
+    CA[C0] = pc[SET][0];
+    CA[C0 + 1] = pc[SET][1];
+    load_pair(x, 2 * i + 2, SET ^ 1);
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-          const float uv = ui[j][o], wv = wi[j][o];
-          pu[j][2] = colv ? uv : 0.f;
-          pw[j][2] = colv ? wv : 0.f;
-        }
-      } else {
-        pc[2] = 0.f;
+    for (int t = 0; t < T; ++t)
 #pragma unroll
-        for (int j = 0; j < R; ++j) pu[j][2] = pw[j][2] = 0.f;
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      push(uw[j][0], pu[j][0]);
-      push(wd[j][0], pw[j][0]);
-      sh.lu[BUF][j][0][tid + 2] = uw[j][0][2];
-#pragma unroll
-      for (int t = 1; t < T; ++t) sh.lu[BUF][j][t][tid + 2] = uw[j][t][3];
-    }
-    sh.lc[ring][tid] = pc[0];
+      for (int h = 0; h < 2; ++h) sh.lu[BUF][t][h][x.tid + 2] = U[t][((2 * PH - 2 * (t + 1) + h) % 6 + 6) % 6];
     __syncthreads();
 #pragma unroll
     for (int t = 1; t <= T; ++t) {
-      const int q = k - 2 * t;
-      float un[R], wn[R];
 #pragma unroll
-      for (int j = 0; j < R; ++j) un[j] = wn[j] = 0.f;
-      if (q >= 0 && q < Z) {
-        if (t <= nlev) {
-          int slot = ring - 2 * t;
-          if (slot < 0) slot += CR;
-          const float a = sh.lc[slot][tid];
-          const int dzs = max(max(g.nb - q, q - (g.nb + g.nz - 1)), 0);
-          const float bq = sh.lb[max(dzs, dxs)];
-#pragma unroll
-          for (int j = 0; j < R; ++j) {
-            const float* L = sh.lu[BUF][j][t - 1];
-            const float cen = uw[j][t - 1][2];
-            const float n1 = (L[tid + 1] + L[tid + 3]) + (uw[j][t - 1][1] + uw[j][t - 1][3]);
-            const float n2 = (L[tid] + L[tid + 4]) + (uw[j][t - 1][0] + uw[j][t - 1][4]);
-            const float lap = 16.f * n1 - n2 - 60.f * cen;
-            wn[j] = bq * wd[j][t - 1][0] + a * lap;
-            un[j] = cen + wn[j];
-          }
-          const int jz = q - g.nb;
-          if (q >= z0 && q < z1 && jz >= 0 && jz < g.nz && (jz & (g.stride - 1)) == 0) {
-            const size_t so = (size_t)(slot0 + t - 1) * g.nsub_p + (size_t)(jz >> g.sshift) * g.nxs + sx;
-#pragma unroll
-            for (int j = 0; j < R; ++j)
-              if (j < nrv && lane_stg) st[j][so] = un[j];
-          }
+      for (int h = 0; h < 2; ++h) {
+        const int sl = ((2 * PH - 2 * t + h) % 6 + 6) % 6;  // slot of row rho = 2i - 2t + h
+        const int sm2 = (sl + 4) % 6, sm1 = (sl + 5) % 6, sp1 = (sl + 1) % 6, sp2 = (sl + 2) % 6;
+        const int cs = ((2 * PH - 2 * t + h) % 12 + 12) % 12;
+        const int ti = 2 * i - 2 * t + h + 2 * T;  // row-table index
+        const int ri = sh.rinfo[ti];
+        const float cen = U[t - 1][sl];
+        float un, wn;
+        if (FULL || t <= x.nlev) {
+          const float* L = sh.lu[BUF][t - 1][h];
+          const float n1 = (L[x.tid + 1] + L[x.tid + 3]) + (U[t - 1][sm1] + U[t - 1][sp1]);
+          const float n2 = (L[x.tid] + L[x.tid + 4]) + (U[t - 1][sm2] + U[t - 1][sp2]);
+          const float lap = 16.f * n1 - n2 - 60.f * cen;
+          const float bq = sh.lb[max(ri >> 8, x.dxs)];
+          wn = bq * Wr[t - 1][sl] + CA[cs] * lap;
+          un = cen + wn;
+          const int rs = sh.rsub[ti];
+          if (x.lane_stg && rs >= 0) x.st[(x.nlev > 0 ? t - 1 : 0) * x.nsub_p + rs] = un;
         } else {
-#pragma unroll
-          for (int j = 0; j < R; ++j) {
-            un[j] = uw[j][t - 1][2];
-            wn[j] = wd[j][t - 1][0];
-          }
+          un = cen;
+          wn = Wr[t - 1][sl];
         }
-      }
-#pragma unroll
-      for (int j = 0; j < R; ++j) {
+        const bool inside = (ri & 1) != 0;
+        un = inside ? un : 0.f;
+        wn = inside ? wn : 0.f;
         if (t < T) {
-          push(uw[j][t], un[j]);
-          push(wd[j][t], wn[j]);
-        }
-      }
-      if (t == T && q >= z0 && q < z1) {
-        const size_t o = (size_t)(q + kGhost) * P;
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-          if (j < nrv && own) {
-            uo[j][o] = un[j];
-            wo[j][o] = wn[j];
+          U[t][sl] = un;
+          Wr[t][sl] = wn;
+        } else {
+          const int ro = sh.rown[ti];
+          if (x.own && ro >= 0) {
+            x.uo[ro] = un;
+            x.wo[ro] = wn;
           }
         }
       }
     }
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      pu[j][0] = pu[j][1];
-      pw[j][0] = pw[j][1];
-      pu[j][1] = pu[j][2];
-      pw[j][1] = pw[j][2];
-    }
-    pc[0] = pc[1];
-    pc[1] = pc[2];
   }
 };
 
-template <int T, int R>
+template <int T, bool FULL>
 __global__ void __launch_bounds__(kBand)
     k_march(Geometry g, const float* __restrict__ ca, const float* __restrict__ bd,
             const float* __restrict__ uin, const float* __restrict__ win, float* __restrict__ uout,
-            float* __restrict__ wout, float* __restrict__ stage, int slot0, int nlev, int nrb_now) {
-  using M = March<T, R>;
+            float* __restrict__ wout, float* __restrict__ stage, int slot0, int nlev) {
+  using M = March2<T, FULL>;
   __shared__ typename M::Shared sh;
-  const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * M::B - 2 * T;  // padded-grid column of thread 0
-  const int c = x0 + tid;
-  const bool colv = (c >= 0 && c < g.X);
-  const bool own = (tid >= 2 * T && tid < kBand - 2 * T && colv);
-  const int Z = g.Z;
+  typename M::Ctx x;
+  x.tid = threadIdx.x;
+  const int r = blockIdx.z;
+  const int c = blockIdx.x * M::B - 2 * T + x.tid;  // padded-grid column
+  x.colv = (c >= 0 && c < g.X);
+  x.own = (x.tid >= 2 * T && x.tid < kBand - 2 * T && x.colv);
+  x.Z = g.Z;
+  x.P = g.Xp;
   const int z0 = blockIdx.y * g.seg_rows;
-  const int z1 = min(Z, z0 + g.seg_rows);
-  const int kb = z0 - 2 * T;
+  const int z1 = min(g.Z, z0 + g.seg_rows);
+  x.kb = z0 - 2 * T;
+  const int n_it = (z1 - z0 + 4 * T + 1) / 2;
+  x.nlev = nlev;
+  x.nsub_p = g.nsub_p;
   const size_t plane = g.plane();
-  // column offset inside a plane row, clamped into the grid so every load is in range
-  const size_t cofs = (size_t)(min(max(c, 0), g.X - 1) + kGhost);
-  const int nrv = min(R, nrb_now - (int)blockIdx.z * R);  // valid receivers of this group
-  const float* ui[R];
-  const float* wi[R];
-  float* uo[R];
-  float* wo[R];
-  float* st[R];
-#pragma unroll
-  for (int j = 0; j < R; ++j) {
-    const int rr = j < nrv ? (int)blockIdx.z * R + j : 0;
-    ui[j] = uin + (size_t)rr * plane + cofs;
-    wi[j] = win + (size_t)rr * plane + cofs;
-    uo[j] = uout + (size_t)rr * plane + cofs;
-    wo[j] = wout + (size_t)rr * plane + cofs;
-    st[j] = stage + (size_t)rr * g.chunk * g.nsub_p;
-  }
-  const float* cap = ca + cofs;
+  const int cofs = min(max(c, 0), g.X - 1) + kGhost;  // clamped: every load is in range
+  x.ui = uin + (size_t)r * plane + cofs;
+  x.wi = win + (size_t)r * plane + cofs;
+  x.uo = uout + (size_t)r * plane + cofs;
+  x.wo = wout + (size_t)r * plane + cofs;
+  x.cap = ca + cofs;
   const int jx = c - g.nb;
-  const int sx = (jx >= 0 && jx < g.nx && (jx & (g.stride - 1)) == 0) ? (jx >> g.sshift) : 0;
-  const bool lane_stg = own && jx >= 0 && jx < g.nx && (jx & (g.stride - 1)) == 0;
-  const int dxs = max(max(g.nb - c, c - (g.nb + g.nx - 1)), 0);  // sponge distance in x
+  const bool subx = jx >= 0 && jx < g.nx && (jx & (g.stride - 1)) == 0;
+  x.st = stage + (size_t)r * g.chunk * g.nsub_p + (size_t)slot0 * g.nsub_p + (subx ? (jx >> g.sshift) : 0);
+  x.lane_stg = x.own && subx;
+  x.dxs = max(max(g.nb - c, c - (g.nb + g.nx - 1)), 0);
 
-  if (tid < 2) {
+  if (x.tid < 2) {
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int j = 0; j < R; ++j)
+      for (int t = 0; t < T; ++t)
 #pragma unroll
-        for (int t = 0; t < T; ++t) {
-          sh.lu[b][j][t][tid] = 0.f;
-          sh.lu[b][j][t][kBand + 2 + tid] = 0.f;
+        for (int h = 0; h < 2; ++h) {
+          sh.lu[b][t][h][x.tid] = 0.f;
+          sh.lu[b][t][h][kBand + 2 + x.tid] = 0.f;
         }
   }
-#pragma unroll
-  for (int i = 0; i < M::CR; ++i) sh.lc[i][tid] = 0.f;
-  for (int i = tid; i <= g.nb; i += kBand) sh.lb[i] = bd[i];
+  for (int i = x.tid; i <= g.nb; i += kBand) sh.lb[i] = bd[i];
+  for (int ti = x.tid; ti < M::NRT; ti += kBand) {
+    const int q = x.kb + ti - 2 * T;
+    const bool inside = q >= 0 && q < g.Z;
+    const int dzs = inside ? max(max(g.nb - q, q - (g.nb + g.nz - 1)), 0) : 0;
+    sh.rinfo[ti] = (inside ? 1 : 0) | (dzs << 8);
+    const bool owned = q >= z0 && q < z1;
+    sh.rown[ti] = owned ? (q + kGhost) * g.Xp : -1;
+    const int jz = q - g.nb;
+    const bool subz = owned && jz >= 0 && jz < g.nz && (jz & (g.stride - 1)) == 0;
+    sh.rsub[ti] = subz ? (jz >> g.sshift) * g.nxs : -1;
+  }
 
   M m;
 #pragma unroll
-  for (int j = 0; j < R; ++j)
+  for (int t = 0; t < T; ++t)
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
+    for (int s2 = 0; s2 < 6; ++s2) m.U[t][s2] = m.Wr[t][s2] = 0.f;
 #pragma unroll
-      for (int i = 0; i < 5; ++i) m.uw[j][t][i] = 0.f;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) m.wd[j][t][i] = 0.f;
-    }
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int rowp = kb + i;
-    const bool ok = colv && rowp >= 0 && rowp < Z;
-    const size_t o = (size_t)(min(max(rowp, 0), Z - 1) + kGhost) * g.Xp;
-    const float cv = cap[o];
-    m.pc[i] = ok ? cv : 0.f;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const float uv = ui[j][o], wv = wi[j][o];
-      m.pu[j][i] = ok ? uv : 0.f;
-      m.pw[j][i] = ok ? wv : 0.f;
-    }
-  }
+  for (int s2 = 0; s2 < 12; ++s2) m.CA[s2] = 0.f;
+  m.load_pair(x, 0, 0);
 
-  const int ke = z1 + 2 * T;
-  int ring = 0;  // (k - kb) % CR
-  for (int k = kb; k < ke; k += 2) {
-    m.template row<0>(sh, g, k, ring, tid, colv, own, lane_stg, dxs, sx, z0, z1, nlev, slot0, ui, wi,
-                      cap, uo, wo, st, nrv);
-    ring = (ring + 1 == M::CR) ? 0 : ring + 1;
-    if (k + 1 < ke) {
-      m.template row<1>(sh, g, k + 1, ring, tid, colv, own, lane_stg, dxs, sx, z0, z1, nlev, slot0,
-                        ui, wi, cap, uo, wo, st, nrv);
-      ring = (ring + 1 == M::CR) ? 0 : ring + 1;
-    }
+  for (int i = 0; i < n_it; i += 6) {
+    m.template iter<0>(sh, x, i);
+    if (i + 1 >= n_it) break;
+    m.template iter<1>(sh, x, i + 1);
+    if (i + 2 >= n_it) break;
+    m.template iter<2>(sh, x, i + 2);
+    if (i + 3 >= n_it) break;
+    m.template iter<3>(sh, x, i + 3);
+    if (i + 4 >= n_it) break;
+    m.template iter<4>(sh, x, i + 4);
+    if (i + 5 >= n_it) break;
+    m.template iter<5>(sh, x, i + 5);
   }
 }
 
@@ -358,20 +329,21 @@ int march_bands(const Geometry& g) { return cdiv(g.X, kBand - 4 * g.tblock); }
 hipError_t launch_march(const Geometry& g, const float* ca, const float* bd, const float* uin,
                         const float* win, float* uout, float* wout, float* stage, int slot0,
                         int nlev, int nrb_now, hipStream_t st) {
-  if (g.nb > kMaxSponge) return hipErrorInvalidValue;
-  dim3 grid(march_bands(g), cdiv(g.Z, g.seg_rows), cdiv(nrb_now, g.rpt));
-#define EHI_MARCH(TT, RR)                                                                     \
-  if (g.tblock == TT && g.rpt == RR) {                                                        \
-    hipLaunchKernelGGL((k_march<TT, RR>), grid, dim3(kBand), 0, st, g, ca, bd, uin, win, uout, \
-                       wout, stage, slot0, nlev, nrb_now);                                    \
-    return hipGetLastError();                                                                 \
+  if (g.nb > kMaxSponge || g.seg_rows > kMaxSegRows || nlev < 1 || nlev > g.tblock)
+    return hipErrorInvalidValue;
+  dim3 grid(march_bands(g), cdiv(g.Z, g.seg_rows), nrb_now);
+#define EHI_MARCH(TT, FF)                                                                          \
+  hipLaunchKernelGGL((k_march<TT, FF>), grid, dim3(kBand), 0, st, g, ca, bd, uin, win, uout, wout, \
+                     stage, slot0, nlev)
+  if (g.tblock == 4) {
+    if (nlev == 4) EHI_MARCH(4, true); else EHI_MARCH(4, false);
+  } else if (g.tblock == 8) {
+    if (nlev == 8) EHI_MARCH(8, true); else EHI_MARCH(8, false);
+  } else {
+    return hipErrorInvalidValue;
   }
-  EHI_MARCH(4, 1)
-  EHI_MARCH(4, 2)
-  EHI_MARCH(8, 1)
-  EHI_MARCH(8, 2)
 #undef EHI_MARCH
-  return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_dft_chunk(const Geometry& g, const float* stage, const float2* tw, int n0,
