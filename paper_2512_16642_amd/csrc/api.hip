@@ -60,7 +60,10 @@ bool validate(const ehi_survey_desc* d, std::string* why) {
   if (d->max_ns < 1 || d->max_ns > (1 << 20)) return bad("max_ns must be in [1, 2^20]");
   if (d->nr_batch < 0) return bad("nr_batch must be >= 0");
   long long Z = (long long)d->nz + 2LL * d->nb, X = (long long)d->nx + 2LL * d->nb;
-  if ((Z + 4) * (X + 4 + ehi::kRowAlign) > (1LL << 30)) return bad("grid too large");
+  // buffer resources address one plane / one staging block with 31-bit byte offsets
+  if ((Z + 4) * (X + 4 + ehi::kRowAlign) > (1LL << 28)) return bad("grid too large");
+  long long nsub = (long long)((d->nz + d->stride - 1) / d->stride) * ((d->nx + d->stride - 1) / d->stride);
+  if ((nsub + 256) * 256LL * 4 >= (1LL << 31)) return bad("subgrid too large for the staging buffer");
   return true;
 }
 
@@ -93,12 +96,12 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   int kmax = std::max(1, g.nsub / 1024);
   g.herk_split = std::max(1, std::min(want, std::min(ehi::kHerkSplitMax, kmax)));
   g.tblock = 4;
-  g.seg_rows = 64;
+  g.seg_rows = 128;
   g.rpt = 2;
   // tuning overrides (launch shapes only; results do not depend on them)
   if (const char* e = std::getenv("EHI_TBLOCK")) {
     int v = std::atoi(e);
-    if (v == 4 || v == 8) g.tblock = v;
+    if (v == 4) g.tblock = v;
   }
   if (const char* e = std::getenv("EHI_RPT")) {
     int v = std::atoi(e);
@@ -316,6 +319,10 @@ ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev) {
     EHI_TRY(ehi::launch_wave_init(g, vel_dev, s->ptr<int32_t>(L.rec), r0, nb_now, ub[0], wb[0],
                                   stage, st),
             "wave init");
+    // the marching kernel relies on zero ghost rings in both ping-pong buffers
+    const size_t nplane = (size_t)nb_now * g.plane();
+    EHI_TRY(ehi::launch_fill_u32(reinterpret_cast<uint32_t*>(ub[1]), 0u, nplane, st), "fill");
+    EHI_TRY(ehi::launch_fill_u32(reinterpret_cast<uint32_t*>(wb[1]), 0u, nplane, st), "fill");
     PROF_N(4);
     // sample n_cur sits in (ub[cur], wb[cur]) and in staging slot (n_cur - 1) % chunk
     int cur = 0;

@@ -55,6 +55,18 @@ constexpr int kBand = 256;  // columns per workgroup (one per thread)
 // so the unrolled body carries almost no scalar control.
 constexpr int kMaxSegRows = 256;
 
+// Raw buffer access: the row offset is a scalar (soffset), the column offset a
+// per-lane constant (voffset); bounds are the plane the resource describes.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
 template <int T, bool FULL>
 struct March2 {
   static constexpr int B = kBand - 4 * T;  // output columns per band
@@ -64,9 +76,9 @@ struct March2 {
   struct Shared {
     float lu[2][T][2][W];  // [buffer][level feeding level+1][row of the pair][column]
     float lb[kMaxSponge + 1];
-    int rinfo[NRT];  // bit 0: row inside the grid, bits 8..: distance into the top/bottom layer
-    int rown[NRT];   // padded-grid row offset (q + ghost) * pitch if the segment owns the row, else -1
-    int rsub[NRT];   // staging row offset (jz >> shift) * nxs if the owned row is on the subgrid, else -1
+    int rdz[NRT];    // distance of the row into the top/bottom layer (0 outside the grid)
+    int rown[NRT];   // byte offset of the row in a plane if the segment owns it, else -1
+    int rsub[NRT];   // byte offset of the row's subgrid line in a staging slot, else -1
   };
 
   float U[T][6];   // level-t rows, slot = rho mod 6
@@ -75,26 +87,25 @@ struct March2 {
   float pu[2][2], pw[2][2], pc[2][2];  // prefetch sets [set][row of pair]
 
   struct Ctx {
-    const float* ui;
-    const float* wi;
-    const float* cap;
-    float* uo;
-    float* wo;
-    float* st;  // staging base of this receiver and column (slot 0)
-    int tid, kb, Z, P, nlev, dxs, nsub_p;
-    bool colv, own, lane_stg;
+    __amdgpu_buffer_rsrc_t ru, rw, rc, rou, row_, rst;
+    int voff;   // byte offset of this lane's column in a plane row (ghost column if outside)
+    int vsub;   // byte offset of this lane's subgrid column in a staging line
+    int tid, kb, Z, Pb, nlev, dxs, slot_bytes;
+    bool own, lane_stg;
   };
+
+  // rows outside the grid read the zero ghost row next to the edge
+  __device__ __forceinline__ int row_bytes(const Ctx& x, int q) const {
+    return (min(max(q, -kGhost), x.Z + kGhost - 1) + kGhost) * x.Pb;
+  }
 
   __device__ __forceinline__ void load_pair(const Ctx& x, int rho, int set) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int q = min(max(x.kb + rho + h, 0), x.Z - 1);  // clamped: always in range
-      const bool ok = x.colv && (x.kb + rho + h) >= 0 && (x.kb + rho + h) < x.Z;
-      const int o = (q + kGhost) * x.P;
-      const float u = x.ui[o], w = x.wi[o], c = x.cap[o];
-      pu[set][h] = ok ? u : 0.f;
-      pw[set][h] = ok ? w : 0.f;
-      pc[set][h] = ok ? c : 0.f;
+      const int so = row_bytes(x, x.kb + rho + h);
+      pu[set][h] = bload(x.ru, x.voff, so);
+      pw[set][h] = bload(x.rw, x.voff, so);
+      pc[set][h] = bload(x.rc, x.voff, so);
     }
   }
 
@@ -124,7 +135,6 @@ struct March2 {
         const int sm2 = (sl + 4) % 6, sm1 = (sl + 5) % 6, sp1 = (sl + 1) % 6, sp2 = (sl + 2) % 6;
         const int cs = ((2 * PH - 2 * t + h) % 12 + 12) % 12;
         const int ti = 2 * i - 2 * t + h + 2 * T;  // row-table index
-        const int ri = sh.rinfo[ti];
         const float cen = U[t - 1][sl];
         float un, wn;
         if (FULL || t <= x.nlev) {
@@ -132,26 +142,23 @@ struct March2 {
           const float n1 = (L[x.tid + 1] + L[x.tid + 3]) + (U[t - 1][sm1] + U[t - 1][sp1]);
           const float n2 = (L[x.tid] + L[x.tid + 4]) + (U[t - 1][sm2] + U[t - 1][sp2]);
           const float lap = 16.f * n1 - n2 - 60.f * cen;
-          const float bq = sh.lb[max(ri >> 8, x.dxs)];
+          const float bq = sh.lb[max(sh.rdz[ti], x.dxs)];
           wn = bq * Wr[t - 1][sl] + CA[cs] * lap;
           un = cen + wn;
-          const int rs = sh.rsub[ti];
-          if (x.lane_stg && rs >= 0) x.st[(x.nlev > 0 ? t - 1 : 0) * x.nsub_p + rs] = un;
+          const int rs = __builtin_amdgcn_readfirstlane(sh.rsub[ti]);
+          if (rs >= 0 && x.lane_stg) bstore(un, x.rst, x.vsub, (t - 1) * x.slot_bytes + rs);
         } else {
           un = cen;
           wn = Wr[t - 1][sl];
         }
-        const bool inside = (ri & 1) != 0;
-        un = inside ? un : 0.f;
-        wn = inside ? wn : 0.f;
         if (t < T) {
           U[t][sl] = un;
           Wr[t][sl] = wn;
         } else {
-          const int ro = sh.rown[ti];
-          if (x.own && ro >= 0) {
-            x.uo[ro] = un;
-            x.wo[ro] = wn;
+          const int ro = __builtin_amdgcn_readfirstlane(sh.rown[ti]);
+          if (ro >= 0 && x.own) {
+            bstore(un, x.rou, x.voff, ro);
+            bstore(wn, x.row_, x.voff, ro);
           }
         }
       }
@@ -170,28 +177,32 @@ __global__ void __launch_bounds__(kBand)
   x.tid = threadIdx.x;
   const int r = blockIdx.z;
   const int c = blockIdx.x * M::B - 2 * T + x.tid;  // padded-grid column
-  x.colv = (c >= 0 && c < g.X);
-  x.own = (x.tid >= 2 * T && x.tid < kBand - 2 * T && x.colv);
+  const bool colv = (c >= 0 && c < g.X);
+  x.own = (x.tid >= 2 * T && x.tid < kBand - 2 * T && colv);
   x.Z = g.Z;
-  x.P = g.Xp;
+  x.Pb = g.Xp * 4;
   const int z0 = blockIdx.y * g.seg_rows;
   const int z1 = min(g.Z, z0 + g.seg_rows);
   x.kb = z0 - 2 * T;
   const int n_it = (z1 - z0 + 4 * T + 1) / 2;
   x.nlev = nlev;
-  x.nsub_p = g.nsub_p;
   const size_t plane = g.plane();
-  const int cofs = min(max(c, 0), g.X - 1) + kGhost;  // clamped: every load is in range
-  x.ui = uin + (size_t)r * plane + cofs;
-  x.wi = win + (size_t)r * plane + cofs;
-  x.uo = uout + (size_t)r * plane + cofs;
-  x.wo = wout + (size_t)r * plane + cofs;
-  x.cap = ca + cofs;
+  const size_t pbytes = plane * sizeof(float);
+  x.ru = make_rsrc(uin + (size_t)r * plane, pbytes);
+  x.rw = make_rsrc(win + (size_t)r * plane, pbytes);
+  x.rc = make_rsrc(ca, pbytes);
+  x.rou = make_rsrc(uout + (size_t)r * plane, pbytes);
+  x.row_ = make_rsrc(wout + (size_t)r * plane, pbytes);
+  const size_t sbytes = (size_t)g.chunk * g.nsub_p * sizeof(float);
+  x.rst = make_rsrc(stage + (size_t)r * g.chunk * g.nsub_p, sbytes);
+  x.slot_bytes = g.nsub_p * 4;
+  // columns outside the grid read the zero ghost column next to the edge
+  x.voff = (min(max(c, -kGhost), g.X + kGhost - 1) + kGhost) * 4;
   const int jx = c - g.nb;
   const bool subx = jx >= 0 && jx < g.nx && (jx & (g.stride - 1)) == 0;
-  x.st = stage + (size_t)r * g.chunk * g.nsub_p + (size_t)slot0 * g.nsub_p + (subx ? (jx >> g.sshift) : 0);
   x.lane_stg = x.own && subx;
-  x.dxs = max(max(g.nb - c, c - (g.nb + g.nx - 1)), 0);
+  x.vsub = subx ? (jx >> g.sshift) * 4 : 0;
+  x.dxs = colv ? max(max(g.nb - c, c - (g.nb + g.nx - 1)), 0) : 0;
 
   if (x.tid < 2) {
 #pragma unroll
@@ -208,13 +219,12 @@ __global__ void __launch_bounds__(kBand)
   for (int ti = x.tid; ti < M::NRT; ti += kBand) {
     const int q = x.kb + ti - 2 * T;
     const bool inside = q >= 0 && q < g.Z;
-    const int dzs = inside ? max(max(g.nb - q, q - (g.nb + g.nz - 1)), 0) : 0;
-    sh.rinfo[ti] = (inside ? 1 : 0) | (dzs << 8);
+    sh.rdz[ti] = inside ? max(max(g.nb - q, q - (g.nb + g.nz - 1)), 0) : 0;
     const bool owned = q >= z0 && q < z1;
-    sh.rown[ti] = owned ? (q + kGhost) * g.Xp : -1;
+    sh.rown[ti] = owned ? (q + kGhost) * x.Pb : -1;
     const int jz = q - g.nb;
     const bool subz = owned && jz >= 0 && jz < g.nz && (jz & (g.stride - 1)) == 0;
-    sh.rsub[ti] = subz ? (jz >> g.sshift) * g.nxs : -1;
+    sh.rsub[ti] = subz ? (slot0 * g.nsub_p + (jz >> g.sshift) * g.nxs) * 4 : -1;
   }
 
   M m;
@@ -337,8 +347,6 @@ hipError_t launch_march(const Geometry& g, const float* ca, const float* bd, con
                      stage, slot0, nlev)
   if (g.tblock == 4) {
     if (nlev == 4) EHI_MARCH(4, true); else EHI_MARCH(4, false);
-  } else if (g.tblock == 8) {
-    if (nlev == 8) EHI_MARCH(8, true); else EHI_MARCH(8, false);
   } else {
     return hipErrorInvalidValue;
   }
