@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--nr-batch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=300, help="FD steps in the CPU sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain 1 GiB device-to-device copy (a known-size kernel "
+                         "for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -103,6 +106,13 @@ def main():
     s = synth.WORKLOADS[args.workload]()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print("# copy calibration: 1 GiB read + 1 GiB written", file=sys.stderr, flush=True)
+        del a, b
     vel = torch.from_numpy(s.velocity()).to(dev)
     R = torch.from_numpy(s.residuals()).to(dev)
     X = torch.empty_like(R)
