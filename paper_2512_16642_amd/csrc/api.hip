@@ -101,7 +101,7 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   // tuning overrides (launch shapes only; results do not depend on them)
   if (const char* e = std::getenv("EHI_TBLOCK")) {
     int v = std::atoi(e);
-    if (v == 4) g.tblock = v;
+    if (v == 4 || v == 8) g.tblock = v;
   }
   if (const char* e = std::getenv("EHI_RPT")) {
     int v = std::atoi(e);

@@ -47,9 +47,9 @@ constexpr int kBand = 256;  // columns per workgroup (one per thread)
 // 2i - 2t + 1.  Level t needs level t-1 rows rho-2..rho+2 (its own column,
 // registers) and the x-neighbours of level t-1 rows 2i - 2t, 2i - 2t + 1, which
 // were produced in iteration i-1 and are published in LDS before the barrier.
-// Per level, rows live in 6-slot register rings (slot = rho mod 6); ca in a
-// 12-slot ring (slot = rho mod 12).  The iteration loop is unrolled by 6 so
-// every ring slot and the LDS buffer index are compile-time constants.
+// Per level, rows live in 6-slot register rings (slot = rho mod 6); ca rows in
+// an LDS ring of 2T + 4 rows.  The iteration loop is unrolled by 6 so every
+// register ring slot and the LDS buffer index are compile-time constants.
 // Row properties (inside the grid, owned by the segment, distance into the
 // absorbing layer, staging offset) are tabulated once per workgroup in LDS,
 // so the unrolled body carries almost no scalar control.
@@ -73,8 +73,11 @@ struct March2 {
   static constexpr int W = kBand + 4;      // LDS row incl. two zero columns per side
   static constexpr int NRT = kMaxSegRows + 6 * T + 8;  // row-table entries (index rho + 2T)
 
+  static constexpr int CR = 2 * T + 4;  // ca ring rows: 2T + 2 in use + one iteration of slack
+
   struct Shared {
     float lu[2][T][2][W];  // [buffer][level feeding level+1][row of the pair][column]
+    float lc[CR][kBand];   // ca ring, slot = rho mod CR
     float lb[kMaxSponge + 1];
     int rdz[NRT];    // distance of the row into the top/bottom layer (0 outside the grid)
     int rown[NRT];   // byte offset of the row in a plane if the segment owns it, else -1
@@ -83,7 +86,6 @@ struct March2 {
 
   float U[T][6];   // level-t rows, slot = rho mod 6
   float Wr[T][6];  // level-t w
-  float CA[12];    // ingested ca rows, slot = rho mod 12
   float pu[2][2], pw[2][2], pc[2][2];  // prefetch sets [set][row of pair]
 
   struct Ctx {
@@ -110,17 +112,17 @@ struct March2 {
   }
 
   template <int PH>  // PH = i mod 6
-  __device__ __forceinline__ void iter(Shared& sh, const Ctx& x, int i) {
+  __device__ __forceinline__ void iter(Shared& sh, const Ctx& x, int i, int cb) {
+    // cb = (2i) mod CR: ca ring slot of row 2i
     constexpr int BUF = PH & 1;
     constexpr int S0 = (2 * PH) % 6;   // ring slot of row 2i
-    constexpr int C0 = (2 * PH) % 12;  // ca slot of row 2i
     constexpr int SET = PH & 1;
     U[0][S0] = pu[SET][0];
     U[0][S0 + 1] = pu[SET][1];
     Wr[0][S0] = pw[SET][0];
     Wr[0][S0 + 1] = pw[SET][1];
-    CA[C0] = pc[SET][0];
-    CA[C0 + 1] = pc[SET][1];
+    sh.lc[cb][x.tid] = pc[SET][0];
+    sh.lc[cb + 1][x.tid] = pc[SET][1];
     load_pair(x, 2 * i + 2, SET ^ 1);
 #pragma unroll
     for (int t = 0; t < T; ++t)
@@ -133,7 +135,8 @@ struct March2 {
       for (int h = 0; h < 2; ++h) {
         const int sl = ((2 * PH - 2 * t + h) % 6 + 6) % 6;  // slot of row rho = 2i - 2t + h
         const int sm2 = (sl + 4) % 6, sm1 = (sl + 5) % 6, sp1 = (sl + 1) % 6, sp2 = (sl + 2) % 6;
-        const int cs = ((2 * PH - 2 * t + h) % 12 + 12) % 12;
+        int cs = cb - 2 * t + h;  // ca ring slot of row rho
+        if (cs < 0) cs += CR;
         const int ti = 2 * i - 2 * t + h + 2 * T;  // row-table index
         const float cen = U[t - 1][sl];
         float un, wn;
@@ -143,7 +146,7 @@ struct March2 {
           const float n2 = (L[x.tid] + L[x.tid + 4]) + (U[t - 1][sm2] + U[t - 1][sp2]);
           const float lap = 16.f * n1 - n2 - 60.f * cen;
           const float bq = sh.lb[max(sh.rdz[ti], x.dxs)];
-          wn = bq * Wr[t - 1][sl] + CA[cs] * lap;
+          wn = bq * Wr[t - 1][sl] + sh.lc[cs][x.tid] * lap;
           un = cen + wn;
           const int rs = __builtin_amdgcn_readfirstlane(sh.rsub[ti]);
           if (rs >= 0 && x.lane_stg) bstore(un, x.rst, x.vsub, (t - 1) * x.slot_bytes + rs);
@@ -175,13 +178,15 @@ __global__ void __launch_bounds__(kBand)
   __shared__ typename M::Shared sh;
   typename M::Ctx x;
   x.tid = threadIdx.x;
-  const int r = blockIdx.z;
-  const int c = blockIdx.x * M::B - 2 * T + x.tid;  // padded-grid column
+  // receivers vary fastest in the grid so the workgroups of one band and segment
+  // run together and share its ca rows in L2
+  const int r = blockIdx.x;
+  const int c = blockIdx.y * M::B - 2 * T + x.tid;  // padded-grid column
   const bool colv = (c >= 0 && c < g.X);
   x.own = (x.tid >= 2 * T && x.tid < kBand - 2 * T && colv);
   x.Z = g.Z;
   x.Pb = g.Xp * 4;
-  const int z0 = blockIdx.y * g.seg_rows;
+  const int z0 = blockIdx.z * g.seg_rows;
   const int z1 = min(g.Z, z0 + g.seg_rows);
   x.kb = z0 - 2 * T;
   const int n_it = (z1 - z0 + 4 * T + 1) / 2;
@@ -232,22 +237,29 @@ __global__ void __launch_bounds__(kBand)
   for (int t = 0; t < T; ++t)
 #pragma unroll
     for (int s2 = 0; s2 < 6; ++s2) m.U[t][s2] = m.Wr[t][s2] = 0.f;
-#pragma unroll
-  for (int s2 = 0; s2 < 12; ++s2) m.CA[s2] = 0.f;
+  for (int s2 = 0; s2 < M::CR; ++s2) sh.lc[s2][x.tid] = 0.f;
   m.load_pair(x, 0, 0);
 
+  int cb = 0;  // (2i) mod CR
+  auto adv = [&]() { cb = (cb + 2 >= M::CR) ? cb + 2 - M::CR : cb + 2; };
   for (int i = 0; i < n_it; i += 6) {
-    m.template iter<0>(sh, x, i);
+    m.template iter<0>(sh, x, i, cb);
+    adv();
     if (i + 1 >= n_it) break;
-    m.template iter<1>(sh, x, i + 1);
+    m.template iter<1>(sh, x, i + 1, cb);
+    adv();
     if (i + 2 >= n_it) break;
-    m.template iter<2>(sh, x, i + 2);
+    m.template iter<2>(sh, x, i + 2, cb);
+    adv();
     if (i + 3 >= n_it) break;
-    m.template iter<3>(sh, x, i + 3);
+    m.template iter<3>(sh, x, i + 3, cb);
+    adv();
     if (i + 4 >= n_it) break;
-    m.template iter<4>(sh, x, i + 4);
+    m.template iter<4>(sh, x, i + 4, cb);
+    adv();
     if (i + 5 >= n_it) break;
-    m.template iter<5>(sh, x, i + 5);
+    m.template iter<5>(sh, x, i + 5, cb);
+    adv();
   }
 }
 
@@ -341,12 +353,14 @@ hipError_t launch_march(const Geometry& g, const float* ca, const float* bd, con
                         int nlev, int nrb_now, hipStream_t st) {
   if (g.nb > kMaxSponge || g.seg_rows > kMaxSegRows || nlev < 1 || nlev > g.tblock)
     return hipErrorInvalidValue;
-  dim3 grid(march_bands(g), cdiv(g.Z, g.seg_rows), nrb_now);
+  dim3 grid(nrb_now, march_bands(g), cdiv(g.Z, g.seg_rows));
 #define EHI_MARCH(TT, FF)                                                                          \
   hipLaunchKernelGGL((k_march<TT, FF>), grid, dim3(kBand), 0, st, g, ca, bd, uin, win, uout, wout, \
                      stage, slot0, nlev)
   if (g.tblock == 4) {
     if (nlev == 4) EHI_MARCH(4, true); else EHI_MARCH(4, false);
+  } else if (g.tblock == 8) {
+    if (nlev == 8) EHI_MARCH(8, true); else EHI_MARCH(8, false);
   } else {
     return hipErrorInvalidValue;
   }
