@@ -90,7 +90,7 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   g.max_ns = d->max_ns;
   g.h = d->h;
   g.dt = d->dt;
-  int ntile = ehi::cdiv(g.nr, ehi::kHerkTile);
+  int ntile = ehi::cdiv(g.nr, d->precision == EHI_PREC_SPLIT_BF16 ? 64 : ehi::kHerkTile);
   int pairs = ntile * (ntile + 1) / 2;
   int want = ehi::cdiv(2048, pairs * g.nf);
   int kmax = std::max(1, g.nsub / 1024);
@@ -360,7 +360,11 @@ ehi_status ehi_build_hessian(ehi_survey* s) {
   const ehi::Layout& L = s->L;
   float2* hpart = s->ptr<float2>(L.hpart);
   PROF(EHI_PROF_HERK, s->stream);
-  EHI_TRY(ehi::launch_herk_fp32(g, s->ptr<float2>(L.ghat), hpart, s->stream), "herk");
+  if (s->precision == EHI_PREC_SPLIT_BF16) {
+    EHI_TRY(ehi::launch_herk_split_bf16(g, s->ptr<float2>(L.ghat), hpart, s->stream), "herk bf16");
+  } else {
+    EHI_TRY(ehi::launch_herk_fp32(g, s->ptr<float2>(L.ghat), hpart, s->stream), "herk fp32");
+  }
   EHI_TRY(ehi::launch_herk_reduce(g, hpart, s->ptr<double2>(L.hhat), s->stream), "herk reduce");
   PROF_N(2);
   PROF_END();

@@ -123,6 +123,8 @@ hipError_t launch_dft_chunk(const Geometry& g, const float* stage, const float2*
                             int cnt, bool first, int r0, int nrb_now, float2* ghat,
                             hipStream_t st);
 hipError_t launch_herk_fp32(const Geometry& g, const float2* ghat, float2* hpart, hipStream_t st);
+hipError_t launch_herk_split_bf16(const Geometry& g, const float2* ghat, float2* hpart,
+                                  hipStream_t st);
 hipError_t launch_herk_reduce(const Geometry& g, const float2* hpart, double2* hhat,
                               hipStream_t st);
 hipError_t launch_penalty(const Geometry& g, const double2* hhat, double mu, double2* qhat,

@@ -86,6 +86,137 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// Precision form: split-BF16 products on MFMA with FP32 accumulation.
+// With g = a + i b, Re H = A A^T + B B^T and Im H = B A^T - A B^T (rows i, j;
+// columns = grid points).  Every FP32 value x is split as x = hi + lo + O(2^-17 x)
+// with hi = bf16(x), lo = bf16(x - hi), and a product xy is taken as
+// hi*hi + hi*lo + lo*hi.  The dropped lo*lo term averages out off the diagonal
+// but is systematically positive in sum_x |g|^2, so the 16x16 tiles on the
+// diagonal of H add lo*lo for the real part.
+//
+// Workgroup: 4 waves, a 64 x 64 tile (i-block, j-block) of H for one frequency
+// and one grid-point partition; each wave owns a 32 x 32 quarter as 2 x 2
+// v_mfma_f32_16x16x32_bf16 tiles for Re and Im.  Per stage, 32 grid points of
+// the 128 rows are loaded once, split into hi/lo BF16 planes in LDS, and read
+// back as MFMA fragments (lane l: row l % 16, points 8 (l / 16) .. + 7).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBt = 64;  // H tile (rows = cols)
+constexpr int kBk = 32;  // grid points per stage (four groups of 8)
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+__global__ void __launch_bounds__(256)
+    k_herk_bf16(Geometry g, const float2* __restrict__ ghat, float2* __restrict__ hpart, int split) {
+  // planes: 0 = Re hi, 1 = Re lo, 2 = Im hi, 3 = Im lo; rows 0..63 i-block, 64..127 j-block;
+  // [plane][group of 8 points][row][8]: every fragment is one aligned 16-byte chunk
+  __shared__ __attribute__((aligned(16))) unsigned short pl[4][kBk / 8][2 * kBt][8];
+  const int nblk = cdiv(g.nr, kBt);
+  int bi, bj;
+  {
+    int p = blockIdx.x, i = 0;
+    while (p >= nblk - i) {
+      p -= nblk - i;
+      ++i;
+    }
+    bi = i;
+    bj = i + p;
+  }
+  const int ks = blockIdx.y;
+  const int f = blockIdx.z;
+  const int kchunk = cdiv(cdiv(g.nsub, split), kBk) * kBk;
+  const int k0 = ks * kchunk;
+  const int k1 = min(g.nsub, k0 + kchunk);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const float2* G = ghat + (size_t)f * g.nr * g.nsub;
+
+  floatx4 re[2][2], im[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) re[a][b] = im[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  // load assignment: thread -> (row 0..127, 16 consecutive points)
+  const int lrow = tid >> 1;
+  const int lhalf = tid & 1;
+  const int grow = lrow < kBt ? bi * kBt + lrow : bj * kBt + (lrow - kBt);
+  const bool rowv = grow < g.nr;
+  const float2* Grow = G + (size_t)(rowv ? grow : 0) * g.nsub;
+
+  for (int kb = k0; kb < k1; kb += kBk) {
+    __syncthreads();
+#pragma unroll 4
+    for (int e = 0; e < 16; ++e) {
+      const int k = kb + lhalf * 16 + e;
+      float2 v = make_float2(0.f, 0.f);
+      if (rowv && k < k1) v = Grow[k];
+      const unsigned short rh = bf16_rne(v.x), ih = bf16_rne(v.y);
+      const int kk = lhalf * 16 + e;
+      pl[0][kk >> 3][lrow][kk & 7] = rh;
+      pl[1][kk >> 3][lrow][kk & 7] = bf16_rne(v.x - bf16_to_f(rh));
+      pl[2][kk >> 3][lrow][kk & 7] = ih;
+      pl[3][kk >> 3][lrow][kk & 7] = bf16_rne(v.y - bf16_to_f(ih));
+    }
+    __syncthreads();
+    const int fr = lane & 15, fg = lane >> 4;
+    bf16x8 ai[2][4], aj[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ai[a][q] = *reinterpret_cast<const bf16x8*>(&pl[q][fg][wi * 32 + a * 16 + fr][0]);
+        aj[a][q] = *reinterpret_cast<const bf16x8*>(&pl[q][fg][kBt + wj * 32 + a * 16 + fr][0]);
+      }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      // -A_i fragments for the subtracted term of Im
+      bf16x8 nrh = -ai[a][0], nrl = -ai[a][1];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        floatx4 r = re[a][b], m = im[a][b];
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][0], aj[b][0], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][0], aj[b][1], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][1], aj[b][0], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][2], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][3], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][2], r, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][0], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][1], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][0], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrh, aj[b][2], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrh, aj[b][3], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrl, aj[b][2], m, 0, 0, 0);
+        if (bi * kBt + wi * 32 + a * 16 == bj * kBt + wj * 32 + b * 16) {
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][1], aj[b][1], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][3], r, 0, 0, 0);
+        }
+        re[a][b] = r;
+        im[a][b] = m;
+      }
+    }
+  }
+  // D[4 (lane / 16) + v][lane % 16] of tile (a, b)
+  float2* out = hpart + ((size_t)ks * g.nf + f) * g.nr * g.nr;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = bi * kBt + wi * 32 + a * 16 + 4 * (lane >> 4) + v;
+        const int j = bj * kBt + wj * 32 + b * 16 + (lane & 15);
+        if (i < g.nr && j < g.nr) out[(size_t)i * g.nr + j] = make_float2(re[a][b][v], im[a][b][v]);
+      }
+}
+
 // hhat[f][i][j] = sum_ks hpart[ks][f][i][j] (FP64, ascending ks) for j >= i,
 // mirrored to [j][i] as the conjugate; the diagonal's imaginary part is 0.
 __global__ void k_herk_reduce(Geometry g, const float2* __restrict__ hpart, double2* __restrict__ hhat,
@@ -116,6 +247,18 @@ hipError_t launch_herk_fp32(const Geometry& g, const float2* ghat, float2* hpart
   int ntile = cdiv(g.nr, T);
   dim3 grid(ntile * (ntile + 1) / 2, g.nf, g.herk_split);
   hipLaunchKernelGGL(k_herk_fp32, grid, dim3(256), 0, st, g, ghat, hpart, g.herk_split);
+  return hipGetLastError();
+}
+
+int herk_bf16_blocks(const Geometry& g) {
+  const int nb = cdiv(g.nr, kBt);
+  return nb * (nb + 1) / 2;
+}
+
+hipError_t launch_herk_split_bf16(const Geometry& g, const float2* ghat, float2* hpart,
+                                  hipStream_t st) {
+  dim3 grid(herk_bf16_blocks(g), g.herk_split, g.nf);
+  hipLaunchKernelGGL(k_herk_bf16, grid, dim3(256), 0, st, g, ghat, hpart, g.herk_split);
   return hipGetLastError();
 }
 

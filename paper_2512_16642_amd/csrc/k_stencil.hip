@@ -307,16 +307,26 @@ __global__ void __launch_bounds__(256)
     }
     __syncthreads();
     const int kend = min(kDftKs, cnt - ks);
-    for (int k = 0; k < kend; k += 4) {
-      const int tau = ks + k + krow;
-      floatx4 b = floatx4{0.f, 0.f, 0.f, 0.f};
-      if (tau < cnt) b = *reinterpret_cast<const floatx4*>(S + (size_t)tau * g.nsub_p + col);
+    // four K-steps (16 samples) of B are loaded before their MFMAs are issued
+    for (int k = 0; k < kend; k += 16) {
+      floatx4 b[4];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const float a = As[k + krow][16 * mt + (lane & 15)];
+      for (int u = 0; u < 4; ++u) {
+        const int tau = ks + k + 4 * u + krow;
+        b[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+        if (tau < cnt) b[u] = *reinterpret_cast<const floatx4*>(S + (size_t)tau * g.nsub_p + col);
+      }
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[j], acc[mt][j], 0, 0, 0);
+      for (int u = 0; u < 4; ++u) {
+        if (k + 4 * u < kend) {
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const float a = As[k + 4 * u + krow][16 * mt + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[u][j], acc[mt][j], 0, 0, 0);
+          }
+        }
       }
     }
   }
