@@ -107,6 +107,10 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
     int v = std::atoi(e);
     if (v == 1 || v == 2) g.rpt = v;
   }
+  if (const char* e = std::getenv("EHI_HERK_SPLIT")) {
+    int v = std::atoi(e);
+    if (v >= 1 && v <= ehi::kHerkSplitMax) g.herk_split = v;
+  }
   if (const char* e = std::getenv("EHI_SEG_ROWS")) {
     int v = std::atoi(e);
     if (v >= 16 && v <= 4096) g.seg_rows = v;
