@@ -94,6 +94,11 @@ __global__ void __launch_bounds__(256)
 // but is systematically positive in sum_x |g|^2, so the 16x16 tiles on the
 // diagonal of H add lo*lo for the real part.
 //
+// The MFMA's internal accumulation is biased (the error of the diagonal grows
+// linearly with the number of MFMAs chained into one accumulator), so each
+// 32-point stage is chained from zero and added to the running FP32 sum with an
+// ordinary round-to-nearest add: the bias is bounded by one stage.
+//
 // Workgroup: 4 waves, a 64 x 64 tile (i-block, j-block) of H for one frequency
 // and one grid-point partition; each wave owns a 32 x 32 quarter as 2 x 2
 // v_mfma_f32_16x16x32_bf16 tiles for Re and Im.  Per stage, 32 grid points of
@@ -181,7 +186,7 @@ __global__ void __launch_bounds__(256)
       bf16x8 nrh = -ai[a][0], nrl = -ai[a][1];
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        floatx4 r = re[a][b], m = im[a][b];
+        floatx4 r = floatx4{0.f, 0.f, 0.f, 0.f}, m = floatx4{0.f, 0.f, 0.f, 0.f};
         r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][0], aj[b][0], r, 0, 0, 0);
         r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][0], aj[b][1], r, 0, 0, 0);
         r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][1], aj[b][0], r, 0, 0, 0);
@@ -198,8 +203,8 @@ __global__ void __launch_bounds__(256)
           r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][1], aj[b][1], r, 0, 0, 0);
           r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][3], r, 0, 0, 0);
         }
-        re[a][b] = r;
-        im[a][b] = m;
+        re[a][b] += r;
+        im[a][b] += m;
       }
     }
   }
