@@ -211,6 +211,9 @@ def main():
         "kernel_ms": {k: round(v[0] / K, 3) for k, v in prof.items()},
         "gcell_updates_per_s": round(cell_updates / (prof["step"][0] / K / 1e3) / 1e9, 2),
         "herk_tflops": round(herk_flops / (herk_ms / 1e3) / 1e12, 2) if herk_ms > 0 else None,
+        "herk_mfma_bf16_tflops": (round(costs.herk_bf16_mfma_flops_per_survey(s.nr, s.nsub, s.nf)
+                                        / (herk_ms / 1e3) / 1e12, 1)
+                                  if herk_ms > 0 and args.precision == "split_bf16" else None),
         "dft_gbs": round(dft_bytes / (dft_ms / 1e3) / 1e9, 1) if dft_ms > 0 else None,
         "dft_tflops": round(dft_flops / (dft_ms / 1e3) / 1e12, 2) if dft_ms > 0 else None,
         "roofline": roof,

@@ -55,6 +55,15 @@ def herk_flops_per_survey(nz, nx, stride, nr, nf):
     return 8.0 * nr * (nr + 1) / 2 * subgrid_points(nz, nx, stride) * nf
 
 
+def herk_bf16_mfma_flops_per_survey(nr, nsub, nf, tile=64):
+    """BF16 MFMA flops the split contraction executes: 16 real products of
+    K = nsub (hi/lo x hi/lo for Re and Im) on every 64 x 64 tile on or above the
+    block diagonal."""
+    nb = -(-nr // tile)
+    pairs = nb * (nb + 1) // 2
+    return 2.0 * 16 * pairs * tile * tile * nsub * nf
+
+
 def herk_bytes_per_survey(nz, nx, stride, nr, nf):
     """Reading the complex64 spectra once."""
     return 8.0 * subgrid_points(nz, nx, stride) * nr * nf

@@ -90,9 +90,9 @@ __global__ void __launch_bounds__(256)
 // With g = a + i b, Re H = A A^T + B B^T and Im H = B A^T - A B^T (rows i, j;
 // columns = grid points).  Every FP32 value x is split as x = hi + lo + O(2^-17 x)
 // with hi = bf16(x), lo = bf16(x - hi), and a product xy is taken as
-// hi*hi + hi*lo + lo*hi.  The dropped lo*lo term averages out off the diagonal
-// but is systematically positive in sum_x |g|^2, so the 16x16 tiles on the
-// diagonal of H add lo*lo for the real part.
+// hi*hi + hi*lo + lo*hi + lo*lo.  (Without lo*lo the diagonal sum_x |g|^2 is
+// biased low by about sum lo^2 / sum x^2 ~ 1e-6, which the ill-conditioned
+// low-frequency systems amplify ~100x in the multipliers.)
 //
 // The MFMA's internal accumulation is biased (the error of the diagonal grows
 // linearly with the number of MFMAs chained into one accumulator), so each
@@ -190,19 +190,19 @@ __global__ void __launch_bounds__(256)
         r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][0], aj[b][0], r, 0, 0, 0);
         r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][0], aj[b][1], r, 0, 0, 0);
         r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][1], aj[b][0], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][1], aj[b][1], r, 0, 0, 0);
         r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][2], r, 0, 0, 0);
         r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][3], r, 0, 0, 0);
         r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][2], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][3], r, 0, 0, 0);
         m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][0], m, 0, 0, 0);
         m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][1], m, 0, 0, 0);
         m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][0], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][1], m, 0, 0, 0);
         m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrh, aj[b][2], m, 0, 0, 0);
         m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrh, aj[b][3], m, 0, 0, 0);
         m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrl, aj[b][2], m, 0, 0, 0);
-        if (bi * kBt + wi * 32 + a * 16 == bj * kBt + wj * 32 + b * 16) {
-          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][1], aj[b][1], r, 0, 0, 0);
-          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][3], r, 0, 0, 0);
-        }
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrl, aj[b][3], m, 0, 0, 0);
         re[a][b] += r;
         im[a][b] += m;
       }
