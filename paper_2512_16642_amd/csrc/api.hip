@@ -144,8 +144,8 @@ ehi::Layout make_layout(const ehi::Geometry& g) {
   L.qhat = take(sizeof(double2) * g.nf * nn);
   L.lfac = take(sizeof(double2) * g.nf * nn);
   L.lfac32 = take(sizeof(float2) * g.nf * nn);
+  L.linv = take(sizeof(float2) * (size_t)g.nf * ehi::cdiv(g.nr, 32) * 32 * 32);
   L.x64 = take(sizeof(double2) * (size_t)g.nf * g.max_ns * g.nr);
-  L.r32 = take(sizeof(float2) * (size_t)g.nf * g.max_ns * g.nr);
   L.status = take(sizeof(int32_t) * (g.nf + 4));
   L.eig = take(sizeof(double) * g.nf);
   L.total = off;
@@ -397,6 +397,7 @@ ehi_status ehi_factor(ehi_survey* s, double mu, int32_t* bad_freq) {
   } else {
     EHI_TRY(ehi::launch_potrf_f32(g, qhat, s->ptr<float2>(L.lfac32), status, st), "potrf f32");
   }
+  EHI_TRY(ehi::launch_diag_inv(g, s->ptr<float2>(L.lfac32), s->ptr<float2>(L.linv), st), "block inverses");
   PROF_END();
   std::vector<int32_t> host(g.nf);
   EHI_TRY(hipMemcpyAsync(host.data(), status, sizeof(int32_t) * g.nf, hipMemcpyDeviceToHost, st),
@@ -430,26 +431,14 @@ ehi_status ehi_apply_multipliers(ehi_survey* s, const void* resid_dev, void* mul
   float2* X = static_cast<float2*>(mult_dev);
   const float2* l32 = s->ptr<float2>(L.lfac32);
   double2* x64 = s->ptr<double2>(L.x64);
-  float2* r32 = s->ptr<float2>(L.r32);
   PROF(EHI_PROF_SOLVE, st);
+  const int refine = s->precision == EHI_PREC_SPLIT_BF16 ? 2 : 0;
   for (int s0 = 0; s0 < ns; s0 += g.max_ns) {
     const int cnt = std::min(g.max_ns, ns - s0);
-    if (s->precision == EHI_PREC_PLAIN_FP32) {
-      EHI_TRY(ehi::launch_trsm(g, l32, R, ns, s0, X, ns, s0, cnt, ehi::kTrsmWorkOnly, x64, st), "trsm");
-      PROF_N(1);
-      continue;
-    }
-    EHI_TRY(ehi::launch_trsm(g, l32, R, ns, s0, r32, g.max_ns, 0, cnt, ehi::kTrsmStoreX64, x64, st),
-            "trsm");
-    for (int it = 0; it < 2; ++it) {
-      EHI_TRY(ehi::launch_residual(g, s->ptr<double2>(L.qhat), R, ns, s0, cnt, x64, r32, st),
-              "residual");
-      EHI_TRY(ehi::launch_trsm(g, l32, r32, g.max_ns, 0, r32, g.max_ns, 0, cnt, ehi::kTrsmAddX64,
-                               x64, st),
-              "trsm refine");
-    }
-    EHI_TRY(ehi::launch_x_out(g, x64, cnt, s0, X, ns, st), "x out");
-    PROF_N(6);
+    EHI_TRY(ehi::launch_apply(g, l32, s->ptr<float2>(L.linv), s->ptr<double2>(L.qhat), R, ns, s0, cnt,
+                              refine, x64, X, st),
+            "apply");
+    PROF_N(1);
   }
   PROF_END();
   return EHI_OK;

@@ -57,8 +57,8 @@ struct Layout {
   size_t qhat;      // double2 [nf][nr][nr]   Hhat + mu I (Hermitian, full)
   size_t lfac;      // double2 [nf][nr][nr]   lower Cholesky factor (FP64 mode)
   size_t lfac32;    // float2 [nf][nr][nr]    complex64 copy (or the FP32 factor)
+  size_t linv;      // float2 [nf][nr/32][32][32] inverses of the 32 x 32 diagonal blocks
   size_t x64;       // double2 [nf][max_ns][nr] refinement accumulator
-  size_t r32;       // float2 [nf][max_ns][nr]  refinement residual
   size_t status;    // int32 [nf + 4]
   size_t eig;       // double [nf]
   size_t total;
@@ -133,23 +133,14 @@ hipError_t launch_potrf_f64(const Geometry& g, const double2* qhat, double2* lfa
                             float2* lfac32, int32_t* status, hipStream_t st);
 hipError_t launch_potrf_f32(const Geometry& g, const double2* qhat, float2* lfac32,
                             int32_t* status, hipStream_t st);
-hipError_t launch_trsm(const Geometry& g, const float2* l32, const float2* rhs, int rhs_ld,
-                       int rhs_off, float2* work, int work_ld, int work_off, int cnt, int mode,
-                       double2* x64, hipStream_t st);
-hipError_t launch_residual(const Geometry& g, const double2* qhat, const float2* resid,
-                           int resid_ns, int s0, int ns, const double2* x64, float2* r32,
-                           hipStream_t st);
-hipError_t launch_x_out(const Geometry& g, const double2* x64, int ns, int s0, float2* out,
-                        int out_ns, hipStream_t st);
+int solve_blocks(const Geometry& g);
+hipError_t launch_diag_inv(const Geometry& g, const float2* l32, float2* inv, hipStream_t st);
+hipError_t launch_apply(const Geometry& g, const float2* l32, const float2* inv,
+                        const double2* qhat, const float2* R, int rld, int s0, int cnt, int refine,
+                        double2* x64, float2* out, hipStream_t st);
 hipError_t launch_power_iter(const Geometry& g, const double2* hhat, double* eig, int iters,
                              hipStream_t st);
 hipError_t launch_c128_from_c64(const float2* in, double2* out, size_t n, hipStream_t st);
 hipError_t launch_c64_from_c128(const double2* in, float2* out, size_t n, hipStream_t st);
-
-// trsm modes: the solution stays in the work vector (complex64); StoreX64 and
-// AddX64 also write / accumulate it into the FP64 refinement accumulator.
-constexpr int kTrsmWorkOnly = 0;
-constexpr int kTrsmStoreX64 = 1;
-constexpr int kTrsmAddX64 = 2;
 
 }  // namespace ehi
