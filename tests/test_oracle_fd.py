@@ -134,3 +134,14 @@ def test_forward_operator_reproduces_green_functions():
         for i in range(op.nr):
             np.testing.assert_allclose(d[i], gt[j, :, s.rec_iz[i], s.rec_ix[i]], rtol=1e-13,
                                        atol=1e-15 * np.abs(gt).max())
+
+
+def test_c_recurrence_matches_numpy():
+    # the plain-C loops (fdcore.c) reproduce the NumPy recurrence
+    if fd._core() is None:
+        pytest.skip("oracle/_fdcore.so not built")
+    for s in (synth.ragged(nt=120), synth.tiny().with_(nt=150)):
+        v = s.velocity()
+        a = fd.green_samples(v, s.nb, s.h, s.dt, s.nt, s.rec_iz[:3], s.rec_ix[:3], s.stride)
+        b = fd.green_samples_c(v, s.nb, s.h, s.dt, s.nt, s.rec_iz[:3], s.rec_ix[:3], s.stride)
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
