@@ -136,6 +136,31 @@ ehi_status ehi_build_hessian(ehi_survey* s);
  * frequency index in *bad_freq (if non-NULL; -1 on success). */
 ehi_status ehi_factor(ehi_survey* s, double mu, int32_t* bad_freq);
 
+/* Batched factorisation of several surveys in one launch (uneven sizes and
+ * either precision form): Qhat_k(w) = Hhat_k(w) + mu[k] I and the Cholesky
+ * factor of every frequency of every survey, one workgroup per (survey,
+ * frequency).  batch_ws: device memory of ehi_batch_workspace_bytes() bytes
+ * for the job table (caller-owned, reusable once the call returns).  Work is
+ * enqueued on stream, which the caller must order after the surveys' own
+ * streams (e.g. by synchronising them); waits for the stream.  On a
+ * non-positive pivot returns EHI_ENOTPD with the first failing (survey,
+ * frequency) in *bad_survey, *bad_freq (either may be NULL); the other surveys
+ * are factored. */
+size_t ehi_batch_workspace_bytes(ehi_survey* const* surveys, int32_t n);
+ehi_status ehi_factor_batch(ehi_survey* const* surveys, int32_t n, const double* mu,
+                            void* batch_ws, size_t ws_bytes, void* stream, int32_t* bad_survey,
+                            int32_t* bad_freq);
+
+/* Routes all later work of the survey to stream (a hipStream_t; NULL = the
+ * default stream), e.g. to capture a build into a HIP graph or to run surveys
+ * concurrently. */
+ehi_status ehi_set_stream(ehi_survey* s, void* stream);
+
+/* Launch shape of the Green-function stepping: time levels per launch
+ * (4 or 8) and rows per marching segment (16..256); 0 keeps the current value.
+ * Results do not depend on them (used by the autotuner). */
+ehi_status ehi_set_launch(ehi_survey* s, int32_t tblock, int32_t seg_rows);
+
 /* X(w) = Qhat(w)^{-1} R(w) for ns sources: resid_dev and mult_dev are device
  * complex64 arrays [nf][ns][nr] (frequency-major, one row of nr receiver
  * values per source).  They may not alias.  Enqueued on stream (NULL = the

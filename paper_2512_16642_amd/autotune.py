@@ -1,0 +1,85 @@
+"""Launch-shape autotuner for the Green-function stepping.
+
+The marching kernel's rows per segment trade redundant halo rows against the
+number of workgroups; the best value depends on the grid height and on how
+many receivers are stepped together.  ``tune`` times a short build (nt_probe
+steps) for each candidate on the real grid and receivers and caches the winner
+in a JSON file keyed by (padded grid, receivers per batch, arch).  Results never
+depend on the launch shape.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from typing import Dict, Optional
+
+import torch
+
+from . import ehi
+
+CANDIDATES = (64, 96, 128, 192, 256)
+
+
+def cache_path() -> str:
+    return os.environ.get("EHI_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "ehi", "tune.json"))
+
+
+def _key(spec, nrb: int) -> str:
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "none"
+    return f"{arch}:Z{spec.nz + 2 * spec.nb}:X{spec.nx + 2 * spec.nb}:nrb{nrb}"
+
+
+def _load() -> Dict[str, dict]:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(cache: Dict[str, dict]):
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune(spec, nrb: Optional[int] = None, nt_probe: int = 64, repeats: int = 2) -> dict:
+    """Best rows-per-segment for this grid and receiver count (cached)."""
+    nrb = spec.nr if not nrb else nrb
+    key = _key(spec, nrb)
+    cache = _load()
+    if key in cache:
+        return cache[key]
+    probe = spec.with_(nt=nt_probe, rec_iz=spec.rec_iz[:nrb], rec_ix=spec.rec_ix[:nrb])
+    vel = torch.from_numpy(probe.velocity()).cuda()
+    sv = ehi.survey_from(probe, max_ns=1)
+    times = {}
+    for seg in CANDIDATES:
+        sv.set_launch(4, seg)
+        sv.build_green(vel)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(repeats):
+            sv.build_green(vel)
+        torch.cuda.synchronize()
+        times[seg] = (time.perf_counter() - t0) / repeats
+    sv.close()
+    best = min(times, key=times.get)
+    entry = {"tblock": 4, "seg_rows": best, "probe_s": {str(k): v for k, v in times.items()}}
+    cache[key] = entry
+    _store(cache)
+    return entry
+
+
+def apply(sv: "ehi.Survey", spec):
+    e = tune(spec, nrb=min(spec.nr, sv_nrb(sv, spec)))
+    sv.set_launch(e["tblock"], e["seg_rows"])
+
+
+def sv_nrb(sv, spec) -> int:
+    return getattr(sv, "nr_batch", 0) or spec.nr

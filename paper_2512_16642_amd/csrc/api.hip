@@ -113,7 +113,7 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   }
   if (const char* e = std::getenv("EHI_SEG_ROWS")) {
     int v = std::atoi(e);
-    if (v >= 16 && v <= 4096) g.seg_rows = v;
+    if (v >= 16 && v <= 256) g.seg_rows = v;
   }
   return g;
 }
@@ -148,6 +148,7 @@ ehi::Layout make_layout(const ehi::Geometry& g) {
   L.x64 = take(sizeof(double2) * (size_t)g.nf * g.max_ns * g.nr);
   L.status = take(sizeof(int32_t) * (g.nf + 4));
   L.eig = take(sizeof(double) * g.nf);
+  L.jobs = take(sizeof(ehi::FactorJob) * g.nf);
   L.total = off;
   return L;
 }
@@ -255,10 +256,10 @@ ehi_status ehi_create(const ehi_survey_desc* desc, void* workspace_dev, size_t w
 
 ehi_status ehi_destroy(ehi_survey* s) {
   if (!s) return EHI_OK;
-  s->prof.end();
+  (void)s->prof.end();
   for (auto& r : s->prof.recs) {
-    hipEventDestroy(r.start);
-    hipEventDestroy(r.stop);
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
   }
   delete s;
   return EHI_OK;
@@ -290,8 +291,8 @@ ehi_status ehi_profile_read(ehi_survey* s, double* ms, int64_t* launches) {
       ms[r.kind] += t;
       launches[r.kind] += r.launches;
     }
-    hipEventDestroy(r.start);
-    hipEventDestroy(r.stop);
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
   }
   s->prof.recs.clear();
   if (first != hipSuccess) return hip_fail(first, "profile read");
@@ -377,41 +378,122 @@ ehi_status ehi_build_hessian(ehi_survey* s) {
 }
 
 ehi_status ehi_factor(ehi_survey* s, double mu, int32_t* bad_freq) {
-  g_err.clear();
-  if (bad_freq) *bad_freq = -1;
-  if (!s) return fail(EHI_EINVAL, "survey is NULL");
-  if (s->state < ehi::State::Hessian) return fail(EHI_ESTATE, "factor before build_hessian");
-  if (!(mu > 0) || !std::isfinite(mu)) return fail(EHI_EINVAL, "mu must be positive and finite");
-  const ehi::Geometry& g = s->g;
-  const ehi::Layout& L = s->L;
-  hipStream_t st = s->stream;
-  double2* qhat = s->ptr<double2>(L.qhat);
-  int32_t* status = s->ptr<int32_t>(L.status);
-  PROF(EHI_PROF_FACTOR, st);
-  EHI_TRY(ehi::launch_penalty(g, s->ptr<double2>(L.hhat), mu, qhat, st), "penalty");
-  PROF_N(2);
-  if (s->precision == EHI_PREC_SPLIT_BF16) {
-    EHI_TRY(ehi::launch_potrf_f64(g, qhat, s->ptr<double2>(L.lfac), s->ptr<float2>(L.lfac32),
-                                  status, st),
-            "potrf f64");
-  } else {
-    EHI_TRY(ehi::launch_potrf_f32(g, qhat, s->ptr<float2>(L.lfac32), status, st), "potrf f32");
+  ehi_survey* one[1] = {s};
+  void* ws = s ? s->ws + s->L.jobs : nullptr;
+  const size_t bytes = s ? sizeof(ehi::FactorJob) * s->g.nf : 0;
+  int32_t bad_s = -1;
+  return ehi_factor_batch(one, 1, &mu, ws, bytes, s ? s->stream : nullptr, &bad_s, bad_freq);
+}
+
+size_t ehi_batch_workspace_bytes(ehi_survey* const* surveys, int32_t n) {
+  if (!surveys || n < 1) {
+    g_err = "no surveys";
+    return 0;
   }
-  EHI_TRY(ehi::launch_diag_inv(g, s->ptr<float2>(L.lfac32), s->ptr<float2>(L.linv), st), "block inverses");
+  size_t jobs = 0;
+  for (int k = 0; k < n; ++k) {
+    if (!surveys[k]) {
+      g_err = "NULL survey in the batch";
+      return 0;
+    }
+    jobs += surveys[k]->g.nf;
+  }
+  return ehi::align_up(sizeof(ehi::FactorJob) * jobs, ehi::kAlign);
+}
+
+ehi_status ehi_factor_batch(ehi_survey* const* surveys, int32_t n, const double* mu, void* batch_ws,
+                            size_t ws_bytes, void* stream, int32_t* bad_survey, int32_t* bad_freq) {
+  g_err.clear();
+  if (bad_survey) *bad_survey = -1;
+  if (bad_freq) *bad_freq = -1;
+  if (!surveys || n < 1 || !mu) return fail(EHI_EINVAL, "no surveys or no mu");
+  std::vector<ehi::FactorJob> jobs;
+  int max_nr = 0;
+  for (int k = 0; k < n; ++k) {
+    ehi_survey* s = surveys[k];
+    if (!s) return fail(EHI_EINVAL, "survey is NULL");
+    if (s->state < ehi::State::Hessian) return fail(EHI_ESTATE, "factor before build_hessian");
+    if (!(mu[k] > 0) || !std::isfinite(mu[k])) return fail(EHI_EINVAL, "mu must be positive and finite");
+    const ehi::Geometry& g = s->g;
+    const ehi::Layout& L = s->L;
+    const size_t nn = (size_t)g.nr * g.nr;
+    const size_t nblk = (size_t)ehi::cdiv(g.nr, 32) * 32 * 32;
+    for (int f = 0; f < g.nf; ++f) {
+      ehi::FactorJob j;
+      j.hhat = s->ptr<double2>(L.hhat) + f * nn;
+      j.qhat = s->ptr<double2>(L.qhat) + f * nn;
+      j.lfac = s->ptr<double2>(L.lfac) + f * nn;
+      j.l32 = s->ptr<float2>(L.lfac32) + f * nn;
+      j.linv = s->ptr<float2>(L.linv) + f * nblk;
+      j.status = s->ptr<int32_t>(L.status) + f;
+      j.mu = mu[k];
+      j.nr = g.nr;
+      j.fp64 = s->precision == EHI_PREC_SPLIT_BF16 ? 1 : 0;
+      jobs.push_back(j);
+    }
+    max_nr = std::max(max_nr, g.nr);
+  }
+  if (!batch_ws || ws_bytes < sizeof(ehi::FactorJob) * jobs.size())
+    return fail(EHI_ENOMEM, "batch workspace too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ehi_survey* s = surveys[0];
+  ehi::FactorJob* djobs = static_cast<ehi::FactorJob*>(batch_ws);
+  PROF(EHI_PROF_FACTOR, st);
+  EHI_TRY(hipMemcpyAsync(djobs, jobs.data(), sizeof(ehi::FactorJob) * jobs.size(),
+                         hipMemcpyHostToDevice, st),
+          "job table upload");
+  EHI_TRY(ehi::launch_factor_jobs(djobs, (int)jobs.size(), st), "factor");
+  EHI_TRY(ehi::launch_diag_inv_jobs(djobs, (int)jobs.size(), max_nr, st), "block inverses");
+  PROF_N(2);
   PROF_END();
-  std::vector<int32_t> host(g.nf);
-  EHI_TRY(hipMemcpyAsync(host.data(), status, sizeof(int32_t) * g.nf, hipMemcpyDeviceToHost, st),
-          "status readback");
+  // status readback (the only wait): one small copy per survey
+  std::vector<std::vector<int32_t>> host(n);
+  for (int k = 0; k < n; ++k) {
+    host[k].assign(surveys[k]->g.nf, 0);
+    EHI_TRY(hipMemcpyAsync(host[k].data(), surveys[k]->ptr<int32_t>(surveys[k]->L.status),
+                           sizeof(int32_t) * surveys[k]->g.nf, hipMemcpyDeviceToHost, st),
+            "status readback");
+  }
   EHI_TRY(hipStreamSynchronize(st), "factor sync");
-  s->state = ehi::State::Hessian;
-  for (int f = 0; f < g.nf; ++f) {
-    if (host[f] != 0) {
-      if (bad_freq) *bad_freq = f;
-      return fail(EHI_ENOTPD, "Qhat not positive definite at frequency index " + std::to_string(f));
+  ehi_status result = EHI_OK;
+  for (int k = 0; k < n; ++k) {
+    surveys[k]->state = ehi::State::Hessian;
+    bool ok = true;
+    for (int f = 0; f < surveys[k]->g.nf; ++f) {
+      if (host[k][f] != 0) {
+        if (result == EHI_OK) {
+          if (bad_survey) *bad_survey = k;
+          if (bad_freq) *bad_freq = f;
+          result = fail(EHI_ENOTPD, "Qhat not positive definite: survey " + std::to_string(k) +
+                                        ", frequency index " + std::to_string(f));
+        }
+        ok = false;
+        break;
+      }
+    }
+    if (ok) {
+      surveys[k]->mu = mu[k];
+      surveys[k]->state = ehi::State::Factored;
     }
   }
-  s->mu = mu;
-  s->state = ehi::State::Factored;
+  return result;
+}
+
+ehi_status ehi_set_stream(ehi_survey* s, void* stream) {
+  g_err.clear();
+  if (!s) return fail(EHI_EINVAL, "survey is NULL");
+  PROF_END();
+  s->stream = static_cast<hipStream_t>(stream);
+  return EHI_OK;
+}
+
+ehi_status ehi_set_launch(ehi_survey* s, int32_t tblock, int32_t seg_rows) {
+  g_err.clear();
+  if (!s) return fail(EHI_EINVAL, "survey is NULL");
+  if (tblock != 0 && tblock != 4 && tblock != 8) return fail(EHI_EINVAL, "tblock must be 0, 4 or 8");
+  if (seg_rows != 0 && (seg_rows < 16 || seg_rows > 256)) return fail(EHI_EINVAL, "seg_rows must be 0 or 16..256");
+  if (tblock) s->g.tblock = tblock;
+  if (seg_rows) s->g.seg_rows = seg_rows;
   return EHI_OK;
 }
 

@@ -61,10 +61,24 @@ struct Layout {
   size_t x64;       // double2 [nf][max_ns][nr] refinement accumulator
   size_t status;    // int32 [nf + 4]
   size_t eig;       // double [nf]
+  size_t jobs;      // FactorJob [nf]
   size_t total;
 };
 
 enum class State : int { Created = 0, Green = 1, Hessian = 2, Factored = 3 };
+
+// One (survey, frequency) factorisation: pointers into that survey's workspace.
+struct FactorJob {
+  const double2* hhat;
+  double2* qhat;
+  double2* lfac;
+  float2* l32;
+  float2* linv;
+  int32_t* status;
+  double mu;
+  int nr;
+  int fp64;
+};
 
 // Event pairs bracketing runs of launches of one kind (EHI_PROF_*).
 struct ProfRecord {
@@ -127,14 +141,9 @@ hipError_t launch_herk_split_bf16(const Geometry& g, const float2* ghat, float2*
                                   hipStream_t st);
 hipError_t launch_herk_reduce(const Geometry& g, const float2* hpart, double2* hhat,
                               hipStream_t st);
-hipError_t launch_penalty(const Geometry& g, const double2* hhat, double mu, double2* qhat,
-                          hipStream_t st);
-hipError_t launch_potrf_f64(const Geometry& g, const double2* qhat, double2* lfac,
-                            float2* lfac32, int32_t* status, hipStream_t st);
-hipError_t launch_potrf_f32(const Geometry& g, const double2* qhat, float2* lfac32,
-                            int32_t* status, hipStream_t st);
+hipError_t launch_factor_jobs(const FactorJob* jobs, int njobs, hipStream_t st);
+hipError_t launch_diag_inv_jobs(const FactorJob* jobs, int njobs, int max_nr, hipStream_t st);
 int solve_blocks(const Geometry& g);
-hipError_t launch_diag_inv(const Geometry& g, const float2* l32, float2* inv, hipStream_t st);
 hipError_t launch_apply(const Geometry& g, const float2* l32, const float2* inv,
                         const double2* qhat, const float2* R, int rld, int s0, int cnt, int refine,
                         double2* x64, float2* out, hipStream_t st);

@@ -1,4 +1,5 @@
-// Penalty and Cholesky factorisation of every frequency block.
+// Penalty and Cholesky factorisation of every frequency block (of one or many
+// surveys).
 //
 // Paper: Q = S S^T + mu I (Hessian definition); each Nr x Nr block Qhat(w) of the
 // block-diagonal frequency system is inverted and stored (frequency-domain
@@ -12,18 +13,6 @@
 
 namespace ehi {
 namespace {
-
-__global__ void k_penalty(Geometry g, const double2* __restrict__ hhat, double mu,
-                          double2* __restrict__ qhat) {
-  const int f = blockIdx.y;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= g.nr * g.nr) return;
-  int i = e / g.nr, j = e % g.nr;
-  size_t o = (size_t)f * g.nr * g.nr + e;
-  double2 v = hhat[o];
-  if (i == j) v = make_double2(v.x + mu, 0.0);
-  qhat[o] = v;
-}
 
 template <class R>
 struct cplx;
@@ -91,52 +80,40 @@ __device__ void chol_inplace(typename cplx<R>::T* A, int n, int32_t* status_f) {
   }
 }
 
-__global__ void __launch_bounds__(256)
-    k_potrf_f64(Geometry g, const double2* __restrict__ qhat, double2* __restrict__ lfac,
-                float2* __restrict__ l32, int32_t* __restrict__ status) {
-  const int f = blockIdx.x;
-  const int n = g.nr;
+// One job = one (survey, frequency): Qhat = Hhat + mu I, then the Cholesky
+// factor in FP64 (kept in lfac, with a complex64 copy in l32) or, for the plain
+// form, in FP32 directly in l32.  A workgroup per job; any mix of sizes and
+// forms in one launch (the batched-survey factorisation).
+__global__ void __launch_bounds__(256) k_factor_jobs(const FactorJob* __restrict__ jobs) {
+  const FactorJob j = jobs[blockIdx.x];
+  const int n = j.nr;
   const size_t nn = (size_t)n * n;
-  double2* A = lfac + f * nn;
-  for (size_t e = threadIdx.x; e < nn; e += blockDim.x) A[e] = qhat[f * nn + e];
+  for (size_t e = threadIdx.x; e < nn; e += blockDim.x) {
+    double2 v = j.hhat[e];
+    if (e % (n + 1) == 0) v = make_double2(v.x + j.mu, 0.0);
+    j.qhat[e] = v;
+  }
   __syncthreads();
-  chol_inplace<double>(A, n, status + f);
-  __syncthreads();
-  for (size_t e = threadIdx.x; e < nn; e += blockDim.x)
-    l32[f * nn + e] = make_float2((float)A[e].x, (float)A[e].y);
-}
-
-__global__ void __launch_bounds__(256)
-    k_potrf_f32(Geometry g, const double2* __restrict__ qhat, float2* __restrict__ l32,
-                int32_t* __restrict__ status) {
-  const int f = blockIdx.x;
-  const int n = g.nr;
-  const size_t nn = (size_t)n * n;
-  float2* A = l32 + f * nn;
-  for (size_t e = threadIdx.x; e < nn; e += blockDim.x)
-    A[e] = make_float2((float)qhat[f * nn + e].x, (float)qhat[f * nn + e].y);
-  __syncthreads();
-  chol_inplace<float>(A, n, status + f);
+  if (j.fp64) {
+    for (size_t e = threadIdx.x; e < nn; e += blockDim.x) j.lfac[e] = j.qhat[e];
+    __syncthreads();
+    chol_inplace<double>(j.lfac, n, j.status);
+    __syncthreads();
+    for (size_t e = threadIdx.x; e < nn; e += blockDim.x)
+      j.l32[e] = make_float2((float)j.lfac[e].x, (float)j.lfac[e].y);
+  } else {
+    for (size_t e = threadIdx.x; e < nn; e += blockDim.x)
+      j.l32[e] = make_float2((float)j.qhat[e].x, (float)j.qhat[e].y);
+    __syncthreads();
+    chol_inplace<float>(j.l32, n, j.status);
+  }
 }
 
 }  // namespace
 
-hipError_t launch_penalty(const Geometry& g, const double2* hhat, double mu, double2* qhat,
-                          hipStream_t st) {
-  dim3 grid(cdiv(g.nr * g.nr, 256), g.nf);
-  hipLaunchKernelGGL(k_penalty, grid, dim3(256), 0, st, g, hhat, mu, qhat);
-  return hipGetLastError();
-}
-
-hipError_t launch_potrf_f64(const Geometry& g, const double2* qhat, double2* lfac, float2* lfac32,
-                            int32_t* status, hipStream_t st) {
-  hipLaunchKernelGGL(k_potrf_f64, dim3(g.nf), dim3(256), 0, st, g, qhat, lfac, lfac32, status);
-  return hipGetLastError();
-}
-
-hipError_t launch_potrf_f32(const Geometry& g, const double2* qhat, float2* lfac32,
-                            int32_t* status, hipStream_t st) {
-  hipLaunchKernelGGL(k_potrf_f32, dim3(g.nf), dim3(256), 0, st, g, qhat, lfac32, status);
+hipError_t launch_factor_jobs(const FactorJob* jobs, int njobs, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_factor_jobs, dim3(njobs), dim3(256), 0, st, jobs);
   return hipGetLastError();
 }
 

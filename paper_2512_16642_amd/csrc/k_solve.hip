@@ -22,21 +22,22 @@ namespace {
 
 constexpr int kSb = 32;  // solve block
 
-// inv[f][I] = inverse of the diagonal block L_II of the complex64 factor,
+// inv[I] = inverse of the diagonal block L_II of a job's complex64 factor,
 // computed in FP64 (rows past nr are padded with the identity).  One thread per
-// column of the block.
-__global__ void __launch_bounds__(kSb)
-    k_diag_inv(Geometry g, const float2* __restrict__ l32, float2* __restrict__ inv) {
-  const int f = blockIdx.y, I = blockIdx.x, j = threadIdx.x;
-  const int n = g.nr;
-  const int nb = cdiv(n, kSb);
+// column of the block; grid (blocks, jobs).
+__global__ void __launch_bounds__(kSb) k_diag_inv(const FactorJob* __restrict__ jobs) {
+  const FactorJob jb = jobs[blockIdx.y];
+  const int I = blockIdx.x, j = threadIdx.x;
+  const int n = jb.nr;
+  if (I >= cdiv(n, kSb)) return;
+  const float2* l32 = jb.l32;
   __shared__ double2 Lb[kSb][kSb];
   for (int r = 0; r < kSb; ++r) {
     const int gr = I * kSb + r, gc = I * kSb + j;
     double2 v = make_double2(0.0, 0.0);
     if (gr < n && gc < n) {
       if (j <= r) {
-        const float2 x = l32[((size_t)f * n + gr) * n + gc];
+        const float2 x = l32[(size_t)gr * n + gc];
         v = make_double2(x.x, x.y);
       }
     } else if (r == j) {
@@ -57,7 +58,7 @@ __global__ void __launch_bounds__(kSb)
     const double d = Lb[r][r].x;  // real and positive
     Y[r][j] = (r < j) ? make_double2(0.0, 0.0) : make_double2(tr / d, ti / d);
   }
-  float2* out = inv + ((size_t)f * nb + I) * kSb * kSb;
+  float2* out = jb.linv + (size_t)I * kSb * kSb;
   for (int r = 0; r < kSb; ++r) out[r * kSb + j] = make_float2((float)Y[r][j].x, (float)Y[r][j].y);
 }
 
@@ -308,8 +309,9 @@ __global__ void __launch_bounds__(256)
 
 int solve_blocks(const Geometry& g) { return cdiv(g.nr, kSb); }
 
-hipError_t launch_diag_inv(const Geometry& g, const float2* l32, float2* inv, hipStream_t st) {
-  hipLaunchKernelGGL(k_diag_inv, dim3(solve_blocks(g), g.nf), dim3(kSb), 0, st, g, l32, inv);
+hipError_t launch_diag_inv_jobs(const FactorJob* jobs, int njobs, int max_nr, hipStream_t st) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_diag_inv, dim3(cdiv(max_nr, kSb), njobs), dim3(kSb), 0, st, jobs);
   return hipGetLastError();
 }
 

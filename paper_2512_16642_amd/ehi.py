@@ -30,7 +30,8 @@ SYMBOLS = (
     "ehi_workspace_bytes", "ehi_create", "ehi_build_green", "ehi_build_hessian", "ehi_factor",
     "ehi_apply_multipliers", "ehi_lambda_max", "ehi_copy_green_dft", "ehi_load_green_dft",
     "ehi_copy_hessian", "ehi_load_hessian", "ehi_copy_factor", "ehi_destroy", "ehi_last_error",
-    "ehi_version", "ehi_profile_enable", "ehi_profile_read",
+    "ehi_version", "ehi_profile_enable", "ehi_profile_read", "ehi_batch_workspace_bytes",
+    "ehi_factor_batch", "ehi_set_stream", "ehi_set_launch",
 )
 PROF_KINDS = ("setup", "step", "dft", "herk", "factor", "solve")
 _PROF_N = 8
@@ -88,6 +89,15 @@ def lib() -> ctypes.CDLL:
     L.ehi_profile_enable.restype = st
     L.ehi_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     L.ehi_profile_read.restype = st
+    L.ehi_batch_workspace_bytes.argtypes = [ctypes.POINTER(vp), i32]
+    L.ehi_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.ehi_factor_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(ctypes.c_double), vp,
+                                   ctypes.c_size_t, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.ehi_factor_batch.restype = st
+    L.ehi_set_stream.argtypes = [vp, vp]
+    L.ehi_set_stream.restype = st
+    L.ehi_set_launch.argtypes = [vp, i32, i32]
+    L.ehi_set_launch.restype = st
     L.ehi_destroy.argtypes = [vp]
     L.ehi_destroy.restype = st
     L.ehi_last_error.argtypes = []
@@ -160,6 +170,7 @@ class Survey:
         self.nxs = (nx + stride - 1) // stride
         self.precision = precision
         self.max_ns = max_ns
+        self.nr_batch = nr_batch
         d, keep = make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision,
                             max_ns, nr_batch)
         L = lib()
@@ -237,6 +248,14 @@ class Survey:
         _check(lib().ehi_copy_factor(self._h, ctypes.c_void_p(out.data_ptr())))
         return out
 
+    def set_stream(self, stream: Optional[torch.cuda.Stream]):
+        """Route this survey's later work to ``stream`` (None = the default stream)."""
+        _check(lib().ehi_set_stream(self._h, ctypes.c_void_p(0 if stream is None else stream.cuda_stream)))
+        self.stream = stream
+
+    def set_launch(self, tblock: int = 0, seg_rows: int = 0):
+        _check(lib().ehi_set_launch(self._h, int(tblock), int(seg_rows)))
+
     # -- kernel timing -------------------------------------------------------------
     def profile(self, enable: bool = True):
         _check(lib().ehi_profile_enable(self._h, 1 if enable else 0))
@@ -267,6 +286,34 @@ class Survey:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def factor_batch(surveys: Sequence["Survey"], mu: Sequence[float],
+                 stream: Optional[torch.cuda.Stream] = None):
+    """Factor several surveys in one launch (uneven sizes).  The surveys'
+    streams are synchronised first.  Raises EhiError (with .bad_survey and
+    .bad_freq) on a non-positive pivot."""
+    if len(surveys) != len(mu) or not surveys:
+        raise ValueError("one mu per survey")
+    L = lib()
+    for sv in surveys:
+        torch.cuda.synchronize(sv.device)
+    handles = (ctypes.c_void_p * len(surveys))(*[sv._h.value for sv in surveys])
+    nbytes = L.ehi_batch_workspace_bytes(handles, len(surveys))
+    if nbytes == 0:
+        raise EhiError(EHI_EINVAL, L.ehi_last_error().decode())
+    dev = surveys[0].device
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    ptr = ws.data_ptr() + (-ws.data_ptr()) % 256
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    mus = (ctypes.c_double * len(mu))(*[float(m) for m in mu])
+    bs, bf = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    rc = L.ehi_factor_batch(handles, len(surveys), mus, ctypes.c_void_p(ptr), ctypes.c_size_t(nbytes),
+                            ctypes.c_void_p(st.cuda_stream), ctypes.byref(bs), ctypes.byref(bf))
+    if rc != EHI_OK:
+        err = EhiError(rc, L.ehi_last_error().decode(), bf.value)
+        err.bad_survey = bs.value
+        raise err
 
 
 def survey_from(spec, precision="split_bf16", max_ns=None, nr_batch=0, **kw) -> Survey:
