@@ -76,11 +76,19 @@ class SurveyBatch:
         return [sv.lambda_max() for sv in self.surveys]
 
     def apply(self, resids: Sequence[torch.Tensor], outs: Optional[Sequence[torch.Tensor]] = None):
-        outs = [None] * len(resids) if outs is None else outs
-        res = []
+        """Deblur every survey's residuals on its own stream; ordered after the
+        current stream (where the inputs were produced) and joined back to it."""
+        cur = torch.cuda.current_stream(self.device)
+        outs = [torch.empty_like(r) for r in resids] if outs is None else list(outs)
+        for st in self.streams:
+            st.wait_stream(cur)
         for sv, st, r, o in zip(self.surveys, self.streams, resids, outs):
-            res.append(sv.apply_multipliers(r, out=o, stream=st))
-        return res
+            sv.apply_multipliers(r, out=o, stream=st)
+            r.record_stream(st)
+            o.record_stream(st)
+        for st in self.streams:
+            cur.wait_stream(st)
+        return outs
 
     def close(self):
         torch.cuda.synchronize(self.device)
