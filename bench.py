@@ -33,7 +33,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="layered_1000x300")
+    ap.add_argument("--workload", default="layered_1000x300",
+                    help="layered_1000x300 (default), tiny, or batch8 (the eight uneven surveys)")
+    ap.add_argument("--batch-nt", type=int, default=4000, help="time steps of the batch8 surveys")
     ap.add_argument("--precision", default="split_bf16", choices=["split_bf16", "plain_fp32"])
     ap.add_argument("--nr-batch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -91,8 +93,84 @@ def cpu_baseline(s, fd_steps):
     }
 
 
+def run_batch(args):
+    """Eight uneven layered surveys: graph-captured builds on per-survey streams,
+    one batched factorisation launch, per-survey deblurs of all their sources."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2512_16642_amd import batch, costs
+
+    specs = synth.batch_surveys(nt=args.batch_nt)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    vels = [torch.from_numpy(s.velocity()).to(dev) for s in specs]
+    Rs = [torch.from_numpy(s.residuals()).to(dev) for s in specs]
+    b = batch.SurveyBatch(specs, precision=args.precision, tune=True)
+    print(f"# batch8: workspaces {b.workspace_bytes / 1e9:.1f} GB, launch shapes tuned", file=sys.stderr,
+          flush=True)
+    b.build(vels, graph=True)
+    mu = [1e-3 * l for l in b.lambda_max()]
+    for _ in range(args.warmup):
+        b.build(vels, graph=True)
+        b.factor(mu)
+        b.apply(Rs)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    tb = tf = ta = 0.0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record(stream)
+        b.build(vels, graph=True)
+        e[1].record(stream)
+        b.factor(mu)            # one launch; waits for its status
+        e[2].record(stream)
+        b.apply(Rs)
+        e[3].record(stream)
+        e[3].synchronize()
+        tb += e[0].elapsed_time(e[1])
+        tf += e[1].elapsed_time(e[2])
+        ta += e[2].elapsed_time(e[3])
+        print(f"# batch step {k} done", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    K = args.steps
+    solves = sum(s.nf * s.ns for s in specs)
+    cells = sum(costs.stencil_cell_updates_per_survey(s.nz, s.nx, s.nb, s.nr, s.nt) for s in specs)
+    out = {
+        "metric": "batched uneven surveys: build+factor s per 8-survey batch; multiplier solves/s",
+        "value": round((tb + tf) / K / 1e3, 4),
+        "unit": "s/batch",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / K * 1e3, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batch8-layered-uneven", "precision": args.precision, "nt": args.batch_nt,
+                   "surveys": [s.name for s in specs]},
+        "stage_ms": {"build_graph": round(tb / K, 2), "factor_batched": round(tf / K, 3),
+                     "apply": round(ta / K, 3)},
+        "surveys_per_s": round(len(specs) / ((tb + tf) / K / 1e3), 3),
+        "solves_per_s": round(solves / (ta / K / 1e3), 1),
+        "gcell_updates_per_s": round(cells / (tb / K / 1e3) / 1e9, 1),
+    }
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "batch8":
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        run_batch(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
               "described in DESIGN.md and not benchmarked", file=sys.stderr)
