@@ -34,9 +34,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="layered_1000x300",
-                    help="layered_1000x300 (default), tiny, or batch8 (the eight uneven surveys)")
+                    help="layered_1000x300 (default), tiny, batch8 (the eight uneven surveys) or serve "
+                         "(Poisson request mix over the eight surveys)")
     ap.add_argument("--batch-nt", type=int, default=4000, help="time steps of the batch8 surveys")
     ap.add_argument("--precision", default="split_bf16", choices=["split_bf16", "plain_fp32"])
+    ap.add_argument("--rate", type=float, default=20.0, help="serve: mean arrivals per second")
+    ap.add_argument("--p-build", type=float, default=0.02, help="serve: probability a request is a build")
+    ap.add_argument("--duration", type=float, default=120.0, help="serve: seconds of arrivals")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: HBM budget")
+    ap.add_argument("--build-slots", type=int, default=2, help="serve: concurrent builds")
     ap.add_argument("--nr-batch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=300, help="FD steps in the CPU sample")
@@ -163,13 +169,76 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_serve(args):
+    """Serving mix: Poisson arrivals (mean args.rate req/s, rng 2400) of rebuilds
+    of the eight uneven surveys (probability args.p_build) and deblurs of
+    U{1..256} sources x all frequencies against resident factors, all eight
+    surveys resident at the start, HBM budget args.budget_gb."""
+    import torch
+
+    import synth
+    from paper_2512_16642_amd import serve
+
+    specs = synth.batch_surveys(nt=args.batch_nt)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    eng = serve.EhiEngine(specs, build_slots=args.build_slots, precision=args.precision, tune=True)
+    srv = serve.Server(eng, budget_bytes=int(args.budget_gb * 1e9), build_slots=args.build_slots)
+    t0 = time.perf_counter()
+    srv.preload(range(len(specs)))
+    print(f"# serve: {len(specs)} surveys resident in {time.perf_counter() - t0:.1f} s, "
+          f"{srv.adm.used / 1e9:.1f} GB of {args.budget_gb:.0f} GB", file=sys.stderr, flush=True)
+    # warm the deblur path of every survey (first-launch costs)
+    warm = [serve.Request(-1 - k, "deblur", 0.0, k, ns=8, seed=k) for k in range(len(specs))]
+    srv.run(warm)
+    reqs = serve.poisson_requests(args.duration, args.rate, args.p_build, len(specs), ns_max=256, seed=2400)
+    print(f"# serve: {len(reqs)} requests over {args.duration:.0f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    def report(t):
+        done = sum(1 for r in reqs if r.status != "pending")
+        print(f"# serve t={t:.0f}s: {done}/{len(reqs)} finished, {srv.adm.used / 1e9:.1f} GB held",
+              file=sys.stderr, flush=True)
+
+    srv.run(reqs, progress=report)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = serve.latency_stats(reqs)
+    solves = sum(specs[r.key].nf * r.ns for r in reqs if r.kind == "deblur" and r.status == "done")
+    builds = sum(1 for r in reqs if r.kind == "build" and r.status == "done")
+    out = {
+        "metric": "serving mix: multiplier solves/s with p50/p99 latency",
+        "value": round(solves / wall, 1),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": len(warm),
+        "ms_per_step": round(wall / max(1, len(reqs)) * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serve-poisson-batch8", "rate_hz": args.rate, "p_build": args.p_build,
+                   "duration_s": args.duration, "budget_gb": args.budget_gb,
+                   "build_slots": args.build_slots, "precision": args.precision, "nt": args.batch_nt},
+        "latency": st,
+        "builds_per_s": round(builds / wall, 3),
+        "wall_s": round(wall, 2),
+        "hbm_peak_gb": round(srv.adm.peak / 1e9, 1),
+        "evictions": srv.evictions,
+    }
+    srv.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
-    if args.workload == "batch8":
+    if args.workload in ("batch8", "serve"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        run_batch(args)
+        (run_batch if args.workload == "batch8" else run_serve)(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "

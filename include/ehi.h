@@ -215,7 +215,9 @@ ehi_status ehi_profile_enable(ehi_survey* s, int enable);
  * launches[EHI_PROF_KINDS] (both zeroed first), then releases the events. */
 ehi_status ehi_profile_read(ehi_survey* s, double* ms, int64_t* launches);
 
-/* Releases the handle (not the workspace).  NULL is accepted. */
+/* Releases the handle (not the workspace) without waiting for the device:
+ * the caller ensures no enqueued work still uses the survey before it frees
+ * or reuses the workspace.  NULL is accepted. */
 ehi_status ehi_destroy(ehi_survey* s);
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -329,13 +329,10 @@ hipError_t launch_apply(const Geometry& g, const float2* l32, const float2* inv,
   if (npad <= 224) EHI_APPLY(32)
   else if (npad <= 448) EHI_APPLY(16)
   else {
-    static bool attr_set = false;
-    if (!attr_set) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply<8>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
-      if (e != hipSuccess) return e;
-      attr_set = true;
-    }
+    // once per process (thread-safe static initialisation)
+    static const hipError_t attr = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&k_apply<8>), hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    if (attr != hipSuccess) return attr;
     EHI_APPLY(8)
   }
 #undef EHI_APPLY

@@ -267,11 +267,15 @@ class Survey:
         _check(lib().ehi_profile_read(self._h, ms, nl))
         return {k: (float(ms[i]), int(nl[i])) for i, k in enumerate(PROF_KINDS)}
 
-    def close(self):
+    def close(self, sync: bool = True):
+        """Release the handle and the workspace.  With ``sync=False`` the caller
+        guarantees that no enqueued work still reads or writes the survey."""
         if self._h is not None:
-            torch.cuda.synchronize(self.device)
+            if sync:
+                torch.cuda.synchronize(self.device)
             lib().ehi_destroy(self._h)
             self._h = None
+            self._ws = None
 
     def __del__(self):
         try:

@@ -164,6 +164,22 @@ def residuals(nf: int, ns: int, nr: int, seed: int) -> np.ndarray:
     return ((re + 1j * im) / math.sqrt(2.0)).astype(np.complex64)
 
 
+def residuals_device(nf: int, ns: int, nr: int, seed: int, device) -> "torch.Tensor":
+    """Residuals ``[nf][ns][nr]`` complex64 drawn on the device (for request
+    streams, where a host draw per request would stall the scheduler).
+
+    torch's device generator seeded with ``seed``: real parts then imaginary
+    parts, each N(0, 1/2).  A different stream of numbers from ``residuals``
+    for the same seed; the same seed always gives the same tensor.
+    """
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    z = torch.randn((2, nf, ns, nr), generator=g, device=device, dtype=torch.float32)
+    z.mul_(math.sqrt(0.5))
+    return torch.complex(z[0], z[1])
+
+
 # ---------------------------------------------------------------------------
 # the workloads
 # ---------------------------------------------------------------------------
