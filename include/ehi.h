@@ -161,6 +161,9 @@ ehi_status ehi_set_stream(ehi_survey* s, void* stream);
  * Results do not depend on them (used by the autotuner). */
 ehi_status ehi_set_launch(ehi_survey* s, int32_t tblock, int32_t seg_rows);
 
+/* The current launch shape (host outputs; either pointer may be NULL). */
+ehi_status ehi_get_launch(const ehi_survey* s, int32_t* tblock, int32_t* seg_rows);
+
 /* X(w) = Qhat(w)^{-1} R(w) for ns sources: resid_dev and mult_dev are device
  * complex64 arrays [nf][ns][nr] (frequency-major, one row of nr receiver
  * values per source).  They may not alias.  Enqueued on stream (NULL = the

@@ -1,10 +1,11 @@
 """Launch-shape autotuner for the Green-function stepping.
 
-The marching kernel's rows per segment trade redundant halo rows against the
-number of workgroups; the best value depends on the grid height and on how
-many receivers are stepped together.  ``tune`` times a short build (nt_probe
-steps) for each candidate on the real grid and receivers and caches the winner
-in a JSON file keyed by (padded grid, receivers per batch, arch).  Results never
+The marching kernel's time levels per launch trade HBM traffic against
+redundant halo work, and its rows per segment trade redundant halo rows against
+the number of workgroups; the best pair depends on the grid and on how many
+receivers are stepped together.  ``tune`` times a short build (nt_probe steps)
+for each candidate pair on the real grid and receivers and caches the winner in
+a JSON file keyed by (padded grid, receivers per batch, arch).  Results never
 depend on the launch shape.
 """
 from __future__ import annotations
@@ -18,7 +19,8 @@ import torch
 
 from . import ehi
 
-CANDIDATES = (64, 96, 128, 192, 256)
+TBLOCKS = (4, 8)
+SEG_ROWS = (64, 96, 128, 192, 256)
 
 
 def cache_path() -> str:
@@ -28,7 +30,7 @@ def cache_path() -> str:
 
 def _key(spec, nrb: int) -> str:
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "none"
-    return f"{arch}:Z{spec.nz + 2 * spec.nb}:X{spec.nx + 2 * spec.nb}:nrb{nrb}"
+    return f"{arch}:Z{spec.nz + 2 * spec.nb}:X{spec.nx + 2 * spec.nb}:nrb{nrb}:v2"
 
 
 def _load() -> Dict[str, dict]:
@@ -59,18 +61,20 @@ def tune(spec, nrb: Optional[int] = None, nt_probe: int = 64, repeats: int = 2) 
     vel = torch.from_numpy(probe.velocity()).cuda()
     sv = ehi.survey_from(probe, max_ns=1)
     times = {}
-    for seg in CANDIDATES:
-        sv.set_launch(4, seg)
-        sv.build_green(vel)  # warm
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(repeats):
-            sv.build_green(vel)
-        torch.cuda.synchronize()
-        times[seg] = (time.perf_counter() - t0) / repeats
+    for tb in TBLOCKS:
+        for seg in SEG_ROWS:
+            sv.set_launch(tb, seg)
+            sv.build_green(vel)  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(repeats):
+                sv.build_green(vel)
+            torch.cuda.synchronize()
+            times[(tb, seg)] = (time.perf_counter() - t0) / repeats
     sv.close()
     best = min(times, key=times.get)
-    entry = {"tblock": 4, "seg_rows": best, "probe_s": {str(k): v for k, v in times.items()}}
+    entry = {"tblock": best[0], "seg_rows": best[1],
+             "probe_s": {f"{k[0]}x{k[1]}": v for k, v in times.items()}}
     cache[key] = entry
     _store(cache)
     return entry

@@ -95,17 +95,17 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   int want = ehi::cdiv(2048, pairs * g.nf);
   int kmax = std::max(1, g.nsub / 1024);
   g.herk_split = std::max(1, std::min(want, std::min(ehi::kHerkSplitMax, kmax)));
-  g.tblock = 4;
+  g.tblock = 8;
   g.seg_rows = 128;
-  g.rpt = 2;
+  g.prefetch = 2;
   // tuning overrides (launch shapes only; results do not depend on them)
   if (const char* e = std::getenv("EHI_TBLOCK")) {
     int v = std::atoi(e);
     if (v == 4 || v == 8) g.tblock = v;
   }
-  if (const char* e = std::getenv("EHI_RPT")) {
+  if (const char* e = std::getenv("EHI_PREFETCH")) {
     int v = std::atoi(e);
-    if (v == 1 || v == 2) g.rpt = v;
+    if (v == 1 || v == 2) g.prefetch = v;
   }
   if (const char* e = std::getenv("EHI_HERK_SPLIT")) {
     int v = std::atoi(e);
@@ -494,6 +494,14 @@ ehi_status ehi_set_launch(ehi_survey* s, int32_t tblock, int32_t seg_rows) {
   if (seg_rows != 0 && (seg_rows < 16 || seg_rows > 256)) return fail(EHI_EINVAL, "seg_rows must be 0 or 16..256");
   if (tblock) s->g.tblock = tblock;
   if (seg_rows) s->g.seg_rows = seg_rows;
+  return EHI_OK;
+}
+
+ehi_status ehi_get_launch(const ehi_survey* s, int32_t* tblock, int32_t* seg_rows) {
+  g_err.clear();
+  if (!s) return fail(EHI_EINVAL, "survey is NULL");
+  if (tblock) *tblock = s->g.tblock;
+  if (seg_rows) *seg_rows = s->g.seg_rows;
   return EHI_OK;
 }
 

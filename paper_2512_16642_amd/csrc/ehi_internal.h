@@ -35,7 +35,7 @@ struct Geometry {
   int herk_split;  // split-K partitions
   int tblock;      // time levels per marching launch (2, 4 or 8; divides chunk)
   int seg_rows;    // output rows per marching segment
-  int rpt;         // receivers per thread in the marching kernel (1 or 2)
+  int prefetch;    // marching iterations between a row's load and its use (1 or 2)
   double h, dt;
   __host__ __device__ size_t plane() const { return (size_t)Zp * Xp; }
 };

@@ -47,13 +47,21 @@ constexpr int kBand = 256;  // columns per workgroup (one per thread)
 // 2i - 2t + 1.  Level t needs level t-1 rows rho-2..rho+2 (its own column,
 // registers) and the x-neighbours of level t-1 rows 2i - 2t, 2i - 2t + 1, which
 // were produced in iteration i-1 and are published in LDS before the barrier.
-// Per level, rows live in 6-slot register rings (slot = rho mod 6); ca rows in
-// an LDS ring of 2T + 4 rows.  The iteration loop is unrolled by 6 so every
-// register ring slot and the LDS buffer index are compile-time constants.
-// Row properties (inside the grid, owned by the segment, distance into the
-// absorbing layer, staging offset) are tabulated once per workgroup in LDS,
-// so the unrolled body carries almost no scalar control.
+// Per level, u and w rows live in 6-slot register rings (slot = rho mod 6) and
+// the ca rows in a register ring of CRR >= 2T + 2 rows (slot = rho mod CRR).
+// The iteration loop is unrolled by UNR, a multiple of every ring's period in
+// iterations, so ring slots, prefetch sets and the LDS buffer index are
+// compile-time constants.
+//
+// LDS holds the rows published for the x-neighbours column-major: entry
+// (column, buffer, level, row of pair) at column * LS + (buffer * T + level) * 2
+// + row.  A lane reads columns c-2..c+2 at fixed offsets from one base, and the
+// odd column stride LS keeps the 32 lanes of a half-wave on distinct banks.
+// Row properties (staging and output offsets, the absorbing-layer factor) are
+// tabulated once per workgroup in LDS, so the unrolled body carries almost no
+// scalar control.
 constexpr int kMaxSegRows = 256;
+constexpr unsigned kDrop = 0x80000000u;  // store offset the buffer unit discards
 
 // Raw buffer access: the row offset is a scalar (soffset), the column offset a
 // per-lane constant (voffset); bounds are the plane the resource describes.
@@ -67,33 +75,53 @@ __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, int vo
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
 }
 
-template <int T, bool FULL>
-struct March2 {
-  static constexpr int B = kBand - 4 * T;  // output columns per band
-  static constexpr int W = kBand + 4;      // LDS row incl. two zero columns per side
+constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+constexpr int lcm_c(int a, int b) { return a / gcd_c(a, b) * b; }
+
+template <int T, bool FULL, int PD>
+struct March3 {
+  static constexpr int CRR = T == 4 ? 12 : 24;          // ca ring rows (>= 2T + 2, even)
+  // iterations per unrolled body: a multiple of the u/w ring (3 iterations), the
+  // ca ring (CRR / 2) and the LDS double buffer (2)
+  static constexpr int UNR = lcm_c(6, CRR / 2);
+  static constexpr int SETS = PD + 1;                    // prefetch sets (rows of i + PD load during i)
+  static_assert(CRR >= 2 * T + 2 && CRR % 2 == 0, "ca ring too short");
+  static_assert(UNR % SETS == 0 && UNR % 2 == 0, "the unrolled body cycles sets and buffers");
+  static constexpr int B = kBand - 4 * T;   // output columns per band
+  static constexpr int W = kBand + 4;       // columns in LDS incl. two zero columns per side
+  static constexpr int LS = 4 * T + 1;      // LDS column stride (words)
   static constexpr int NRT = kMaxSegRows + 6 * T + 8;  // row-table entries (index rho + 2T)
 
-  static constexpr int CR = 2 * T + 4;  // ca ring rows: 2T + 2 in use + one iteration of slack
-
-  struct Shared {
-    float lu[2][T][2][W];  // [buffer][level feeding level+1][row of the pair][column]
-    float lc[CR][kBand];   // ca ring, slot = rho mod CR
-    float lb[kMaxSponge + 1];
-    int rdz[NRT];    // distance of the row into the top/bottom layer (0 outside the grid)
-    int rown[NRT];   // byte offset of the row in a plane if the segment owns it, else -1
-    int rsub[NRT];   // byte offset of the row's subgrid line in a staging slot, else -1
+  // Row table entry: bz = bd[distance of the row into the top/bottom layer]
+  // (1 outside the grid), own = byte offset of the row in a plane if the
+  // segment owns it else -1, sub = byte offset of the row's subgrid line in a
+  // staging slot else -1.  One broadcast LDS read per (level, row).
+  struct alignas(16) RowEntry {
+    float bz;
+    int own, sub, pad;
   };
 
-  float U[T][6];   // level-t rows, slot = rho mod 6
-  float Wr[T][6];  // level-t w
-  float pu[2][2], pw[2][2], pc[2][2];  // prefetch sets [set][row of pair]
+  struct Shared {
+    float lu[W * LS];
+    RowEntry rt[NRT];
+  };
+
+  float U[T][6];    // level-t rows, slot = rho mod 6
+  float Wr[T][6];   // level-t w
+  float C[CRR];     // ca rows, slot = rho mod CRR
+  float pu[SETS][2], pw[SETS][2], pc[SETS][2];  // prefetch sets [set][row of pair]
 
   struct Ctx {
     __amdgpu_buffer_rsrc_t ru, rw, rc, rou, row_, rst;
     int voff;   // byte offset of this lane's column in a plane row (ghost column if outside)
-    int vsub;   // byte offset of this lane's subgrid column in a staging line
-    int tid, kb, Z, Pb, nlev, dxs, slot_bytes;
-    bool own, lane_stg;
+    // Per-lane store offsets: this lane's column in an output plane row and its
+    // subgrid column in a staging line, or kDrop on lanes that must not store.
+    // The buffer unit discards a store whose offset lies beyond the buffer; the
+    // row part (scalar offset) is < 2^31 since planes and staging blocks are
+    // limited to 2 GiB, so kDrop plus it never wraps back into range.
+    unsigned vown, vsub;
+    int tid, kb, Z, Pb, nlev, slot_bytes;
+    float bx;   // bd[distance of the column into the left/right layer]
   };
 
   // rows outside the grid read the zero ghost row next to the edge
@@ -111,45 +139,50 @@ struct March2 {
     }
   }
 
-  template <int PH>  // PH = i mod 6
-  __device__ __forceinline__ void iter(Shared& sh, const Ctx& x, int i, int cb) {
-    // cb = (2i) mod CR: ca ring slot of row 2i
+  static __device__ __forceinline__ constexpr int mod(int a, int m) { return ((a % m) + m) % m; }
+
+  template <int PH>  // PH = i mod UNR
+  __device__ __forceinline__ void iter(Shared& sh, const Ctx& x, int i) {
     constexpr int BUF = PH & 1;
-    constexpr int S0 = (2 * PH) % 6;   // ring slot of row 2i
-    constexpr int SET = PH & 1;
+    constexpr int S0 = mod(2 * PH, 6);     // u/w ring slot of row 2i
+    constexpr int C0 = mod(2 * PH, CRR);   // ca ring slot of row 2i
+    constexpr int SET = PH % SETS;
     U[0][S0] = pu[SET][0];
     U[0][S0 + 1] = pu[SET][1];
     Wr[0][S0] = pw[SET][0];
     Wr[0][S0 + 1] = pw[SET][1];
-    sh.lc[cb][x.tid] = pc[SET][0];
-    sh.lc[cb + 1][x.tid] = pc[SET][1];
-    load_pair(x, 2 * i + 2, SET ^ 1);
+    C[C0] = pc[SET][0];
+    C[C0 + 1] = pc[SET][1];
+    load_pair(x, 2 * (i + PD), (PH + PD) % SETS);
+    float* col = sh.lu + x.tid * LS;  // column c - 2 of this lane; own column at + 2 LS
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
-      for (int h = 0; h < 2; ++h) sh.lu[BUF][t][h][x.tid + 2] = U[t][((2 * PH - 2 * (t + 1) + h) % 6 + 6) % 6];
+      for (int h = 0; h < 2; ++h) col[2 * LS + (BUF * T + t) * 2 + h] = U[t][mod(2 * PH - 2 * (t + 1) + h, 6)];
     __syncthreads();
 #pragma unroll
     for (int t = 1; t <= T; ++t) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const int sl = ((2 * PH - 2 * t + h) % 6 + 6) % 6;  // slot of row rho = 2i - 2t + h
+        const int sl = mod(2 * PH - 2 * t + h, 6);  // slot of row rho = 2i - 2t + h
         const int sm2 = (sl + 4) % 6, sm1 = (sl + 5) % 6, sp1 = (sl + 1) % 6, sp2 = (sl + 2) % 6;
-        int cs = cb - 2 * t + h;  // ca ring slot of row rho
-        if (cs < 0) cs += CR;
+        const int cs = mod(2 * PH - 2 * t + h, CRR);
         const int ti = 2 * i - 2 * t + h + 2 * T;  // row-table index
+        const RowEntry re = sh.rt[ti];
         const float cen = U[t - 1][sl];
         float un, wn;
         if (FULL || t <= x.nlev) {
-          const float* L = sh.lu[BUF][t - 1][h];
-          const float n1 = (L[x.tid + 1] + L[x.tid + 3]) + (U[t - 1][sm1] + U[t - 1][sp1]);
-          const float n2 = (L[x.tid] + L[x.tid + 4]) + (U[t - 1][sm2] + U[t - 1][sp2]);
+          const int e = (BUF * T + t - 1) * 2 + h;
+          const float n1 = (col[LS + e] + col[3 * LS + e]) + (U[t - 1][sm1] + U[t - 1][sp1]);
+          const float n2 = (col[e] + col[4 * LS + e]) + (U[t - 1][sm2] + U[t - 1][sp2]);
           const float lap = 16.f * n1 - n2 - 60.f * cen;
-          const float bq = sh.lb[max(sh.rdz[ti], x.dxs)];
-          wn = bq * Wr[t - 1][sl] + sh.lc[cs][x.tid] * lap;
+          // bd is non-increasing in the distance, so bd[max(dz, dx)] = min(bd[dz], bd[dx]);
+          // both are positive floats, whose bit patterns order like the integers
+          const float bq = __int_as_float(min(__float_as_int(re.bz), __float_as_int(x.bx)));
+          wn = bq * Wr[t - 1][sl] + C[cs] * lap;
           un = cen + wn;
-          const int rs = __builtin_amdgcn_readfirstlane(sh.rsub[ti]);
-          if (rs >= 0 && x.lane_stg) bstore(un, x.rst, x.vsub, (t - 1) * x.slot_bytes + rs);
+          const int rs = __builtin_amdgcn_readfirstlane(re.sub);
+          if (rs >= 0) bstore(un, x.rst, (int)x.vsub, (t - 1) * x.slot_bytes + rs);
         } else {
           un = cen;
           wn = Wr[t - 1][sl];
@@ -158,23 +191,33 @@ struct March2 {
           U[t][sl] = un;
           Wr[t][sl] = wn;
         } else {
-          const int ro = __builtin_amdgcn_readfirstlane(sh.rown[ti]);
-          if (ro >= 0 && x.own) {
-            bstore(un, x.rou, x.voff, ro);
-            bstore(wn, x.row_, x.voff, ro);
+          const int ro = __builtin_amdgcn_readfirstlane(re.own);
+          if (ro >= 0) {
+            bstore(un, x.rou, (int)x.vown, ro);
+            bstore(wn, x.row_, (int)x.vown, ro);
           }
         }
       }
     }
   }
+
+  template <int PH>
+  __device__ __forceinline__ bool body(Shared& sh, const Ctx& x, int i, int n_it) {
+    if constexpr (PH < UNR) {
+      if (i + PH >= n_it) return false;
+      iter<PH>(sh, x, i + PH);
+      return body<PH + 1>(sh, x, i, n_it);
+    }
+    return true;
+  }
 };
 
-template <int T, bool FULL>
+template <int T, bool FULL, int PD>
 __global__ void __launch_bounds__(kBand)
     k_march(Geometry g, const float* __restrict__ ca, const float* __restrict__ bd,
             const float* __restrict__ uin, const float* __restrict__ win, float* __restrict__ uout,
             float* __restrict__ wout, float* __restrict__ stage, int slot0, int nlev) {
-  using M = March2<T, FULL>;
+  using M = March3<T, FULL, PD>;
   __shared__ typename M::Shared sh;
   typename M::Ctx x;
   x.tid = threadIdx.x;
@@ -183,7 +226,7 @@ __global__ void __launch_bounds__(kBand)
   const int r = blockIdx.x;
   const int c = blockIdx.y * M::B - 2 * T + x.tid;  // padded-grid column
   const bool colv = (c >= 0 && c < g.X);
-  x.own = (x.tid >= 2 * T && x.tid < kBand - 2 * T && colv);
+  const bool own = (x.tid >= 2 * T && x.tid < kBand - 2 * T && colv);
   x.Z = g.Z;
   x.Pb = g.Xp * 4;
   const int z0 = blockIdx.z * g.seg_rows;
@@ -205,31 +248,28 @@ __global__ void __launch_bounds__(kBand)
   x.voff = (min(max(c, -kGhost), g.X + kGhost - 1) + kGhost) * 4;
   const int jx = c - g.nb;
   const bool subx = jx >= 0 && jx < g.nx && (jx & (g.stride - 1)) == 0;
-  x.lane_stg = x.own && subx;
-  x.vsub = subx ? (jx >> g.sshift) * 4 : 0;
-  x.dxs = colv ? max(max(g.nb - c, c - (g.nb + g.nx - 1)), 0) : 0;
+  x.vown = own ? (unsigned)x.voff : kDrop;
+  x.vsub = (own && subx) ? (unsigned)((jx >> g.sshift) * 4) : kDrop;
+  x.bx = bd[colv ? max(max(g.nb - c, c - (g.nb + g.nx - 1)), 0) : 0];
 
-  if (x.tid < 2) {
+  // the two zero columns on each side of the band
+  if (x.tid < 4) {
+    const int zc = x.tid < 2 ? x.tid : kBand + x.tid;
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int t = 0; t < T; ++t)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          sh.lu[b][t][h][x.tid] = 0.f;
-          sh.lu[b][t][h][kBand + 2 + x.tid] = 0.f;
-        }
+    for (int e = 0; e < 4 * T; ++e) sh.lu[zc * M::LS + e] = 0.f;
   }
-  for (int i = x.tid; i <= g.nb; i += kBand) sh.lb[i] = bd[i];
   for (int ti = x.tid; ti < M::NRT; ti += kBand) {
     const int q = x.kb + ti - 2 * T;
     const bool inside = q >= 0 && q < g.Z;
-    sh.rdz[ti] = inside ? max(max(g.nb - q, q - (g.nb + g.nz - 1)), 0) : 0;
+    typename M::RowEntry e;
+    e.bz = bd[inside ? max(max(g.nb - q, q - (g.nb + g.nz - 1)), 0) : 0];
     const bool owned = q >= z0 && q < z1;
-    sh.rown[ti] = owned ? (q + kGhost) * x.Pb : -1;
+    e.own = owned ? (q + kGhost) * x.Pb : -1;
     const int jz = q - g.nb;
     const bool subz = owned && jz >= 0 && jz < g.nz && (jz & (g.stride - 1)) == 0;
-    sh.rsub[ti] = subz ? (slot0 * g.nsub_p + (jz >> g.sshift) * g.nxs) * 4 : -1;
+    e.sub = subz ? (slot0 * g.nsub_p + (jz >> g.sshift) * g.nxs) * 4 : -1;
+    e.pad = 0;
+    sh.rt[ti] = e;
   }
 
   M m;
@@ -237,30 +277,13 @@ __global__ void __launch_bounds__(kBand)
   for (int t = 0; t < T; ++t)
 #pragma unroll
     for (int s2 = 0; s2 < 6; ++s2) m.U[t][s2] = m.Wr[t][s2] = 0.f;
-  for (int s2 = 0; s2 < M::CR; ++s2) sh.lc[s2][x.tid] = 0.f;
-  m.load_pair(x, 0, 0);
+#pragma unroll
+  for (int s2 = 0; s2 < M::CRR; ++s2) m.C[s2] = 0.f;
+#pragma unroll
+  for (int p = 0; p < PD; ++p) m.load_pair(x, 2 * p, p);
 
-  int cb = 0;  // (2i) mod CR
-  auto adv = [&]() { cb = (cb + 2 >= M::CR) ? cb + 2 - M::CR : cb + 2; };
-  for (int i = 0; i < n_it; i += 6) {
-    m.template iter<0>(sh, x, i, cb);
-    adv();
-    if (i + 1 >= n_it) break;
-    m.template iter<1>(sh, x, i + 1, cb);
-    adv();
-    if (i + 2 >= n_it) break;
-    m.template iter<2>(sh, x, i + 2, cb);
-    adv();
-    if (i + 3 >= n_it) break;
-    m.template iter<3>(sh, x, i + 3, cb);
-    adv();
-    if (i + 4 >= n_it) break;
-    m.template iter<4>(sh, x, i + 4, cb);
-    adv();
-    if (i + 5 >= n_it) break;
-    m.template iter<5>(sh, x, i + 5, cb);
-    adv();
-  }
+  for (int i = 0; i < n_it; i += M::UNR)
+    if (!m.template body<0>(sh, x, i, n_it)) break;
 }
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -364,16 +387,21 @@ hipError_t launch_march(const Geometry& g, const float* ca, const float* bd, con
   if (g.nb > kMaxSponge || g.seg_rows > kMaxSegRows || nlev < 1 || nlev > g.tblock)
     return hipErrorInvalidValue;
   dim3 grid(nrb_now, march_bands(g), cdiv(g.Z, g.seg_rows));
-#define EHI_MARCH(TT, FF)                                                                          \
-  hipLaunchKernelGGL((k_march<TT, FF>), grid, dim3(kBand), 0, st, g, ca, bd, uin, win, uout, wout, \
+#define EHI_MARCH(TT, FF, PP)                                                                       \
+  hipLaunchKernelGGL((k_march<TT, FF, PP>), grid, dim3(kBand), 0, st, g, ca, bd, uin, win, uout, wout, \
                      stage, slot0, nlev)
+#define EHI_MARCH_T(TT, PP)                  \
+  if (nlev == TT) EHI_MARCH(TT, true, PP);   \
+  else EHI_MARCH(TT, false, PP);
+  if (g.prefetch != 1 && g.prefetch != 2) return hipErrorInvalidValue;
   if (g.tblock == 4) {
-    if (nlev == 4) EHI_MARCH(4, true); else EHI_MARCH(4, false);
+    if (g.prefetch == 1) { EHI_MARCH_T(4, 1) } else { EHI_MARCH_T(4, 2) }
   } else if (g.tblock == 8) {
-    if (nlev == 8) EHI_MARCH(8, true); else EHI_MARCH(8, false);
+    if (g.prefetch == 1) { EHI_MARCH_T(8, 1) } else { EHI_MARCH_T(8, 2) }
   } else {
     return hipErrorInvalidValue;
   }
+#undef EHI_MARCH_T
 #undef EHI_MARCH
   return hipGetLastError();
 }

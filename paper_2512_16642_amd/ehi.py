@@ -31,7 +31,7 @@ SYMBOLS = (
     "ehi_apply_multipliers", "ehi_lambda_max", "ehi_copy_green_dft", "ehi_load_green_dft",
     "ehi_copy_hessian", "ehi_load_hessian", "ehi_copy_factor", "ehi_destroy", "ehi_last_error",
     "ehi_version", "ehi_profile_enable", "ehi_profile_read", "ehi_batch_workspace_bytes",
-    "ehi_factor_batch", "ehi_set_stream", "ehi_set_launch",
+    "ehi_factor_batch", "ehi_set_stream", "ehi_set_launch", "ehi_get_launch",
 )
 PROF_KINDS = ("setup", "step", "dft", "herk", "factor", "solve")
 _PROF_N = 8
@@ -98,6 +98,8 @@ def lib() -> ctypes.CDLL:
     L.ehi_set_stream.restype = st
     L.ehi_set_launch.argtypes = [vp, i32, i32]
     L.ehi_set_launch.restype = st
+    L.ehi_get_launch.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.ehi_get_launch.restype = st
     L.ehi_destroy.argtypes = [vp]
     L.ehi_destroy.restype = st
     L.ehi_last_error.argtypes = []
@@ -255,6 +257,12 @@ class Survey:
 
     def set_launch(self, tblock: int = 0, seg_rows: int = 0):
         _check(lib().ehi_set_launch(self._h, int(tblock), int(seg_rows)))
+
+    def get_launch(self) -> tuple:
+        """(time levels per marching launch, rows per marching segment)."""
+        tb, sr = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().ehi_get_launch(self._h, ctypes.byref(tb), ctypes.byref(sr)))
+        return int(tb.value), int(sr.value)
 
     # -- kernel timing -------------------------------------------------------------
     def profile(self, enable: bool = True):
