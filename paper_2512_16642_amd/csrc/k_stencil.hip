@@ -304,7 +304,10 @@ __global__ void __launch_bounds__(256)
     k_dft_mfma(Geometry g, const float* __restrict__ stage, const float2* __restrict__ tw, int n0,
                int cnt, int first, int r0, float2* __restrict__ ghat) {
   constexpr int MP = 16 * MT;
-  __shared__ float As[kDftKs][MP];
+  // row stride = 16 (mod 32) words: the two sample rows a half-wave reads sit on
+  // disjoint banks
+  constexpr int MS = MP % 32 == 0 ? MP + 16 : MP;
+  __shared__ float As[kDftKs][MS];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int r = blockIdx.y;
@@ -317,37 +320,49 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[mt][j] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int twoF = 2 * g.nf;
-  for (int ks = 0; ks < cnt; ks += kDftKs) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < kDftKs * MP; e += 256) {
-      const int t = e / MP, m = e % MP;
-      float v = 0.f;
-      if (ks + t < cnt && m < twoF) {
-        const float2 z = tw[(size_t)(n0 - 1 + ks + t) * g.nf + (m >> 1)];
-        v = (m & 1) ? z.y : z.x;
-      }
-      As[t][m] = v;
+  // B (staging) in groups of four K-steps (16 samples); the group after the
+  // current one is loaded before the current group's MFMAs are issued
+  auto load_b = [&](floatx4* b, int k16) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int tau = k16 + 4 * u + krow;
+      b[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+      if (tau < cnt) b[u] = *reinterpret_cast<const floatx4*>(S + (size_t)tau * g.nsub_p + col);
     }
-    __syncthreads();
-    const int kend = min(kDftKs, cnt - ks);
-    // four K-steps (16 samples) of B are loaded before their MFMAs are issued
-    for (int k = 0; k < kend; k += 16) {
-      floatx4 b[4];
+  };
+  const int ngrp = (cnt + 15) / 16;
+  floatx4 b[2][4];
+  load_b(b[0], 0);
+  for (int gi = 0; gi < ngrp; gi += 2) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int tau = ks + k + 4 * u + krow;
-        b[u] = floatx4{0.f, 0.f, 0.f, 0.f};
-        if (tau < cnt) b[u] = *reinterpret_cast<const floatx4*>(S + (size_t)tau * g.nsub_p + col);
+    for (int p = 0; p < 2; ++p) {
+      const int gg = gi + p;
+      if (gg >= ngrp) break;
+      const int k16 = gg * 16;
+      const int kl = k16 % kDftKs;  // sample offset inside the LDS stage
+      if (kl == 0) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < kDftKs * MP; e += 256) {
+          const int t = e / MP, m = e % MP;
+          float v = 0.f;
+          if (k16 + t < cnt && m < twoF) {
+            const float2 z = tw[(size_t)(n0 - 1 + k16 + t) * g.nf + (m >> 1)];
+            v = (m & 1) ? z.y : z.x;
+          }
+          As[t][m] = v;
+        }
+        __syncthreads();
       }
+      if (gg + 1 < ngrp) load_b(b[p ^ 1], k16 + 16);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        if (k + 4 * u < kend) {
+        if (k16 + 4 * u < cnt) {
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) {
-            const float a = As[k + 4 * u + krow][16 * mt + (lane & 15)];
+            const float a = As[kl + 4 * u + krow][16 * mt + (lane & 15)];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-              acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[u][j], acc[mt][j], 0, 0, 0);
+              acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[p][u][j], acc[mt][j], 0, 0, 0);
           }
         }
       }
