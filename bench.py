@@ -319,7 +319,7 @@ def main():
 
     # roofline of the dominant kernel (the marching stencil)
     nrb = args.nr_batch if args.nr_batch > 0 else s.nr
-    tblock, seg_rows = sv.get_launch()
+    tblock, seg_rows, band = sv.get_launch()
     step_ms, step_launches = prof["step"]
     cell_updates = costs.stencil_cell_updates_per_survey(s.nz, s.nx, s.nb, s.nr, s.nt)
     bpc = costs.stencil_bytes_per_cell_update(s.nz, s.nx, s.nb, s.stride, nrb, tblock)
@@ -328,7 +328,8 @@ def main():
     bytes_launch = bytes_total / max(step_launches, 1)
     achieved = bytes_launch / avg_step_s / 1e9
     roof = {
-        "kernel": f"k_march<{tblock}> (stencil, {tblock} time levels per launch, {seg_rows}-row segments)",
+        "kernel": f"k_march<{tblock}> (stencil, {tblock} time levels per launch, {seg_rows}-row segments, "
+                  f"{band}-column bands)",
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,

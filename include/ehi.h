@@ -157,12 +157,15 @@ ehi_status ehi_factor_batch(ehi_survey* const* surveys, int32_t n, const double*
 ehi_status ehi_set_stream(ehi_survey* s, void* stream);
 
 /* Launch shape of the Green-function stepping: time levels per launch
- * (4 or 8) and rows per marching segment (16..256); 0 keeps the current value.
- * Results do not depend on them (used by the autotuner). */
-ehi_status ehi_set_launch(ehi_survey* s, int32_t tblock, int32_t seg_rows);
+ * (4 or 8; 0 keeps the current value), rows per marching segment (16..256;
+ * 0 keeps), and columns per marching workgroup (256, 384, 448 or 512; 0 picks
+ * the width that covers the padded grid with the fewest lanes for the chosen
+ * time levels; -1 keeps the current request).  Results do not depend on them
+ * (used by the autotuner).  EHI_EINVAL for any other value. */
+ehi_status ehi_set_launch(ehi_survey* s, int32_t tblock, int32_t seg_rows, int32_t band);
 
-/* The current launch shape (host outputs; either pointer may be NULL). */
-ehi_status ehi_get_launch(const ehi_survey* s, int32_t* tblock, int32_t* seg_rows);
+/* The current launch shape (host outputs; any pointer may be NULL). */
+ehi_status ehi_get_launch(const ehi_survey* s, int32_t* tblock, int32_t* seg_rows, int32_t* band);
 
 /* X(w) = Qhat(w)^{-1} R(w) for ns sources: resid_dev and mult_dev are device
  * complex64 arrays [nf][ns][nr] (frequency-major, one row of nr receiver

@@ -30,7 +30,7 @@ def cache_path() -> str:
 
 def _key(spec, nrb: int) -> str:
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "none"
-    return f"{arch}:Z{spec.nz + 2 * spec.nb}:X{spec.nx + 2 * spec.nb}:nrb{nrb}:v2"
+    return f"{arch}:Z{spec.nz + 2 * spec.nb}:X{spec.nx + 2 * spec.nb}:nrb{nrb}:v3"
 
 
 def _load() -> Dict[str, dict]:
@@ -63,7 +63,7 @@ def tune(spec, nrb: Optional[int] = None, nt_probe: int = 64, repeats: int = 2) 
     times = {}
     for tb in TBLOCKS:
         for seg in SEG_ROWS:
-            sv.set_launch(tb, seg)
+            sv.set_launch(tb, seg, 0)
             sv.build_green(vel)  # warm
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -73,7 +73,7 @@ def tune(spec, nrb: Optional[int] = None, nt_probe: int = 64, repeats: int = 2) 
             times[(tb, seg)] = (time.perf_counter() - t0) / repeats
     sv.close()
     best = min(times, key=times.get)
-    entry = {"tblock": best[0], "seg_rows": best[1],
+    entry = {"tblock": best[0], "seg_rows": best[1], "band": 0,
              "probe_s": {f"{k[0]}x{k[1]}": v for k, v in times.items()}}
     cache[key] = entry
     _store(cache)
@@ -82,7 +82,7 @@ def tune(spec, nrb: Optional[int] = None, nt_probe: int = 64, repeats: int = 2) 
 
 def apply(sv: "ehi.Survey", spec):
     e = tune(spec, nrb=min(spec.nr, sv_nrb(sv, spec)))
-    sv.set_launch(e["tblock"], e["seg_rows"])
+    sv.set_launch(e["tblock"], e["seg_rows"], e.get("band", 0))
 
 
 def sv_nrb(sv, spec) -> int:

@@ -97,15 +97,10 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   g.herk_split = std::max(1, std::min(want, std::min(ehi::kHerkSplitMax, kmax)));
   g.tblock = 8;
   g.seg_rows = 128;
-  g.prefetch = 2;
   // tuning overrides (launch shapes only; results do not depend on them)
   if (const char* e = std::getenv("EHI_TBLOCK")) {
     int v = std::atoi(e);
     if (v == 4 || v == 8) g.tblock = v;
-  }
-  if (const char* e = std::getenv("EHI_PREFETCH")) {
-    int v = std::atoi(e);
-    if (v == 1 || v == 2) g.prefetch = v;
   }
   if (const char* e = std::getenv("EHI_HERK_SPLIT")) {
     int v = std::atoi(e);
@@ -113,8 +108,14 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   }
   if (const char* e = std::getenv("EHI_SEG_ROWS")) {
     int v = std::atoi(e);
-    if (v >= 16 && v <= 256) g.seg_rows = v;
+    if (v >= ehi::kMinSegRows && v <= ehi::kMaxSegRows) g.seg_rows = v;
   }
+  g.band_req = 0;
+  if (const char* e = std::getenv("EHI_BAND")) {
+    int v = std::atoi(e);
+    if (v == 256 || v == 384 || v == 448 || v == 512) g.band_req = v;
+  }
+  g.band = g.band_req ? g.band_req : ehi::march_band_for(g.X, g.tblock);
   return g;
 }
 
@@ -131,6 +132,7 @@ ehi::Layout make_layout(const ehi::Geometry& g) {
   L.rec = take(sizeof(int32_t) * 2 * g.nr);
   L.ca = take(sizeof(float) * g.plane());
   L.bd = take(sizeof(float) * (ehi::kMaxSponge + 1));
+  L.rowtab = take(sizeof(ehi::RowEntry) * (size_t)ehi::cdiv(g.Z, ehi::kMinSegRows) * ehi::kRowTabStride);
   L.vmax = take(sizeof(uint32_t) * 4);
   L.tw = take(sizeof(float2) * (size_t)g.nt * g.nf);
   L.u0 = take(sizeof(float) * g.plane() * g.nrb);
@@ -312,7 +314,9 @@ ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev) {
   PROF(EHI_PROF_SETUP, st);
   EHI_TRY(ehi::launch_vmax(vel_dev, g.nz * g.nx, vmax, st), "vmax");
   EHI_TRY(ehi::launch_coefficients(g, vel_dev, vmax, ca, bd, st), "coefficients");
-  PROF_N(3);
+  ehi::RowEntry* rowtab = s->ptr<ehi::RowEntry>(L.rowtab);
+  EHI_TRY(ehi::launch_row_table(g, bd, rowtab, st), "row table");
+  PROF_N(4);
   const float2* tw = s->ptr<float2>(L.tw);
   float2* ghat = s->ptr<float2>(L.ghat);
   float* stage = s->ptr<float>(L.stage);
@@ -344,7 +348,7 @@ ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev) {
       // advance to the next multiple of tblock (never past the chunk end: tblock | chunk)
       const int target = std::min(g.nt, (n_cur / g.tblock + 1) * g.tblock);
       PROF(EHI_PROF_STEP, st);
-      EHI_TRY(ehi::launch_march(g, ca, bd, ub[cur], wb[cur], ub[1 - cur], wb[1 - cur], stage,
+      EHI_TRY(ehi::launch_march(g, ca, bd, rowtab, ub[cur], wb[cur], ub[1 - cur], wb[1 - cur], stage,
                                 n_cur % g.chunk, target - n_cur, nb_now, st),
               "time steps");
       PROF_N(1);
@@ -487,21 +491,27 @@ ehi_status ehi_set_stream(ehi_survey* s, void* stream) {
   return EHI_OK;
 }
 
-ehi_status ehi_set_launch(ehi_survey* s, int32_t tblock, int32_t seg_rows) {
+ehi_status ehi_set_launch(ehi_survey* s, int32_t tblock, int32_t seg_rows, int32_t band) {
   g_err.clear();
   if (!s) return fail(EHI_EINVAL, "survey is NULL");
   if (tblock != 0 && tblock != 4 && tblock != 8) return fail(EHI_EINVAL, "tblock must be 0, 4 or 8");
-  if (seg_rows != 0 && (seg_rows < 16 || seg_rows > 256)) return fail(EHI_EINVAL, "seg_rows must be 0 or 16..256");
+  if (seg_rows != 0 && (seg_rows < ehi::kMinSegRows || seg_rows > ehi::kMaxSegRows))
+    return fail(EHI_EINVAL, "seg_rows must be 0 or 16..256");
+  if (band != -1 && band != 0 && band != 256 && band != 384 && band != 448 && band != 512)
+    return fail(EHI_EINVAL, "band must be -1, 0, 256, 384, 448 or 512");
   if (tblock) s->g.tblock = tblock;
   if (seg_rows) s->g.seg_rows = seg_rows;
+  if (band != -1) s->g.band_req = band;
+  s->g.band = s->g.band_req ? s->g.band_req : ehi::march_band_for(s->g.X, s->g.tblock);
   return EHI_OK;
 }
 
-ehi_status ehi_get_launch(const ehi_survey* s, int32_t* tblock, int32_t* seg_rows) {
+ehi_status ehi_get_launch(const ehi_survey* s, int32_t* tblock, int32_t* seg_rows, int32_t* band) {
   g_err.clear();
   if (!s) return fail(EHI_EINVAL, "survey is NULL");
   if (tblock) *tblock = s->g.tblock;
   if (seg_rows) *seg_rows = s->g.seg_rows;
+  if (band) *band = s->g.band;
   return EHI_OK;
 }
 

@@ -35,7 +35,8 @@ struct Geometry {
   int herk_split;  // split-K partitions
   int tblock;      // time levels per marching launch (2, 4 or 8; divides chunk)
   int seg_rows;    // output rows per marching segment
-  int prefetch;    // marching iterations between a row's load and its use (1 or 2)
+  int band;        // columns per marching workgroup (256, 384, 448 or 512)
+  int band_req;    // requested band width, 0 = the one with the fewest lanes for tblock
   double h, dt;
   __host__ __device__ size_t plane() const { return (size_t)Zp * Xp; }
 };
@@ -46,6 +47,7 @@ struct Layout {
   size_t rec;       // int32 [2][nr]  (iz then ix, interior indices)
   size_t ca;        // float [Zp][Xp]  kappa / (12 h^2 a)
   size_t bd;        // float [kMaxSponge + 1]  b / a by distance into the layer
+  size_t rowtab;    // RowEntry [cdiv(Z, kMinSegRows)][kRowTabStride]  marching row table
   size_t vmax;      // uint32 [4]  max velocity bits
   size_t tw;        // float2 [nt][nf] exp(-i w n dt), n = 1..nt
   size_t u0, u1;    // float [nrb][Zp][Xp]  (ping-pong)
@@ -121,6 +123,22 @@ struct ehi_survey {
 
 namespace ehi {
 
+// Marching segments hold kMinSegRows..kMaxSegRows output rows.  A launch reads,
+// per segment, kRowTabStride row-table entries: entry ti describes padded row
+// z0 - 4T + ti (z0 = first owned row, T = time levels per launch).
+constexpr int kMinSegRows = 16;
+constexpr int kMaxSegRows = 256;
+constexpr int kRowTabStride = kMaxSegRows + 6 * 8 + 8;
+
+// bz = b / a of the row's distance into the top/bottom layer (1 outside the
+// grid); own = byte offset of the row in a plane if the segment owns it, else
+// -1; sub = byte offset of the row's subgrid line inside a staging slot if the
+// segment owns it and it lies on the subgrid, else -1.
+struct alignas(16) RowEntry {
+  float bz;
+  int32_t own, sub, pad;
+};
+
 // ---- launchers (each returns hipGetLastError() of its launch) ----------------
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t st);
 hipError_t launch_vmax(const float* vel, int n, uint32_t* out_bits, hipStream_t st);
@@ -130,9 +148,11 @@ hipError_t launch_twiddles(const Geometry& g, const double* freq, float2* tw, hi
 hipError_t launch_wave_init(const Geometry& g, const float* vel, const int32_t* rec, int r0,
                             int nrb_now, float* u0, float* w0, float* stage, hipStream_t st);
 int march_bands(const Geometry& g);
-hipError_t launch_march(const Geometry& g, const float* ca, const float* bd, const float* uin,
-                        const float* win, float* uout, float* wout, float* stage, int slot0,
-                        int nlev, int nrb_now, hipStream_t st);
+int march_band_for(int X, int tblock);  // band width covering X columns with the fewest lanes
+hipError_t launch_row_table(const Geometry& g, const float* bd, RowEntry* rt, hipStream_t st);
+hipError_t launch_march(const Geometry& g, const float* ca, const float* bd, const RowEntry* rt,
+                        const float* uin, const float* win, float* uout, float* wout, float* stage,
+                        int slot0, int nlev, int nrb_now, hipStream_t st);
 hipError_t launch_dft_chunk(const Geometry& g, const float* stage, const float2* tw, int n0,
                             int cnt, bool first, int r0, int nrb_now, float2* ghat,
                             hipStream_t st);

@@ -9,7 +9,7 @@
 // computation to avoid storing the wavefields).
 //
 // Time stepping: k_march advances T time levels per launch.  A workgroup owns
-// a band of kBand columns of one receiver's grid (overlapping its neighbours by
+// a band of KB columns of one receiver's grid (overlapping its neighbours by
 // 2T columns on each side, the halo the T steps consume) and marches down the
 // rows.  Each thread owns one column and keeps, for every level, a window of
 // five rows of u and a three-row delay line of w in registers; level t at row q
@@ -24,7 +24,9 @@
 namespace ehi {
 namespace {
 
-constexpr int kBand = 256;  // columns per workgroup (one per thread)
+// Band widths (columns per workgroup, one per thread) instantiated; the host
+// picks the one that covers the padded grid with the fewest lanes.
+constexpr int kBands[] = {256, 384, 448, 512};
 
 // Increment-form recurrence (per cell, FP32):
 //   w <- ba * w + ca * (16 (u_{z-1} + u_{z+1} + u_{x-1} + u_{x+1})
@@ -57,11 +59,11 @@ constexpr int kBand = 256;  // columns per workgroup (one per thread)
 // (column, buffer, level, row of pair) at column * LS + (buffer * T + level) * 2
 // + row.  A lane reads columns c-2..c+2 at fixed offsets from one base, and the
 // odd column stride LS keeps the 32 lanes of a half-wave on distinct banks.
-// Row properties (staging and output offsets, the absorbing-layer factor) are
-// tabulated once per workgroup in LDS, so the unrolled body carries almost no
-// scalar control.
-constexpr int kMaxSegRows = 256;
+// Row properties (staging and output offsets, the absorbing-layer factor) come
+// from a per-segment row table in global memory; its entries are uniform, so
+// they are read with scalar loads straight into scalar registers.
 constexpr unsigned kDrop = 0x80000000u;  // store offset the buffer unit discards
+typedef const __attribute__((address_space(4))) RowEntry CRowEntry;
 
 // Raw buffer access: the row offset is a scalar (soffset), the column offset a
 // per-lane constant (voffset); bounds are the plane the resource describes.
@@ -78,7 +80,7 @@ __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, int vo
 constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
 constexpr int lcm_c(int a, int b) { return a / gcd_c(a, b) * b; }
 
-template <int T, bool FULL, int PD>
+template <int T, bool FULL, int PD, int KB>
 struct March3 {
   static constexpr int CRR = T == 4 ? 12 : 24;          // ca ring rows (>= 2T + 2, even)
   // iterations per unrolled body: a multiple of the u/w ring (3 iterations), the
@@ -87,23 +89,13 @@ struct March3 {
   static constexpr int SETS = PD + 1;                    // prefetch sets (rows of i + PD load during i)
   static_assert(CRR >= 2 * T + 2 && CRR % 2 == 0, "ca ring too short");
   static_assert(UNR % SETS == 0 && UNR % 2 == 0, "the unrolled body cycles sets and buffers");
-  static constexpr int B = kBand - 4 * T;   // output columns per band
-  static constexpr int W = kBand + 4;       // columns in LDS incl. two zero columns per side
+  static constexpr int B = KB - 4 * T;      // output columns per band
+  static constexpr int W = KB + 4;          // columns in LDS incl. two zero columns per side
   static constexpr int LS = 4 * T + 1;      // LDS column stride (words)
-  static constexpr int NRT = kMaxSegRows + 6 * T + 8;  // row-table entries (index rho + 2T)
-
-  // Row table entry: bz = bd[distance of the row into the top/bottom layer]
-  // (1 outside the grid), own = byte offset of the row in a plane if the
-  // segment owns it else -1, sub = byte offset of the row's subgrid line in a
-  // staging slot else -1.  One broadcast LDS read per (level, row).
-  struct alignas(16) RowEntry {
-    float bz;
-    int own, sub, pad;
-  };
+  static_assert(kMaxSegRows + 6 * T + 8 <= kRowTabStride, "row table too short");
 
   struct Shared {
     float lu[W * LS];
-    RowEntry rt[NRT];
   };
 
   float U[T][6];    // level-t rows, slot = rho mod 6
@@ -121,6 +113,8 @@ struct March3 {
     // limited to 2 GiB, so kDrop plus it never wraps back into range.
     unsigned vown, vsub;
     int tid, kb, Z, Pb, nlev, slot_bytes;
+    int slot_off;        // byte offset of staging slot slot0
+    const CRowEntry* rt; // this segment's row table (entry rho + 2T = row kb + rho)
     float bx;   // bd[distance of the column into the left/right layer]
   };
 
@@ -143,6 +137,7 @@ struct March3 {
 
   template <int PH>  // PH = i mod UNR
   __device__ __forceinline__ void iter(Shared& sh, const Ctx& x, int i) {
+    const CRowEntry* rrow = x.rt + 2 * i;  // entry 2T - 2t + h: row rho = 2i - 2t + h
     constexpr int BUF = PH & 1;
     constexpr int S0 = mod(2 * PH, 6);     // u/w ring slot of row 2i
     constexpr int C0 = mod(2 * PH, CRR);   // ca ring slot of row 2i
@@ -167,8 +162,9 @@ struct March3 {
         const int sl = mod(2 * PH - 2 * t + h, 6);  // slot of row rho = 2i - 2t + h
         const int sm2 = (sl + 4) % 6, sm1 = (sl + 5) % 6, sp1 = (sl + 1) % 6, sp2 = (sl + 2) % 6;
         const int cs = mod(2 * PH - 2 * t + h, CRR);
-        const int ti = 2 * i - 2 * t + h + 2 * T;  // row-table index
-        const RowEntry re = sh.rt[ti];
+        const float re_bz = rrow[2 * T - 2 * t + h].bz;
+        const int re_sub = rrow[2 * T - 2 * t + h].sub;
+        const int re_own = rrow[2 * T - 2 * t + h].own;
         const float cen = U[t - 1][sl];
         float un, wn;
         if (FULL || t <= x.nlev) {
@@ -178,11 +174,10 @@ struct March3 {
           const float lap = 16.f * n1 - n2 - 60.f * cen;
           // bd is non-increasing in the distance, so bd[max(dz, dx)] = min(bd[dz], bd[dx]);
           // both are positive floats, whose bit patterns order like the integers
-          const float bq = __int_as_float(min(__float_as_int(re.bz), __float_as_int(x.bx)));
+          const float bq = __int_as_float(min(__float_as_int(re_bz), __float_as_int(x.bx)));
           wn = bq * Wr[t - 1][sl] + C[cs] * lap;
           un = cen + wn;
-          const int rs = __builtin_amdgcn_readfirstlane(re.sub);
-          if (rs >= 0) bstore(un, x.rst, (int)x.vsub, (t - 1) * x.slot_bytes + rs);
+          if (re_sub >= 0) bstore(un, x.rst, (int)x.vsub, x.slot_off + (t - 1) * x.slot_bytes + re_sub);
         } else {
           un = cen;
           wn = Wr[t - 1][sl];
@@ -191,10 +186,9 @@ struct March3 {
           U[t][sl] = un;
           Wr[t][sl] = wn;
         } else {
-          const int ro = __builtin_amdgcn_readfirstlane(re.own);
-          if (ro >= 0) {
-            bstore(un, x.rou, (int)x.vown, ro);
-            bstore(wn, x.row_, (int)x.vown, ro);
+          if (re_own >= 0) {
+            bstore(un, x.rou, (int)x.vown, re_own);
+            bstore(wn, x.row_, (int)x.vown, re_own);
           }
         }
       }
@@ -212,12 +206,13 @@ struct March3 {
   }
 };
 
-template <int T, bool FULL, int PD>
-__global__ void __launch_bounds__(kBand)
+template <int T, bool FULL, int PD, int KB>
+__global__ void __launch_bounds__(KB)
     k_march(Geometry g, const float* __restrict__ ca, const float* __restrict__ bd,
-            const float* __restrict__ uin, const float* __restrict__ win, float* __restrict__ uout,
-            float* __restrict__ wout, float* __restrict__ stage, int slot0, int nlev) {
-  using M = March3<T, FULL, PD>;
+            const RowEntry* __restrict__ rowtab, const float* __restrict__ uin,
+            const float* __restrict__ win, float* __restrict__ uout, float* __restrict__ wout,
+            float* __restrict__ stage, int slot0, int nlev) {
+  using M = March3<T, FULL, PD, KB>;
   __shared__ typename M::Shared sh;
   typename M::Ctx x;
   x.tid = threadIdx.x;
@@ -226,7 +221,7 @@ __global__ void __launch_bounds__(kBand)
   const int r = blockIdx.x;
   const int c = blockIdx.y * M::B - 2 * T + x.tid;  // padded-grid column
   const bool colv = (c >= 0 && c < g.X);
-  const bool own = (x.tid >= 2 * T && x.tid < kBand - 2 * T && colv);
+  const bool own = (x.tid >= 2 * T && x.tid < KB - 2 * T && colv);
   x.Z = g.Z;
   x.Pb = g.Xp * 4;
   const int z0 = blockIdx.z * g.seg_rows;
@@ -244,6 +239,10 @@ __global__ void __launch_bounds__(kBand)
   const size_t sbytes = (size_t)g.chunk * g.nsub_p * sizeof(float);
   x.rst = make_rsrc(stage + (size_t)r * g.chunk * g.nsub_p, sbytes);
   x.slot_bytes = g.nsub_p * 4;
+  x.slot_off = slot0 * x.slot_bytes;
+  // the table is read-only during the launch: constant address space, so the
+  // uniform entries are fetched with scalar loads
+  x.rt = (const CRowEntry*)rowtab + (size_t)blockIdx.z * kRowTabStride;
   // columns outside the grid read the zero ghost column next to the edge
   x.voff = (min(max(c, -kGhost), g.X + kGhost - 1) + kGhost) * 4;
   const int jx = c - g.nb;
@@ -254,22 +253,9 @@ __global__ void __launch_bounds__(kBand)
 
   // the two zero columns on each side of the band
   if (x.tid < 4) {
-    const int zc = x.tid < 2 ? x.tid : kBand + x.tid;
+    const int zc = x.tid < 2 ? x.tid : KB + x.tid;
 #pragma unroll
     for (int e = 0; e < 4 * T; ++e) sh.lu[zc * M::LS + e] = 0.f;
-  }
-  for (int ti = x.tid; ti < M::NRT; ti += kBand) {
-    const int q = x.kb + ti - 2 * T;
-    const bool inside = q >= 0 && q < g.Z;
-    typename M::RowEntry e;
-    e.bz = bd[inside ? max(max(g.nb - q, q - (g.nb + g.nz - 1)), 0) : 0];
-    const bool owned = q >= z0 && q < z1;
-    e.own = owned ? (q + kGhost) * x.Pb : -1;
-    const int jz = q - g.nb;
-    const bool subz = owned && jz >= 0 && jz < g.nz && (jz & (g.stride - 1)) == 0;
-    e.sub = subz ? (slot0 * g.nsub_p + (jz >> g.sshift) * g.nxs) * 4 : -1;
-    e.pad = 0;
-    sh.rt[ti] = e;
   }
 
   M m;
@@ -394,28 +380,79 @@ __global__ void __launch_bounds__(256)
 
 }  // namespace
 
-int march_bands(const Geometry& g) { return cdiv(g.X, kBand - 4 * g.tblock); }
+// Row table for the current launch shape: entry ti of segment sg describes
+// padded row q = sg * seg_rows - 4T + ti.
+__global__ void k_row_table(Geometry g, const float* __restrict__ bd, RowEntry* __restrict__ rt,
+                            int nseg) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nseg * kRowTabStride) return;
+  const int sg = e / kRowTabStride, ti = e % kRowTabStride;
+  const int z0 = sg * g.seg_rows;
+  const int z1 = min(g.Z, z0 + g.seg_rows);
+  const int q = z0 - 4 * g.tblock + ti;
+  const bool inside = q >= 0 && q < g.Z;
+  RowEntry r;
+  r.bz = bd[inside ? max(max(g.nb - q, q - (g.nb + g.nz - 1)), 0) : 0];
+  const bool owned = q >= z0 && q < z1;
+  r.own = owned ? (q + kGhost) * g.Xp * 4 : -1;
+  const int jz = q - g.nb;
+  const bool subz = owned && jz >= 0 && jz < g.nz && (jz & (g.stride - 1)) == 0;
+  r.sub = subz ? (jz >> g.sshift) * g.nxs * 4 : -1;
+  r.pad = 0;
+  rt[e] = r;
+}
 
-hipError_t launch_march(const Geometry& g, const float* ca, const float* bd, const float* uin,
-                        const float* win, float* uout, float* wout, float* stage, int slot0,
-                        int nlev, int nrb_now, hipStream_t st) {
-  if (g.nb > kMaxSponge || g.seg_rows > kMaxSegRows || nlev < 1 || nlev > g.tblock)
+int march_bands(const Geometry& g) { return cdiv(g.X, g.band - 4 * g.tblock); }
+
+hipError_t launch_row_table(const Geometry& g, const float* bd, RowEntry* rt, hipStream_t st) {
+  if (g.seg_rows < kMinSegRows || g.seg_rows > kMaxSegRows) return hipErrorInvalidValue;
+  const int nseg = cdiv(g.Z, g.seg_rows);
+  const int n = nseg * kRowTabStride;
+  hipLaunchKernelGGL(k_row_table, dim3(cdiv(n, 256)), dim3(256), 0, st, g, bd, rt, nseg);
+  return hipGetLastError();
+}
+
+int march_band_for(int X, int tblock) {
+  int best = kBands[0], lanes = 1 << 30;
+  for (int kb : kBands) {
+    const int l = cdiv(X, kb - 4 * tblock) * kb;
+    if (l <= lanes) {  // ties go to the wider band (fewer overlapping halos)
+      lanes = l;
+      best = kb;
+    }
+  }
+  return best;
+}
+
+hipError_t launch_march(const Geometry& g, const float* ca, const float* bd, const RowEntry* rt,
+                        const float* uin, const float* win, float* uout, float* wout, float* stage,
+                        int slot0, int nlev, int nrb_now, hipStream_t st) {
+  if (g.nb > kMaxSponge || g.seg_rows < kMinSegRows || g.seg_rows > kMaxSegRows || nlev < 1 ||
+      nlev > g.tblock)
     return hipErrorInvalidValue;
   dim3 grid(nrb_now, march_bands(g), cdiv(g.Z, g.seg_rows));
-#define EHI_MARCH(TT, FF, PP)                                                                       \
-  hipLaunchKernelGGL((k_march<TT, FF, PP>), grid, dim3(kBand), 0, st, g, ca, bd, uin, win, uout, wout, \
-                     stage, slot0, nlev)
-#define EHI_MARCH_T(TT, PP)                  \
-  if (nlev == TT) EHI_MARCH(TT, true, PP);   \
-  else EHI_MARCH(TT, false, PP);
-  if (g.prefetch != 1 && g.prefetch != 2) return hipErrorInvalidValue;
+#define EHI_MARCH(TT, FF, KK)                                                                     \
+  hipLaunchKernelGGL((k_march<TT, FF, 2, KK>), grid, dim3(KK), 0, st, g, ca, bd, rt, uin, win,   \
+                     uout, wout, stage, slot0, nlev)
+#define EHI_MARCH_T(TT, KK)                \
+  if (nlev == TT) EHI_MARCH(TT, true, KK); \
+  else EHI_MARCH(TT, false, KK);
+#define EHI_MARCH_B(TT)                                 \
+  switch (g.band) {                                     \
+    case 256: EHI_MARCH_T(TT, 256) break;               \
+    case 384: EHI_MARCH_T(TT, 384) break;               \
+    case 448: EHI_MARCH_T(TT, 448) break;               \
+    case 512: EHI_MARCH_T(TT, 512) break;               \
+    default: return hipErrorInvalidValue;               \
+  }
   if (g.tblock == 4) {
-    if (g.prefetch == 1) { EHI_MARCH_T(4, 1) } else { EHI_MARCH_T(4, 2) }
+    EHI_MARCH_B(4)
   } else if (g.tblock == 8) {
-    if (g.prefetch == 1) { EHI_MARCH_T(8, 1) } else { EHI_MARCH_T(8, 2) }
+    EHI_MARCH_B(8)
   } else {
     return hipErrorInvalidValue;
   }
+#undef EHI_MARCH_B
 #undef EHI_MARCH_T
 #undef EHI_MARCH
   return hipGetLastError();

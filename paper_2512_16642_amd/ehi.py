@@ -96,9 +96,9 @@ def lib() -> ctypes.CDLL:
     L.ehi_factor_batch.restype = st
     L.ehi_set_stream.argtypes = [vp, vp]
     L.ehi_set_stream.restype = st
-    L.ehi_set_launch.argtypes = [vp, i32, i32]
+    L.ehi_set_launch.argtypes = [vp, i32, i32, i32]
     L.ehi_set_launch.restype = st
-    L.ehi_get_launch.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.ehi_get_launch.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.ehi_get_launch.restype = st
     L.ehi_destroy.argtypes = [vp]
     L.ehi_destroy.restype = st
@@ -255,14 +255,16 @@ class Survey:
         _check(lib().ehi_set_stream(self._h, ctypes.c_void_p(0 if stream is None else stream.cuda_stream)))
         self.stream = stream
 
-    def set_launch(self, tblock: int = 0, seg_rows: int = 0):
-        _check(lib().ehi_set_launch(self._h, int(tblock), int(seg_rows)))
+    def set_launch(self, tblock: int = 0, seg_rows: int = 0, band: int = -1):
+        """Marching launch shape; 0 keeps tblock / seg_rows, band 0 = automatic,
+        band -1 keeps the current band request."""
+        _check(lib().ehi_set_launch(self._h, int(tblock), int(seg_rows), int(band)))
 
     def get_launch(self) -> tuple:
-        """(time levels per marching launch, rows per marching segment)."""
-        tb, sr = ctypes.c_int32(0), ctypes.c_int32(0)
-        _check(lib().ehi_get_launch(self._h, ctypes.byref(tb), ctypes.byref(sr)))
-        return int(tb.value), int(sr.value)
+        """(time levels per marching launch, rows per marching segment, band width)."""
+        tb, sr, bw = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().ehi_get_launch(self._h, ctypes.byref(tb), ctypes.byref(sr), ctypes.byref(bw)))
+        return int(tb.value), int(sr.value), int(bw.value)
 
     # -- kernel timing -------------------------------------------------------------
     def profile(self, enable: bool = True):
