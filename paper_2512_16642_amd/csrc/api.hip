@@ -90,7 +90,8 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   g.max_ns = d->max_ns;
   g.h = d->h;
   g.dt = d->dt;
-  int ntile = ehi::cdiv(g.nr, d->precision == EHI_PREC_SPLIT_BF16 ? 64 : ehi::kHerkTile);
+  g.split_bf16 = d->precision == EHI_PREC_SPLIT_BF16 ? 1 : 0;
+  int ntile = ehi::cdiv(g.nr, g.split_bf16 ? 64 : ehi::kHerkTile);
   int pairs = ntile * (ntile + 1) / 2;
   int want = ehi::cdiv(2048, pairs * g.nf);
   int kmax = std::max(1, g.nsub / 1024);
@@ -141,12 +142,17 @@ ehi::Layout make_layout(const ehi::Geometry& g) {
   L.w1 = take(sizeof(float) * g.plane() * g.nrb);
   L.stage = take(sizeof(float) * (size_t)g.nrb * g.chunk * g.nsub_p);
   L.ghat = take(sizeof(float2) * (size_t)g.nf * g.nr * g.nsub);
+  L.planes = take(g.split_bf16 ? sizeof(uint4) * 4 * (size_t)g.nf * g.nr * ehi::cdiv(g.nsub, 8) : 0);
   L.hpart = take(sizeof(float2) * (size_t)g.herk_split * g.nf * nn);
   L.hhat = take(sizeof(double2) * g.nf * nn);
   L.qhat = take(sizeof(double2) * g.nf * nn);
   L.lfac = take(sizeof(double2) * g.nf * nn);
   L.lfac32 = take(sizeof(float2) * g.nf * nn);
-  L.linv = take(sizeof(float2) * (size_t)g.nf * ehi::cdiv(g.nr, 32) * 32 * 32);
+  const size_t np = (size_t)ehi::solve_blocks(g) * 32;
+  L.m64 = take(sizeof(double2) * (size_t)g.nf * np * np);
+  L.m32 = take(sizeof(float2) * (size_t)g.nf * np * np);
+  L.y32 = take(sizeof(float2) * (size_t)g.nf * g.max_ns * g.nr);
+  L.r32 = take(sizeof(float2) * (size_t)g.nf * g.max_ns * g.nr);
   L.x64 = take(sizeof(double2) * (size_t)g.nf * g.max_ns * g.nr);
   L.status = take(sizeof(int32_t) * (g.nf + 4));
   L.eig = take(sizeof(double) * g.nf);
@@ -370,12 +376,14 @@ ehi_status ehi_build_hessian(ehi_survey* s) {
   float2* hpart = s->ptr<float2>(L.hpart);
   PROF(EHI_PROF_HERK, s->stream);
   if (s->precision == EHI_PREC_SPLIT_BF16) {
-    EHI_TRY(ehi::launch_herk_split_bf16(g, s->ptr<float2>(L.ghat), hpart, s->stream), "herk bf16");
+    uint4* planes = s->ptr<uint4>(L.planes);
+    EHI_TRY(ehi::launch_split_planes(g, s->ptr<float2>(L.ghat), planes, s->stream), "split planes");
+    EHI_TRY(ehi::launch_herk_split_bf16(g, planes, hpart, s->stream), "herk bf16");
   } else {
     EHI_TRY(ehi::launch_herk_fp32(g, s->ptr<float2>(L.ghat), hpart, s->stream), "herk fp32");
   }
   EHI_TRY(ehi::launch_herk_reduce(g, hpart, s->ptr<double2>(L.hhat), s->stream), "herk reduce");
-  PROF_N(2);
+  PROF_N(s->precision == EHI_PREC_SPLIT_BF16 ? 3 : 2);
   PROF_END();
   s->state = ehi::State::Hessian;
   return EHI_OK;
@@ -421,14 +429,15 @@ ehi_status ehi_factor_batch(ehi_survey* const* surveys, int32_t n, const double*
     const ehi::Geometry& g = s->g;
     const ehi::Layout& L = s->L;
     const size_t nn = (size_t)g.nr * g.nr;
-    const size_t nblk = (size_t)ehi::cdiv(g.nr, 32) * 32 * 32;
+    const size_t npp = (size_t)ehi::solve_blocks(g) * 32 * ehi::solve_blocks(g) * 32;
     for (int f = 0; f < g.nf; ++f) {
       ehi::FactorJob j;
       j.hhat = s->ptr<double2>(L.hhat) + f * nn;
       j.qhat = s->ptr<double2>(L.qhat) + f * nn;
       j.lfac = s->ptr<double2>(L.lfac) + f * nn;
       j.l32 = s->ptr<float2>(L.lfac32) + f * nn;
-      j.linv = s->ptr<float2>(L.linv) + f * nblk;
+      j.m64 = s->ptr<double2>(L.m64) + f * npp;
+      j.m32 = s->ptr<float2>(L.m32) + f * npp;
       j.status = s->ptr<int32_t>(L.status) + f;
       j.mu = mu[k];
       j.nr = g.nr;
@@ -447,8 +456,8 @@ ehi_status ehi_factor_batch(ehi_survey* const* surveys, int32_t n, const double*
                          hipMemcpyHostToDevice, st),
           "job table upload");
   EHI_TRY(ehi::launch_factor_jobs(djobs, (int)jobs.size(), st), "factor");
-  EHI_TRY(ehi::launch_diag_inv_jobs(djobs, (int)jobs.size(), max_nr, st), "block inverses");
-  PROF_N(2);
+  EHI_TRY(ehi::launch_minv_jobs(djobs, (int)jobs.size(), max_nr, st), "triangular inverses");
+  PROF_N(3);
   PROF_END();
   // status readback (the only wait): one small copy per survey
   std::vector<std::vector<int32_t>> host(n);
@@ -529,16 +538,15 @@ ehi_status ehi_apply_multipliers(ehi_survey* s, const void* resid_dev, void* mul
   hipStream_t st = stream ? static_cast<hipStream_t>(stream) : s->stream;
   const float2* R = static_cast<const float2*>(resid_dev);
   float2* X = static_cast<float2*>(mult_dev);
-  const float2* l32 = s->ptr<float2>(L.lfac32);
   double2* x64 = s->ptr<double2>(L.x64);
   PROF(EHI_PROF_SOLVE, st);
   const int refine = s->precision == EHI_PREC_SPLIT_BF16 ? 2 : 0;
   for (int s0 = 0; s0 < ns; s0 += g.max_ns) {
     const int cnt = std::min(g.max_ns, ns - s0);
-    EHI_TRY(ehi::launch_apply(g, l32, s->ptr<float2>(L.linv), s->ptr<double2>(L.qhat), R, ns, s0, cnt,
-                              refine, x64, X, st),
+    EHI_TRY(ehi::launch_apply(g, s->ptr<float2>(L.m32), s->ptr<double2>(L.qhat), R, ns, s0, cnt,
+                              refine, s->ptr<float2>(L.y32), s->ptr<float2>(L.r32), x64, X, st),
             "apply");
-    PROF_N(1);
+    PROF_N(2 + 3 * refine);
   }
   PROF_END();
   return EHI_OK;

@@ -33,6 +33,7 @@ struct Geometry {
   int chunk;       // time samples per DFT chunk (staging depth; multiple of 4 and tblock)
   int nt, nr, nf, nrb, max_ns;
   int herk_split;  // split-K partitions
+  int split_bf16;  // 1: split-BF16 contraction (hi/lo planes kept), 0: plain FP32
   int tblock;      // time levels per marching launch (2, 4 or 8; divides chunk)
   int seg_rows;    // output rows per marching segment
   int band;        // columns per marching workgroup (256, 384, 448 or 512)
@@ -54,12 +55,16 @@ struct Layout {
   size_t w0, w1;    // float [nrb][Zp][Xp]  (ping-pong)
   size_t stage;     // float [nrb][chunk][nsub_p]
   size_t ghat;      // float2 [nf][nr][nsub]
+  size_t planes;    // uint4 [nf][nr][cdiv(nsub, 8)][4]  BF16 hi/lo planes of ghat (split form)
   size_t hpart;     // float2 [split][nf][nr][nr]
   size_t hhat;      // double2 [nf][nr][nr]
   size_t qhat;      // double2 [nf][nr][nr]   Hhat + mu I (Hermitian, full)
   size_t lfac;      // double2 [nf][nr][nr]   lower Cholesky factor (FP64 mode)
   size_t lfac32;    // float2 [nf][nr][nr]    complex64 copy (or the FP32 factor)
-  size_t linv;      // float2 [nf][nr/32][32][32] inverses of the 32 x 32 diagonal blocks
+  size_t m64;       // double2 [nf][np][np]  FP64 scratch of the triangular inverse
+  size_t m32;       // float2 [nf][np][np]  complex64 M = L^{-1} (np = 32 cdiv(nr, 32))
+  size_t y32;       // float2 [nf][max_ns][nr]  solve scratch
+  size_t r32;       // float2 [nf][max_ns][nr]  refinement residual
   size_t x64;       // double2 [nf][max_ns][nr] refinement accumulator
   size_t status;    // int32 [nf + 4]
   size_t eig;       // double [nf]
@@ -75,7 +80,8 @@ struct FactorJob {
   double2* qhat;
   double2* lfac;
   float2* l32;
-  float2* linv;
+  double2* m64;   // [np][np] FP64 scratch of the triangular inverse (np = 32 cdiv(nr, 32))
+  float2* m32;    // [np][np] complex64 inverse M = L^{-1}, zero above the diagonal
   int32_t* status;
   double mu;
   int nr;
@@ -157,15 +163,16 @@ hipError_t launch_dft_chunk(const Geometry& g, const float* stage, const float2*
                             int cnt, bool first, int r0, int nrb_now, float2* ghat,
                             hipStream_t st);
 hipError_t launch_herk_fp32(const Geometry& g, const float2* ghat, float2* hpart, hipStream_t st);
-hipError_t launch_herk_split_bf16(const Geometry& g, const float2* ghat, float2* hpart,
+hipError_t launch_split_planes(const Geometry& g, const float2* ghat, uint4* planes, hipStream_t st);
+hipError_t launch_herk_split_bf16(const Geometry& g, const uint4* planes, float2* hpart,
                                   hipStream_t st);
 hipError_t launch_herk_reduce(const Geometry& g, const float2* hpart, double2* hhat,
                               hipStream_t st);
 hipError_t launch_factor_jobs(const FactorJob* jobs, int njobs, hipStream_t st);
-hipError_t launch_diag_inv_jobs(const FactorJob* jobs, int njobs, int max_nr, hipStream_t st);
+hipError_t launch_minv_jobs(const FactorJob* jobs, int njobs, int max_nr, hipStream_t st);
 int solve_blocks(const Geometry& g);
-hipError_t launch_apply(const Geometry& g, const float2* l32, const float2* inv,
-                        const double2* qhat, const float2* R, int rld, int s0, int cnt, int refine,
+hipError_t launch_apply(const Geometry& g, const float2* m32, const double2* qhat, const float2* R,
+                        int rld, int s0, int cnt, int refine, float2* y32, float2* r32,
                         double2* x64, float2* out, hipStream_t st);
 hipError_t launch_power_iter(const Geometry& g, const double2* hhat, double* eig, int iters,
                              hipStream_t st);

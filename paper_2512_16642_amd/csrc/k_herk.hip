@@ -102,13 +102,23 @@ __global__ void __launch_bounds__(256)
 // Workgroup: 4 waves, a 64 x 64 tile (i-block, j-block) of H for one frequency
 // and one grid-point partition; each wave owns a 32 x 32 quarter as 2 x 2
 // v_mfma_f32_16x16x32_bf16 tiles for Re and Im.  Per stage, 32 grid points of
-// the 128 rows are loaded once, split into hi/lo BF16 planes in LDS, and read
-// back as MFMA fragments (lane l: row l % 16, points 8 (l / 16) .. + 7).
+// the 128 rows are split into hi/lo BF16 planes and stored in LDS as 16-byte
+// fragments [plane][group of 8 points][row] (lane l of an MFMA reads row
+// l % 16, points 8 (l / 16) .. + 7: one aligned 16-byte read).  Stages are
+// double-buffered: the global loads of stage s + 1 are in flight while the
+// MFMAs of stage s run, and one barrier separates stages.
+//
+// Work items (tile pair, partition, frequency) are laid out so that the tile
+// pairs of one (partition, frequency) run on the same XCD (workgroups are
+// dealt to the 8 XCDs round-robin): the row blocks they share are then read
+// from HBM into that XCD's L2 once instead of once per pair.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBt = 64;  // H tile (rows = cols)
 constexpr int kBk = 32;  // grid points per stage (four groups of 8)
+constexpr int kXcd = 8;  // XCDs per device
 
 __device__ __forceinline__ unsigned short bf16_rne(float x) {
   unsigned u = __float_as_uint(x);
@@ -117,15 +127,53 @@ __device__ __forceinline__ unsigned short bf16_rne(float x) {
 }
 __device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
+// BF16 hi/lo planes of the spectra, written once per build: planes[f][r][c][q]
+// holds points 8c .. 8c + 7 of plane q (0 = Re hi, 1 = Re lo, 2 = Im hi,
+// 3 = Im lo) as one 16-byte fragment; points beyond nsub are zero.  Every FP32
+// value x is split as hi = bf16(x), lo = bf16(x - hi), both rounded to nearest
+// even.
 __global__ void __launch_bounds__(256)
-    k_herk_bf16(Geometry g, const float2* __restrict__ ghat, float2* __restrict__ hpart, int split) {
-  // planes: 0 = Re hi, 1 = Re lo, 2 = Im hi, 3 = Im lo; rows 0..63 i-block, 64..127 j-block;
-  // [plane][group of 8 points][row][8]: every fragment is one aligned 16-byte chunk
-  __shared__ __attribute__((aligned(16))) unsigned short pl[4][kBk / 8][2 * kBt][8];
+    k_split_planes(Geometry g, const float2* __restrict__ ghat, u32x4* __restrict__ planes) {
+  const int ngrp = cdiv(g.nsub, 8);
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)g.nf * g.nr * ngrp) return;
+  const size_t row = e / ngrp;  // f * nr + r
+  const int c = (int)(e % ngrp);
+  const float2* src = ghat + row * g.nsub + 8 * c;
+  unsigned w[4][4];
+#pragma unroll
+  for (int p = 0; p < 8; p += 2) {
+    unsigned short h[4][2];
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const float2 z = 8 * c + p + d < g.nsub ? src[p + d] : make_float2(0.f, 0.f);
+      h[0][d] = bf16_rne(z.x);
+      h[1][d] = bf16_rne(z.x - bf16_to_f(h[0][d]));
+      h[2][d] = bf16_rne(z.y);
+      h[3][d] = bf16_rne(z.y - bf16_to_f(h[2][d]));
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[q][p >> 1] = (unsigned)h[q][0] | ((unsigned)h[q][1] << 16);
+  }
+  u32x4* dst = planes + e * 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) dst[q] = u32x4{w[q][0], w[q][1], w[q][2], w[q][3]};
+}
+
+__global__ void __launch_bounds__(256)
+    k_herk_bf16(Geometry g, const u32x4* __restrict__ planes, float2* __restrict__ hpart, int split) {
+  // planes: 0 = Re hi, 1 = Re lo, 2 = Im hi, 3 = Im lo; rows 0..63 i-block, 64..127 j-block
+  __shared__ u32x4 pl[2][4][kBk / 8][2 * kBt];
   const int nblk = cdiv(g.nr, kBt);
+  const int npair = nblk * (nblk + 1) / 2;
+  // XCD-aware work item: consecutive items (the pairs of one partition and
+  // frequency) go to the workgroups one XCD receives
+  const int n = blockIdx.x;
+  const int n8 = gridDim.x / kXcd * kXcd;
+  const int item = n < n8 ? (n % kXcd) * (n8 / kXcd) + n / kXcd : n;
   int bi, bj;
   {
-    int p = blockIdx.x, i = 0;
+    int p = item % npair, i = 0;
     while (p >= nblk - i) {
       p -= nblk - i;
       ++i;
@@ -133,15 +181,15 @@ __global__ void __launch_bounds__(256)
     bi = i;
     bj = i + p;
   }
-  const int ks = blockIdx.y;
-  const int f = blockIdx.z;
+  const int ks = (item / npair) % split;
+  const int f = item / (npair * split);
   const int kchunk = cdiv(cdiv(g.nsub, split), kBk) * kBk;
   const int k0 = ks * kchunk;
   const int k1 = min(g.nsub, k0 + kchunk);
+  const int ngrp = cdiv(g.nsub, 8);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
-  const float2* G = ghat + (size_t)f * g.nr * g.nsub;
 
   floatx4 re[2][2], im[2][2];
 #pragma unroll
@@ -149,41 +197,54 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int b = 0; b < 2; ++b) re[a][b] = im[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  // load assignment: thread -> (row 0..127, 16 consecutive points)
-  const int lrow = tid >> 1;
-  const int lhalf = tid & 1;
+  // load tasks: row lrow (0..127), point groups (tid >> 7) and (tid >> 7) + 2
+  const int lrow = tid & (2 * kBt - 1);
   const int grow = lrow < kBt ? bi * kBt + lrow : bj * kBt + (lrow - kBt);
   const bool rowv = grow < g.nr;
-  const float2* Grow = G + (size_t)(rowv ? grow : 0) * g.nsub;
-
-  for (int kb = k0; kb < k1; kb += kBk) {
-    __syncthreads();
-#pragma unroll 4
-    for (int e = 0; e < 16; ++e) {
-      const int k = kb + lhalf * 16 + e;
-      float2 v = make_float2(0.f, 0.f);
-      if (rowv && k < k1) v = Grow[k];
-      const unsigned short rh = bf16_rne(v.x), ih = bf16_rne(v.y);
-      const int kk = lhalf * 16 + e;
-      pl[0][kk >> 3][lrow][kk & 7] = rh;
-      pl[1][kk >> 3][lrow][kk & 7] = bf16_rne(v.x - bf16_to_f(rh));
-      pl[2][kk >> 3][lrow][kk & 7] = ih;
-      pl[3][kk >> 3][lrow][kk & 7] = bf16_rne(v.y - bf16_to_f(ih));
+  const u32x4* Prow = planes + ((size_t)f * g.nr + (rowv ? grow : 0)) * ngrp * 4;
+  u32x4 v[2][4];
+  auto gload = [&](int kb) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int c = kb / 8 + (tid >> 7) + 2 * p;  // group; groups past k1 hold zeros or lie in
+      const bool ok = rowv && 8 * c < k1;         // the next partition (masked here)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[p][q] = ok ? Prow[(size_t)c * 4 + q] : u32x4{0u, 0u, 0u, 0u};
     }
-    __syncthreads();
-    const int fr = lane & 15, fg = lane >> 4;
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int grp = (tid >> 7) + 2 * p;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) pl[buf][q][grp][lrow] = v[p][q];
+    }
+  };
+
+  const int nst = cdiv(k1 - k0, kBk);
+  if (nst > 0) {
+    gload(k0);
+    lstore(0);
+  }
+  __syncthreads();
+  const int fr = lane & 15, fg = lane >> 4;
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nst) gload(k0 + (st + 1) * kBk);
     bf16x8 ai[2][4], aj[2][4];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        ai[a][q] = *reinterpret_cast<const bf16x8*>(&pl[q][fg][wi * 32 + a * 16 + fr][0]);
-        aj[a][q] = *reinterpret_cast<const bf16x8*>(&pl[q][fg][kBt + wj * 32 + a * 16 + fr][0]);
+        ai[a][q] = __builtin_bit_cast(bf16x8, pl[buf][q][fg][wi * 32 + a * 16 + fr]);
+        aj[a][q] = __builtin_bit_cast(bf16x8, pl[buf][q][fg][kBt + wj * 32 + a * 16 + fr]);
       }
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      // -A_i fragments for the subtracted term of Im
-      bf16x8 nrh = -ai[a][0], nrl = -ai[a][1];
+      // -A_i fragments for the subtracted term of Im (sign bits flipped)
+      const u32x4 sgn = u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+      const bf16x8 nrh = __builtin_bit_cast(bf16x8, __builtin_bit_cast(u32x4, ai[a][0]) ^ sgn);
+      const bf16x8 nrl = __builtin_bit_cast(bf16x8, __builtin_bit_cast(u32x4, ai[a][1]) ^ sgn);
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         floatx4 r = floatx4{0.f, 0.f, 0.f, 0.f}, m = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -207,6 +268,8 @@ __global__ void __launch_bounds__(256)
         im[a][b] += m;
       }
     }
+    if (st + 1 < nst) lstore(buf ^ 1);
+    __syncthreads();
   }
   // D[4 (lane / 16) + v][lane % 16] of tile (a, b)
   float2* out = hpart + ((size_t)ks * g.nf + f) * g.nr * g.nr;
@@ -215,10 +278,10 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = bi * kBt + wi * 32 + a * 16 + 4 * (lane >> 4) + v;
+      for (int v4 = 0; v4 < 4; ++v4) {
+        const int i = bi * kBt + wi * 32 + a * 16 + 4 * (lane >> 4) + v4;
         const int j = bj * kBt + wj * 32 + b * 16 + (lane & 15);
-        if (i < g.nr && j < g.nr) out[(size_t)i * g.nr + j] = make_float2(re[a][b][v], im[a][b][v]);
+        if (i < g.nr && j < g.nr) out[(size_t)i * g.nr + j] = make_float2(re[a][b][v4], im[a][b][v4]);
       }
 }
 
@@ -260,10 +323,21 @@ int herk_bf16_blocks(const Geometry& g) {
   return nb * (nb + 1) / 2;
 }
 
-hipError_t launch_herk_split_bf16(const Geometry& g, const float2* ghat, float2* hpart,
+hipError_t launch_split_planes(const Geometry& g, const float2* ghat, uint4* planes, hipStream_t st) {
+  const size_t n = (size_t)g.nf * g.nr * cdiv(g.nsub, 8);
+  const size_t blocks = (n + 255) / 256;
+  if (blocks > 0x7fffffffULL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_split_planes, dim3((unsigned)blocks), dim3(256), 0, st, g, ghat,
+                     reinterpret_cast<u32x4*>(planes));
+  return hipGetLastError();
+}
+
+hipError_t launch_herk_split_bf16(const Geometry& g, const uint4* planes, float2* hpart,
                                   hipStream_t st) {
-  dim3 grid(herk_bf16_blocks(g), g.herk_split, g.nf);
-  hipLaunchKernelGGL(k_herk_bf16, grid, dim3(256), 0, st, g, ghat, hpart, g.herk_split);
+  const long long items = (long long)herk_bf16_blocks(g) * g.herk_split * g.nf;
+  if (items > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_herk_bf16, dim3((unsigned)items), dim3(256), 0, st, g,
+                     reinterpret_cast<const u32x4*>(planes), hpart, g.herk_split);
   return hipGetLastError();
 }
 

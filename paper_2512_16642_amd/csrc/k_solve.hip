@@ -3,9 +3,15 @@
 // Paper: the block-diagonal frequency system is solved separately per frequency
 // for every source with the stored blocks (frequency-domain inversion; the
 // per-source step of the multiplier-based algorithm computes delta d^e in the
-// frequency domain).  The factor L (complex64 copy) drives blocked forward and
-// back substitution; in the split-BF16 precision mode two refinement steps
-// compute the residual R - Qhat X in FP64 and correct X (accumulated in FP64).
+// frequency domain).
+//
+// The two triangular solves with the Cholesky factor L are applied as products
+// with M = L^{-1}: X = M^H (M R).  M is formed once per factorisation in FP64
+// (block-column recursion below) and kept as a zero-padded complex64 matrix, so
+// every solve is a dense batched product over (row tile, source tile,
+// frequency) with no sequential dependency between rows.  In the split-BF16
+// precision mode two refinement steps follow: r = R - Qhat X in FP64 (X kept in
+// FP64), X += M^H (M r) in FP32.
 #include <hip/hip_runtime.h>
 
 #include "ehi_internal.h"
@@ -13,23 +19,25 @@
 namespace ehi {
 namespace {
 
+constexpr int kSb = 32;  // block of the triangular inversion
+
 // ---------------------------------------------------------------------------
-// Blocked multi-source solves.  L is split into 32 x 32 blocks; the inverses of
-// the diagonal blocks are formed once after the factorisation, so every block
-// step of the forward solve  X_I = inv(L_II) (B_I - sum_{J<I} L_IJ X_J)  and of
-// the back solve with L^H is a pair of small dense products over the sources of
-// a tile, with no row-by-row dependency chain inside a block.
-
-constexpr int kSb = 32;  // solve block
-
-// inv[I] = inverse of the diagonal block L_II of a job's complex64 factor,
-// computed in FP64 (rows past nr are padded with the identity).  One thread per
-// column of the block; grid (blocks, jobs).
+// M = L^{-1}, L padded to np = 32 * cdiv(nr, 32) rows with the identity
+// (L_pad = diag(L, I), so M_pad = diag(M, I)).
+//
+// Pass 1 (k_diag_inv): D_I = inverse of the diagonal block L_II in FP64, one
+// workgroup of 32 threads (one per column) per (block, job); written to the
+// diagonal blocks of the job's FP64 scratch m64.
+// Pass 2 (k_tri_inv_cols): block column J of M, one workgroup per (J, job):
+// M_JJ = D_J and, for I = J+1, ..., M_IJ = -D_I sum_{K=J}^{I-1} L_IK M_KJ.
+// Writes the complex64 copy (zeros above the diagonal) used by the solves.
 __global__ void __launch_bounds__(kSb) k_diag_inv(const FactorJob* __restrict__ jobs) {
   const FactorJob jb = jobs[blockIdx.y];
   const int I = blockIdx.x, j = threadIdx.x;
   const int n = jb.nr;
-  if (I >= cdiv(n, kSb)) return;
+  const int nb = cdiv(n, kSb);
+  const int np = nb * kSb;
+  if (I >= nb) return;
   const float2* l32 = jb.l32;
   __shared__ double2 Lb[kSb][kSb];
   for (int r = 0; r < kSb; ++r) {
@@ -58,190 +66,225 @@ __global__ void __launch_bounds__(kSb) k_diag_inv(const FactorJob* __restrict__ 
     const double d = Lb[r][r].x;  // real and positive
     Y[r][j] = (r < j) ? make_double2(0.0, 0.0) : make_double2(tr / d, ti / d);
   }
-  float2* out = jb.linv + (size_t)I * kSb * kSb;
-  for (int r = 0; r < kSb; ++r) out[r * kSb + j] = make_float2((float)Y[r][j].x, (float)Y[r][j].y);
+  double2* out = jb.m64 + ((size_t)I * kSb) * np + I * kSb;
+  for (int r = 0; r < kSb; ++r) out[(size_t)r * np + j] = Y[r][j];
 }
 
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // conj(a) * b
-  return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+__device__ __forceinline__ double2 zmac(double2 acc, double2 a, double2 b) {
+  acc.x += a.x * b.x - a.y * b.y;
+  acc.y += a.x * b.y + a.y * b.x;
+  return acc;
 }
 
-// Workgroup of 256 threads = CT sources x RG row groups; thread (c, gq) owns,
-// inside every 32-row block, rows gq*RPT .. gq*RPT + RPT - 1 of source column c.
-template <int CT>
-struct Tile {
-  static constexpr int RG = 256 / CT;
-  static constexpr int RPT = kSb / RG;
+__global__ void __launch_bounds__(256) k_tri_inv_cols(const FactorJob* __restrict__ jobs) {
+  const FactorJob jb = jobs[blockIdx.y];
+  const int J = blockIdx.x;
+  const int n = jb.nr;
+  const int nb = cdiv(n, kSb);
+  const int np = nb * kSb;
+  if (J >= nb) return;
+  __shared__ double2 Ls[kSb][kSb + 1];
+  __shared__ double2 Xs[kSb][kSb + 1];
+  __shared__ double2 Ts[kSb][kSb + 1];
+  const int tid = threadIdx.x;
+  const int r = tid >> 3, c0 = (tid & 7) * 4;  // this thread: row r, columns c0 .. c0 + 3
+  double2* m64 = jb.m64;
+  float2* m32 = jb.m32;
+  auto put32 = [&](int I, int rr, int cc, double2 v) {
+    m32[(size_t)(I * kSb + rr) * np + J * kSb + cc] = make_float2((float)v.x, (float)v.y);
+  };
+  // blocks above the diagonal are zero; the diagonal block is D_J
+  for (int I = 0; I < J; ++I)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) put32(I, r, c0 + q, make_double2(0.0, 0.0));
+#pragma unroll
+  for (int q = 0; q < 4; ++q) put32(J, r, c0 + q, m64[(size_t)(J * kSb + r) * np + J * kSb + c0 + q]);
+  for (int I = J + 1; I < nb; ++I) {
+    double2 t[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[q] = make_double2(0.0, 0.0);
+    for (int K = J; K < I; ++K) {
+      __syncthreads();
+      // L_IK (zero outside the nr x nr factor) and M_KJ
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gr = I * kSb + r, gc = K * kSb + c0 + q;
+        double2 v = make_double2(0.0, 0.0);
+        if (gr < n && gc < n) {
+          const float2 x = jb.l32[(size_t)gr * n + gc];
+          v = make_double2(x.x, x.y);
+        }
+        Ls[r][c0 + q] = v;
+        Xs[r][c0 + q] = m64[(size_t)(K * kSb + r) * np + J * kSb + c0 + q];
+      }
+      __syncthreads();
+      for (int k = 0; k < kSb; ++k) {
+        const double2 a = Ls[r][k];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) t[q] = zmac(t[q], a, Xs[k][c0 + q]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Ts[r][c0 + q] = t[q];
+      Ls[r][c0 + q] = m64[(size_t)(I * kSb + r) * np + I * kSb + c0 + q];  // D_I
+    }
+    __syncthreads();
+    double2 x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[q] = make_double2(0.0, 0.0);
+    for (int k = 0; k < kSb; ++k) {
+      const double2 a = Ls[r][k];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = zmac(x[q], a, Ts[k][c0 + q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double2 v = make_double2(-x[q].x, -x[q].y);
+      m64[(size_t)(I * kSb + r) * np + J * kSb + c0 + q] = v;
+      put32(I, r, c0 + q, v);
+    }
+    // the next block reads this one back through global memory
+    __threadfence_block();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched complex products for the solves, one frequency per blockIdx.z:
+//   C(i, j) = sum_k op(A)(i, k) B(k, j),  i < n (receivers), j < ns (sources)
+// A: MODE 0: Qhat (FP64, n x n, row-major); MODE 1: M (lower, np x np);
+// MODE 2: M^H, i.e. A(i, k) = conj(M(k, i)).  Tiles of M that are zero by
+// triangularity are skipped.  B(k, j) = Bm[j * ldb + k] (source-major, as the
+// residuals are stored), read as zero for k >= n.
+// Workgroup: a 64 x 64 tile of C, each thread a 4 x 4 register tile; K in
+// stages of 16 through LDS.
+enum { kEpiStore = 0, kEpiResid = 1, kEpiX64Set = 2, kEpiX64Add = 3, kEpiOut = 4 };
+
+struct GemmArgs {
+  const void* A;    // float2 or double2
+  size_t sA;        // per-frequency stride (elements)
+  int lda;
+  const void* B;    // float2 (FP32) or double2 (FP64)
+  size_t sB;
+  int ldb;
+  int n, ns;        // rows of C (receivers), columns (sources)
+  int kmax;         // K extent (n for Qhat, np for M; B rows >= n read as zero)
+  float2* C;        // float2 outputs (kEpiStore, kEpiResid, kEpiOut)
+  size_t sC;
+  int ldc;
+  const float2* R;  // residuals (kEpiResid)
+  size_t sR;
+  int ldr;
+  double2* X;       // FP64 iterate (kEpiX64Set/Add/Out)
+  size_t sX;
+  int ldx;
 };
 
-// In-place solve of L L^H x = b for the tile's columns held in xs[row][c].
-template <int CT>
-__device__ void tile_solve(const Geometry& g, const float2* __restrict__ L,
-                           const float2* __restrict__ inv, float2 (*xs)[CT + 1], int c, int gq) {
-  constexpr int RPT = Tile<CT>::RPT;
-  const int n = g.nr;
-  const int nb = cdiv(n, kSb);
-  float2 t[RPT];
-  // forward
-  for (int I = 0; I < nb; ++I) {
+template <typename T> struct Cx;
+template <> struct Cx<float> { typedef float2 t; };
+template <> struct Cx<double> { typedef double2 t; };
+
+constexpr int kGm = 64, kGn = 64, kGk = 16;
+
+template <typename T, int MODE, int EPI>
+__global__ void __launch_bounds__(256) k_cgemm(GemmArgs a) {
+  typedef typename Cx<T>::t C2;
+  __shared__ C2 As[kGk][kGm];
+  __shared__ C2 Bs[kGk][kGn];
+  const int f = blockIdx.z;
+  const int i0 = blockIdx.y * kGm, j0 = blockIdx.x * kGn;
+  const int tid = threadIdx.x;
+  const int ty = tid >> 4, tx = tid & 15;
+  const C2* A = static_cast<const C2*>(a.A) + (size_t)f * a.sA;
+  const C2* B = static_cast<const C2*>(a.B) + (size_t)f * a.sB;
+  C2 acc[4][4];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = I * kSb + gq * RPT + q;
-      float2 acc = xs[r][c];
-      if (r < n) {
-        const float2* Lr = L + (size_t)r * n;
-        for (int k = 0; k < I * kSb; ++k) {
-          const float2 p = cmul(Lr[k], xs[k][c]);
-          acc.x -= p.x;
-          acc.y -= p.y;
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = C2{0, 0};
+  int kbeg = 0, kend = min(a.kmax, a.n);
+  if (MODE == 1) kend = min(kend, i0 + kGm);             // M(i, k) = 0 for k > i
+  if (MODE == 2) kbeg = i0 / kGk * kGk;                  // conj(M(k, i)) = 0 for k < i
+  for (int k0 = kbeg; k0 < kend; k0 += kGk) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      if (MODE == 2) {
+        const int kk = e / kGm, ii = e % kGm;          // contiguous along i
+        const int gk = k0 + kk, gi = i0 + ii;
+        C2 v = C2{0, 0};
+        if (gk < kend && gi < a.kmax) {
+          const C2 m = A[(size_t)gk * a.lda + gi];
+          v = C2{m.x, -m.y};
         }
+        As[kk][ii] = v;
+      } else {
+        const int ii = e / kGk, kk = e % kGk;          // contiguous along k
+        const int gk = k0 + kk, gi = i0 + ii;
+        As[kk][ii] = (gk < kend && gi < a.kmax) ? A[(size_t)gi * a.lda + gk] : C2{0, 0};
       }
-      t[q] = acc;
+      const int jj = e / kGk, kk = e % kGk;
+      const int gk = k0 + kk, gj = j0 + jj;
+      Bs[kk][jj] = (gk < kend && gj < a.ns) ? B[(size_t)gj * a.ldb + gk] : C2{0, 0};
     }
     __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kGk; ++kk) {
+      C2 av[4], bv[4];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) xs[I * kSb + gq * RPT + q][c] = t[q];
-    __syncthreads();
-    const float2* Ib = inv + (size_t)I * kSb * kSb;
+      for (int r = 0; r < 4; ++r) av[r] = As[kk][ty * 4 + r];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int rr = gq * RPT + q;
-      float2 acc = make_float2(0.f, 0.f);
-      for (int k = 0; k <= rr; ++k) {
-        const float2 p = cmul(Ib[rr * kSb + k], xs[I * kSb + k][c]);
-        acc.x += p.x;
-        acc.y += p.y;
-      }
-      t[q] = acc;
+      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][tx * 4 + c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          acc[r][c].x += av[r].x * bv[c].x - av[r].y * bv[c].y;
+          acc[r][c].y += av[r].x * bv[c].y + av[r].y * bv[c].x;
+        }
     }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) xs[I * kSb + gq * RPT + q][c] = t[q];
-    __syncthreads();
   }
-  // backward with L^H
-  for (int I = nb - 1; I >= 0; --I) {
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = I * kSb + gq * RPT + q;
-      float2 acc = xs[r][c];
-      if (r < n) {
-        for (int k = (I + 1) * kSb; k < n; ++k) {
-          const float2 p = cmulc(L[(size_t)k * n + r], xs[k][c]);
-          acc.x -= p.x;
-          acc.y -= p.y;
+  for (int c = 0; c < 4; ++c) {
+    const int j = j0 + tx * 4 + c;
+    if (j >= a.ns) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + ty * 4 + r;
+      if (i >= a.n) continue;
+      const C2 v = acc[r][c];
+      if (EPI == kEpiStore) {
+        a.C[(size_t)f * a.sC + (size_t)j * a.ldc + i] = make_float2((float)v.x, (float)v.y);
+      } else if (EPI == kEpiResid) {
+        const float2 rr = a.R[(size_t)f * a.sR + (size_t)j * a.ldr + i];
+        a.C[(size_t)f * a.sC + (size_t)j * a.ldc + i] =
+            make_float2((float)((double)rr.x - (double)v.x), (float)((double)rr.y - (double)v.y));
+      } else {
+        double2* xp = a.X + (size_t)f * a.sX + (size_t)j * a.ldx + i;
+        if (EPI == kEpiX64Set) {
+          *xp = make_double2((double)v.x, (double)v.y);
+        } else if (EPI == kEpiX64Add) {
+          double2 o = *xp;
+          o.x += (double)v.x;
+          o.y += (double)v.y;
+          *xp = o;
+        } else {  // kEpiOut
+          const double2 o = *xp;
+          a.C[(size_t)f * a.sC + (size_t)j * a.ldc + i] =
+              make_float2((float)(o.x + (double)v.x), (float)(o.y + (double)v.y));
         }
       }
-      t[q] = acc;
     }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) xs[I * kSb + gq * RPT + q][c] = t[q];
-    __syncthreads();
-    const float2* Ib = inv + (size_t)I * kSb * kSb;
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int rr = gq * RPT + q;
-      float2 acc = make_float2(0.f, 0.f);
-      for (int k = rr; k < kSb; ++k) {
-        const float2 p = cmulc(Ib[k * kSb + rr], xs[I * kSb + k][c]);
-        acc.x += p.x;
-        acc.y += p.y;
-      }
-      t[q] = acc;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) xs[I * kSb + gq * RPT + q][c] = t[q];
-    __syncthreads();
   }
 }
 
-// One (frequency, tile of CT sources): X = Qhat^{-1} R.  refine = 0: FP32
-// solve only, written to out.  refine = 2: FP32 solve, then two steps of
-// r = R - Qhat X in FP64, d = solve(r), X += d with X kept in FP64 (x64 scratch).
-template <int CT>
-__global__ void __launch_bounds__(256)
-    k_apply(Geometry g, const float2* __restrict__ l32, const float2* __restrict__ inv,
-            const double2* __restrict__ qhat, const float2* __restrict__ R, int rld, int s0, int cnt,
-            int refine, double2* __restrict__ x64, float2* __restrict__ out) {
-  extern __shared__ float2 xs_raw[];
-  float2(*xs)[CT + 1] = reinterpret_cast<float2(*)[CT + 1]>(xs_raw);
-  const int f = blockIdx.y;
-  const int c = threadIdx.x % CT, gq = threadIdx.x / CT;
-  const int sl = blockIdx.x * CT + c;  // source inside this call's chunk
-  const bool sv = sl < cnt;
-  const int n = g.nr;
-  const int nb = cdiv(n, kSb);
-  constexpr int RPT = Tile<CT>::RPT;
-  const float2* L = l32 + (size_t)f * n * n;
-  const float2* Iv = inv + (size_t)f * nb * kSb * kSb;
-  const float2* Rc = R + ((size_t)f * rld + s0 + (sv ? sl : 0)) * n;
-  double2* xc = x64 + ((size_t)f * g.max_ns + (sv ? sl : 0)) * n;
-  // rows owned by this thread: I*32 + gq*RPT + q
-  for (int I = 0; I < nb; ++I)
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = I * kSb + gq * RPT + q;
-      xs[r][c] = (sv && r < n) ? Rc[r] : make_float2(0.f, 0.f);
-    }
-  __syncthreads();
-  tile_solve<CT>(g, L, Iv, xs, c, gq);
-  if (refine > 0) {
-    for (int I = 0; I < nb; ++I)
-#pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        const int r = I * kSb + gq * RPT + q;
-        if (sv && r < n) xc[r] = make_double2((double)xs[r][c].x, (double)xs[r][c].y);
-      }
-    __threadfence_block();
-    __syncthreads();
-    const double2* Q = qhat + (size_t)f * n * n;
-    for (int it = 0; it < refine; ++it) {
-      for (int I = 0; I < nb; ++I)
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          const int r = I * kSb + gq * RPT + q;
-          float2 v = make_float2(0.f, 0.f);
-          if (sv && r < n) {
-            const double2* Qr = Q + (size_t)r * n;
-            double tr = (double)Rc[r].x, ti = (double)Rc[r].y;
-            for (int k = 0; k < n; ++k) {
-              const double2 a = Qr[k], b = xc[k];
-              tr -= a.x * b.x - a.y * b.y;
-              ti -= a.x * b.y + a.y * b.x;
-            }
-            v = make_float2((float)tr, (float)ti);
-          }
-          xs[r][c] = v;
-        }
-      __syncthreads();
-      tile_solve<CT>(g, L, Iv, xs, c, gq);
-      for (int I = 0; I < nb; ++I)
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          const int r = I * kSb + gq * RPT + q;
-          if (sv && r < n) {
-            double2 o = xc[r];
-            o.x += (double)xs[r][c].x;
-            o.y += (double)xs[r][c].y;
-            xc[r] = o;
-          }
-        }
-      __threadfence_block();
-      __syncthreads();
-    }
-  }
-  float2* Oc = out + ((size_t)f * rld + s0 + (sv ? sl : 0)) * n;
-  for (int I = 0; I < nb; ++I)
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = I * kSb + gq * RPT + q;
-      if (sv && r < n) Oc[r] = refine > 0 ? make_float2((float)xc[r].x, (float)xc[r].y) : xs[r][c];
-    }
+template <typename T, int MODE, int EPI>
+hipError_t run_gemm(const GemmArgs& a, int nf, hipStream_t st) {
+  dim3 grid(cdiv(a.ns, kGn), cdiv(a.n, kGm), nf);
+  hipLaunchKernelGGL((k_cgemm<T, MODE, EPI>), grid, dim3(256), 0, st, a);
+  return hipGetLastError();
 }
 
 // Largest eigenvalue of each Hhat(w) by power iteration in FP64 (one workgroup
@@ -305,38 +348,72 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0) eig[f] = lam;
 }
 
+
 }  // namespace
 
 int solve_blocks(const Geometry& g) { return cdiv(g.nr, kSb); }
 
-hipError_t launch_diag_inv_jobs(const FactorJob* jobs, int njobs, int max_nr, hipStream_t st) {
-  if (njobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_diag_inv, dim3(cdiv(max_nr, kSb), njobs), dim3(kSb), 0, st, jobs);
+hipError_t launch_minv_jobs(const FactorJob* jobs, int njobs, int max_nr, hipStream_t st) {
+  const int nb = cdiv(max_nr, kSb);
+  hipLaunchKernelGGL(k_diag_inv, dim3(nb, njobs), dim3(kSb), 0, st, jobs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tri_inv_cols, dim3(nb, njobs), dim3(256), 0, st, jobs);
   return hipGetLastError();
 }
 
-hipError_t launch_apply(const Geometry& g, const float2* l32, const float2* inv,
-                        const double2* qhat, const float2* R, int rld, int s0, int cnt, int refine,
+hipError_t launch_apply(const Geometry& g, const float2* m32, const double2* qhat, const float2* R,
+                        int rld, int s0, int cnt, int refine, float2* y32, float2* r32,
                         double2* x64, float2* out, hipStream_t st) {
-  const int npad = solve_blocks(g) * kSb;
-#define EHI_APPLY(CTV)                                                                          \
-  {                                                                                             \
-    const size_t sh = (size_t)npad * ((CTV) + 1) * sizeof(float2);                              \
-    hipLaunchKernelGGL(k_apply<CTV>, dim3(cdiv(cnt, CTV), g.nf), dim3(256), sh, st, g, l32, inv, \
-                       qhat, R, rld, s0, cnt, refine, x64, out);                                 \
+  const int n = g.nr, np = solve_blocks(g) * kSb;
+  const size_t nn = (size_t)n * n, npp = (size_t)np * np;
+  const size_t sv = (size_t)g.max_ns * n;  // scratch per frequency
+  GemmArgs a{};
+  a.n = n;
+  a.ns = cnt;
+  // Y = M R
+  a.A = m32; a.sA = npp; a.lda = np; a.kmax = np;
+  a.B = R + (size_t)s0 * n; a.sB = (size_t)rld * n; a.ldb = n;
+  a.C = y32; a.sC = sv; a.ldc = n;
+  hipError_t e = run_gemm<float, 1, kEpiStore>(a, g.nf, st);
+  if (e != hipSuccess) return e;
+  // X = M^H Y
+  a.B = y32; a.sB = sv; a.ldb = n;
+  if (refine == 0) {
+    a.C = out + (size_t)s0 * n; a.sC = (size_t)rld * n; a.ldc = n;
+    return run_gemm<float, 2, kEpiStore>(a, g.nf, st);
   }
-  // dynamic LDS npad * (CT + 1) * 8 bytes: <= 64 KiB up to 224 / 448 rows
-  if (npad <= 224) EHI_APPLY(32)
-  else if (npad <= 448) EHI_APPLY(16)
-  else {
-    // once per process (thread-safe static initialisation)
-    static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&k_apply<8>), hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
-    if (attr != hipSuccess) return attr;
-    EHI_APPLY(8)
+  a.X = x64; a.sX = sv; a.ldx = n;
+  e = run_gemm<float, 2, kEpiX64Set>(a, g.nf, st);
+  if (e != hipSuccess) return e;
+  for (int it = 0; it < refine; ++it) {
+    // r = R - Qhat X (FP64)
+    GemmArgs q = a;
+    q.A = qhat; q.sA = nn; q.lda = n; q.kmax = n;
+    q.B = x64; q.sB = sv; q.ldb = n;
+    q.R = R + (size_t)s0 * n; q.sR = (size_t)rld * n; q.ldr = n;
+    q.C = r32; q.sC = sv; q.ldc = n;
+    e = run_gemm<double, 0, kEpiResid>(q, g.nf, st);
+    if (e != hipSuccess) return e;
+    // Y = M r
+    GemmArgs y = a;
+    y.A = m32; y.sA = npp; y.lda = np; y.kmax = np;
+    y.B = r32; y.sB = sv; y.ldb = n;
+    y.C = y32; y.sC = sv; y.ldc = n;
+    e = run_gemm<float, 1, kEpiStore>(y, g.nf, st);
+    if (e != hipSuccess) return e;
+    // X += M^H Y (the last step writes the complex64 result)
+    GemmArgs x = y;
+    x.B = y32;
+    if (it + 1 < refine) {
+      e = run_gemm<float, 2, kEpiX64Add>(x, g.nf, st);
+    } else {
+      x.C = out + (size_t)s0 * n; x.sC = (size_t)rld * n; x.ldc = n;
+      e = run_gemm<float, 2, kEpiOut>(x, g.nf, st);
+    }
+    if (e != hipSuccess) return e;
   }
-#undef EHI_APPLY
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 hipError_t launch_power_iter(const Geometry& g, const double2* hhat, double* eig, int iters,
