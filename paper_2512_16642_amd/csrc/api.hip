@@ -142,7 +142,6 @@ ehi::Layout make_layout(const ehi::Geometry& g) {
   L.w1 = take(sizeof(float) * g.plane() * g.nrb);
   L.stage = take(sizeof(float) * (size_t)g.nrb * g.chunk * g.nsub_p);
   L.ghat = take(sizeof(float2) * (size_t)g.nf * g.nr * g.nsub);
-  L.planes = take(g.split_bf16 ? sizeof(uint4) * 4 * (size_t)g.nf * g.nr * ehi::cdiv(g.nsub, 8) : 0);
   L.hpart = take(sizeof(float2) * (size_t)g.herk_split * g.nf * nn);
   L.hhat = take(sizeof(double2) * g.nf * nn);
   L.qhat = take(sizeof(double2) * g.nf * nn);
@@ -376,14 +375,12 @@ ehi_status ehi_build_hessian(ehi_survey* s) {
   float2* hpart = s->ptr<float2>(L.hpart);
   PROF(EHI_PROF_HERK, s->stream);
   if (s->precision == EHI_PREC_SPLIT_BF16) {
-    uint4* planes = s->ptr<uint4>(L.planes);
-    EHI_TRY(ehi::launch_split_planes(g, s->ptr<float2>(L.ghat), planes, s->stream), "split planes");
-    EHI_TRY(ehi::launch_herk_split_bf16(g, planes, hpart, s->stream), "herk bf16");
+    EHI_TRY(ehi::launch_herk_split_bf16(g, s->ptr<float2>(L.ghat), hpart, s->stream), "herk bf16");
   } else {
     EHI_TRY(ehi::launch_herk_fp32(g, s->ptr<float2>(L.ghat), hpart, s->stream), "herk fp32");
   }
   EHI_TRY(ehi::launch_herk_reduce(g, hpart, s->ptr<double2>(L.hhat), s->stream), "herk reduce");
-  PROF_N(s->precision == EHI_PREC_SPLIT_BF16 ? 3 : 2);
+  PROF_N(2);
   PROF_END();
   s->state = ehi::State::Hessian;
   return EHI_OK;

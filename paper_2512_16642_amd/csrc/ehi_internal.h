@@ -33,7 +33,7 @@ struct Geometry {
   int chunk;       // time samples per DFT chunk (staging depth; multiple of 4 and tblock)
   int nt, nr, nf, nrb, max_ns;
   int herk_split;  // split-K partitions
-  int split_bf16;  // 1: split-BF16 contraction (hi/lo planes kept), 0: plain FP32
+  int split_bf16;  // 1: split-BF16 contraction, 0: plain FP32
   int tblock;      // time levels per marching launch (2, 4 or 8; divides chunk)
   int seg_rows;    // output rows per marching segment
   int band;        // columns per marching workgroup (256, 384, 448 or 512)
@@ -55,7 +55,6 @@ struct Layout {
   size_t w0, w1;    // float [nrb][Zp][Xp]  (ping-pong)
   size_t stage;     // float [nrb][chunk][nsub_p]
   size_t ghat;      // float2 [nf][nr][nsub]
-  size_t planes;    // uint4 [nf][nr][cdiv(nsub, 8)][4]  BF16 hi/lo planes of ghat (split form)
   size_t hpart;     // float2 [split][nf][nr][nr]
   size_t hhat;      // double2 [nf][nr][nr]
   size_t qhat;      // double2 [nf][nr][nr]   Hhat + mu I (Hermitian, full)
@@ -163,8 +162,7 @@ hipError_t launch_dft_chunk(const Geometry& g, const float* stage, const float2*
                             int cnt, bool first, int r0, int nrb_now, float2* ghat,
                             hipStream_t st);
 hipError_t launch_herk_fp32(const Geometry& g, const float2* ghat, float2* hpart, hipStream_t st);
-hipError_t launch_split_planes(const Geometry& g, const float2* ghat, uint4* planes, hipStream_t st);
-hipError_t launch_herk_split_bf16(const Geometry& g, const uint4* planes, float2* hpart,
+hipError_t launch_herk_split_bf16(const Geometry& g, const float2* ghat, float2* hpart,
                                   hipStream_t st);
 hipError_t launch_herk_reduce(const Geometry& g, const float2* hpart, double2* hhat,
                               hipStream_t st);

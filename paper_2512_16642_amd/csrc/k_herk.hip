@@ -115,53 +115,19 @@ __global__ void __launch_bounds__(256)
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kBt = 64;  // H tile (rows = cols)
 constexpr int kBk = 32;  // grid points per stage (four groups of 8)
 constexpr int kXcd = 8;  // XCDs per device
 
-__device__ __forceinline__ unsigned short bf16_rne(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
-// BF16 hi/lo planes of the spectra, written once per build: planes[f][r][c][q]
-// holds points 8c .. 8c + 7 of plane q (0 = Re hi, 1 = Re lo, 2 = Im hi,
-// 3 = Im lo) as one 16-byte fragment; points beyond nsub are zero.  Every FP32
-// value x is split as hi = bf16(x), lo = bf16(x - hi), both rounded to nearest
-// even.
+// VEC: every row of ghat starts 16-byte aligned (nsub even), so 8 points load
+// as four 16-byte loads.  Every FP32 value x is split as hi = bf16(x),
+// lo = bf16(x - hi), both rounded to nearest even by the hardware conversion.
+template <bool VEC>
 __global__ void __launch_bounds__(256)
-    k_split_planes(Geometry g, const float2* __restrict__ ghat, u32x4* __restrict__ planes) {
-  const int ngrp = cdiv(g.nsub, 8);
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (size_t)g.nf * g.nr * ngrp) return;
-  const size_t row = e / ngrp;  // f * nr + r
-  const int c = (int)(e % ngrp);
-  const float2* src = ghat + row * g.nsub + 8 * c;
-  unsigned w[4][4];
-#pragma unroll
-  for (int p = 0; p < 8; p += 2) {
-    unsigned short h[4][2];
-#pragma unroll
-    for (int d = 0; d < 2; ++d) {
-      const float2 z = 8 * c + p + d < g.nsub ? src[p + d] : make_float2(0.f, 0.f);
-      h[0][d] = bf16_rne(z.x);
-      h[1][d] = bf16_rne(z.x - bf16_to_f(h[0][d]));
-      h[2][d] = bf16_rne(z.y);
-      h[3][d] = bf16_rne(z.y - bf16_to_f(h[2][d]));
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) w[q][p >> 1] = (unsigned)h[q][0] | ((unsigned)h[q][1] << 16);
-  }
-  u32x4* dst = planes + e * 4;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) dst[q] = u32x4{w[q][0], w[q][1], w[q][2], w[q][3]};
-}
-
-__global__ void __launch_bounds__(256)
-    k_herk_bf16(Geometry g, const u32x4* __restrict__ planes, float2* __restrict__ hpart, int split) {
+    k_herk_bf16(Geometry g, const float2* __restrict__ ghat, float2* __restrict__ hpart, int split) {
   // planes: 0 = Re hi, 1 = Re lo, 2 = Im hi, 3 = Im lo; rows 0..63 i-block, 64..127 j-block
   __shared__ u32x4 pl[2][4][kBk / 8][2 * kBt];
   const int nblk = cdiv(g.nr, kBt);
@@ -186,10 +152,10 @@ __global__ void __launch_bounds__(256)
   const int kchunk = cdiv(cdiv(g.nsub, split), kBk) * kBk;
   const int k0 = ks * kchunk;
   const int k1 = min(g.nsub, k0 + kchunk);
-  const int ngrp = cdiv(g.nsub, 8);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
+  const float2* G = ghat + (size_t)f * g.nr * g.nsub;
 
   floatx4 re[2][2], im[2][2];
 #pragma unroll
@@ -201,23 +167,45 @@ __global__ void __launch_bounds__(256)
   const int lrow = tid & (2 * kBt - 1);
   const int grow = lrow < kBt ? bi * kBt + lrow : bj * kBt + (lrow - kBt);
   const bool rowv = grow < g.nr;
-  const u32x4* Prow = planes + ((size_t)f * g.nr + (rowv ? grow : 0)) * ngrp * 4;
-  u32x4 v[2][4];
+  const float2* Grow = G + (size_t)(rowv ? grow : 0) * g.nsub;
+  float2 v[2][8];
   auto gload = [&](int kb) {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-      const int c = kb / 8 + (tid >> 7) + 2 * p;  // group; groups past k1 hold zeros or lie in
-      const bool ok = rowv && 8 * c < k1;         // the next partition (masked here)
+      const int k = kb + 8 * ((tid >> 7) + 2 * p);
+      if (VEC && rowv && k + 8 <= k1) {
+        const floatx4* src = reinterpret_cast<const floatx4*>(Grow + k);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[p][q] = ok ? Prow[(size_t)c * 4 + q] : u32x4{0u, 0u, 0u, 0u};
+        for (int e = 0; e < 4; ++e) {
+          const floatx4 q = src[e];
+          v[p][2 * e] = make_float2(q[0], q[1]);
+          v[p][2 * e + 1] = make_float2(q[2], q[3]);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[p][e] = (rowv && k + e < k1) ? Grow[k + e] : make_float2(0.f, 0.f);
+      }
     }
   };
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       const int grp = (tid >> 7) + 2 * p;
+      unsigned w[4][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) pl[buf][q][grp][lrow] = v[p][q];
+      for (int e = 0; e < 8; e += 2) {
+        const float2 z0 = v[p][e], z1 = v[p][e + 1];
+        const bf16x2 rh = {(__bf16)z0.x, (__bf16)z1.x};
+        const bf16x2 ih = {(__bf16)z0.y, (__bf16)z1.y};
+        const bf16x2 rl = {(__bf16)(z0.x - (float)rh[0]), (__bf16)(z1.x - (float)rh[1])};
+        const bf16x2 il = {(__bf16)(z0.y - (float)ih[0]), (__bf16)(z1.y - (float)ih[1])};
+        w[0][e >> 1] = __builtin_bit_cast(unsigned, rh);
+        w[1][e >> 1] = __builtin_bit_cast(unsigned, rl);
+        w[2][e >> 1] = __builtin_bit_cast(unsigned, ih);
+        w[3][e >> 1] = __builtin_bit_cast(unsigned, il);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) pl[buf][q][grp][lrow] = u32x4{w[q][0], w[q][1], w[q][2], w[q][3]};
     }
   };
 
@@ -323,21 +311,15 @@ int herk_bf16_blocks(const Geometry& g) {
   return nb * (nb + 1) / 2;
 }
 
-hipError_t launch_split_planes(const Geometry& g, const float2* ghat, uint4* planes, hipStream_t st) {
-  const size_t n = (size_t)g.nf * g.nr * cdiv(g.nsub, 8);
-  const size_t blocks = (n + 255) / 256;
-  if (blocks > 0x7fffffffULL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_split_planes, dim3((unsigned)blocks), dim3(256), 0, st, g, ghat,
-                     reinterpret_cast<u32x4*>(planes));
-  return hipGetLastError();
-}
-
-hipError_t launch_herk_split_bf16(const Geometry& g, const uint4* planes, float2* hpart,
+hipError_t launch_herk_split_bf16(const Geometry& g, const float2* ghat, float2* hpart,
                                   hipStream_t st) {
   const long long items = (long long)herk_bf16_blocks(g) * g.herk_split * g.nf;
   if (items > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_herk_bf16, dim3((unsigned)items), dim3(256), 0, st, g,
-                     reinterpret_cast<const u32x4*>(planes), hpart, g.herk_split);
+  dim3 grid((unsigned)items);
+  if (g.nsub % 2 == 0)
+    hipLaunchKernelGGL(k_herk_bf16<true>, grid, dim3(256), 0, st, g, ghat, hpart, g.herk_split);
+  else
+    hipLaunchKernelGGL(k_herk_bf16<false>, grid, dim3(256), 0, st, g, ghat, hpart, g.herk_split);
   return hipGetLastError();
 }
 
