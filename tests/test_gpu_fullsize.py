@@ -109,6 +109,22 @@ def test_full_solve_backward_error(full):
         assert berr < 1e-6, (f, berr)
 
 
+def test_full_plain_form_solve_error(ehi, full):
+    # the same Hessian solved by the plain FP32 form (FP32 Cholesky, no
+    # refinement) against the split form's refined solve, whose backward error
+    # is < 1e-6 (test above): isolates the solve error of each form at full size
+    s = full["s"]
+    sp = ehi.survey_from(s, precision="plain_fp32")
+    sp.load_hessian(full["H"])
+    sp.factor(full["mu"])
+    Xp = sp.apply_multipliers(full["R"]).cpu().numpy()
+    sp.close()
+    X = full["X"].cpu().numpy()
+    errs = [rel(Xp[f], X[f]) for f in range(s.nf)]
+    print("full-size plain-form solve vs refined solve: max", max(errs), "min", min(errs))
+    assert max(errs) < 1e-1
+
+
 def test_full_grid_two_receiver_survey_end_to_end(ehi, full, oracle_sample):
     s = full["s"].with_(rec_iz=tuple(full["s"].rec_iz[k] for k in SAMPLE),
                         rec_ix=tuple(full["s"].rec_ix[k] for k in SAMPLE))
@@ -125,3 +141,13 @@ def test_full_grid_two_receiver_survey_end_to_end(ehi, full, oracle_sample):
     errs = [rel(X[f], Xr[f]) for f in range(s.nf)]
     print("full-grid 2-receiver multipliers rel err: max", max(errs))
     assert max(errs) < 1e-5
+    # the plain FP32 form on the same survey (recorded for the comparison)
+    sp = ehi.survey_from(s, precision="plain_fp32")
+    sp.build_green(torch.from_numpy(full["v"]).cuda())
+    sp.build_hessian()
+    sp.factor(mu)
+    Xp = sp.apply_multipliers(torch.from_numpy(R).cuda()).cpu().numpy()
+    sp.close()
+    errs_p = [rel(Xp[f], Xr[f]) for f in range(s.nf)]
+    print("full-grid 2-receiver plain-form multipliers rel err: max", max(errs_p))
+    assert max(errs_p) < 1e-2

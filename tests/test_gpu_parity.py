@@ -183,6 +183,21 @@ def test_end_to_end_tiny(ehi, tiny_ref):
     assert max(errs) < 1e-5
 
 
+def test_end_to_end_tiny_plain_form(ehi, tiny_ref):
+    # the plain FP32 form (FP32 contraction, FP32 Cholesky, no refinement): its
+    # error is bounded by cond(Qhat) * 2^-24-sized terms, far looser than the
+    # split form's; recorded for the comparison of the two forms
+    s = tiny_ref["s"]
+    sv = ehi.survey_from(s, precision="plain_fp32")
+    sv.build_green(dev(tiny_ref["v"]))
+    sv.build_hessian()
+    sv.factor(tiny_ref["mu"])
+    X = sv.apply_multipliers(dev(tiny_ref["R"])).cpu().numpy()
+    errs = per_freq_rel(X, tiny_ref["X"])
+    print("plain-form end-to-end multipliers rel err per freq", errs)
+    assert max(errs) < 1e-2
+
+
 def test_lambda_max(ehi, tiny_ref):
     s = tiny_ref["s"]
     sv = ehi.survey_from(s)
