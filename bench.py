@@ -29,10 +29,10 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per marching launch measured with rocprofv3 (FETCH_SIZE x 2 +
 # WRITE_SIZE x 1 KiB, scales from a 1 GiB copy), keyed by (workload,
-# precision, time levels, segment rows, receivers per launch); recorded in
+# precision, time levels, segment rows, band width, receivers per launch); recorded in
 # profiles/survey_layered-1000x300_pmc.md.  Any other shape reports null.
 MEASURED_TRAFFIC = {
-    ("layered-1000x300-nr200-nt4000-nf30-ns200", "split_bf16", 8, 128, 200): (465320.5 * 2 + 1152724.8) * 1024,
+    ("layered-1000x300-nr200-nt4000-nf30-ns200", "split_bf16", 8, 128, 256, 200): (461812.5 * 2 + 1152341.5) * 1024,
 }
 
 
@@ -335,7 +335,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": MEASURED_TRAFFIC.get((s.name, args.precision, tblock, seg_rows, nrb)),
+        "traffic": MEASURED_TRAFFIC.get((s.name, args.precision, tblock, seg_rows, band, nrb)),
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "avg_launch_us": round(avg_step_s * 1e6, 2),
         "bytes_per_launch": round(bytes_launch),
