@@ -157,8 +157,10 @@ __global__ void __launch_bounds__(256) k_tri_inv_cols(const FactorJob* __restric
 // MODE 2: M^H, i.e. A(i, k) = conj(M(k, i)).  Tiles of M that are zero by
 // triangularity are skipped.  B(k, j) = Bm[j * ldb + k] (source-major, as the
 // residuals are stored), read as zero for k >= n.
-// Workgroup: a 64 x 64 tile of C, each thread a 4 x 4 register tile; K in
-// stages of 16 through LDS.
+// Workgroup: a 64 x 64 tile of C, each thread a 4 x 4 register tile (rows
+// 4 ty + r, columns 4 tx + c); K in stages of 16 through LDS.  The LDS tiles
+// keep the register-tile index outermost (entry r * 16 + ty, c * 16 + tx), so
+// the lanes of a half-wave read consecutive elements.
 enum { kEpiStore = 0, kEpiResid = 1, kEpiX64Set = 2, kEpiX64Add = 3, kEpiOut = 4 };
 
 struct GemmArgs {
@@ -219,24 +221,24 @@ __global__ void __launch_bounds__(256) k_cgemm(GemmArgs a) {
           const C2 m = A[(size_t)gk * a.lda + gi];
           v = C2{m.x, -m.y};
         }
-        As[kk][ii] = v;
+        As[kk][(ii & 3) * 16 + (ii >> 2)] = v;
       } else {
         const int ii = e / kGk, kk = e % kGk;          // contiguous along k
         const int gk = k0 + kk, gi = i0 + ii;
-        As[kk][ii] = (gk < kend && gi < a.kmax) ? A[(size_t)gi * a.lda + gk] : C2{0, 0};
+        As[kk][(ii & 3) * 16 + (ii >> 2)] = (gk < kend && gi < a.kmax) ? A[(size_t)gi * a.lda + gk] : C2{0, 0};
       }
       const int jj = e / kGk, kk = e % kGk;
       const int gk = k0 + kk, gj = j0 + jj;
-      Bs[kk][jj] = (gk < kend && gj < a.ns) ? B[(size_t)gj * a.ldb + gk] : C2{0, 0};
+      Bs[kk][(jj & 3) * 16 + (jj >> 2)] = (gk < kend && gj < a.ns) ? B[(size_t)gj * a.ldb + gk] : C2{0, 0};
     }
     __syncthreads();
 #pragma unroll 4
     for (int kk = 0; kk < kGk; ++kk) {
       C2 av[4], bv[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) av[r] = As[kk][ty * 4 + r];
+      for (int r = 0; r < 4; ++r) av[r] = As[kk][r * 16 + ty];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][tx * 4 + c];
+      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][c * 16 + tx];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
