@@ -66,6 +66,20 @@ typedef enum {
   EHI_PREC_SPLIT_BF16 = 1
 } ehi_precision;
 
+/* Weighting of the time-domain cross-correlations in the Fourier diagonals
+ * (the weighting function of the algorithm for the Fourier block-diagonal
+ * Hessian). */
+typedef enum {
+  /* W constant (long-record limit): Hhat(w) = Ghat(w) Ghat(w)^H with the final
+     spectra (sum over the subgrid) */
+  EHI_WEIGHT_LONG_RECORD = 0,
+  /* W(m, n) = min(Nt - m, Nt - n): Hhat(w) = (1/Nt) sum_{p=1}^{Nt}
+     Ghat_p(w) Ghat_p(w)^H, Ghat_p the DFT truncated after sample p.
+     Requires EHI_PREC_SPLIT_BF16 and all receivers stepped together
+     (nr_batch 0 or >= nr); computed during ehi_build_green. */
+  EHI_WEIGHT_FINITE_RECORD = 1
+} ehi_weighting;
+
 /*
  * Survey descriptor.  Host memory; copied by ehi_create.
  *   nz, nx    interior grid, row-major [nz][nx], z pointing down.  >= 4 each.
@@ -85,6 +99,7 @@ typedef enum {
  *             calls are split.  Sizes the refinement scratch.  >= 1.
  *   nr_batch  receivers time-stepped together (0 = all).  Sizes the
  *             wavefield buffers.
+ *   weighting an ehi_weighting value.
  */
 typedef struct {
   int32_t nz, nx, nb;
@@ -99,6 +114,7 @@ typedef struct {
   int32_t precision;
   int32_t max_ns;
   int32_t nr_batch;
+  int32_t weighting;
 } ehi_survey_desc;
 
 typedef struct ehi_survey ehi_survey;
@@ -184,7 +200,8 @@ ehi_status ehi_lambda_max(ehi_survey* s, double* out);
 ehi_status ehi_copy_green_dft(ehi_survey* s, void* out_dev);
 
 /* Replaces Ghat by the caller's complex64 [nf][nr][nzs][nxs] device array, so
- * the later stages can be run on given spectra.  Asynchronous. */
+ * the later stages can be run on given spectra.  Asynchronous.  EHI_ESTATE for
+ * a finite-record survey (its Hessian needs the time samples). */
 ehi_status ehi_load_green_dft(ehi_survey* s, const void* in_dev);
 
 /* Copies Hhat (no penalty), complex128 [nf][nr][nr] (full Hermitian), to

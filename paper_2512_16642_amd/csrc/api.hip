@@ -59,6 +59,13 @@ bool validate(const ehi_survey_desc* d, std::string* why) {
     return bad("unknown precision mode");
   if (d->max_ns < 1 || d->max_ns > (1 << 20)) return bad("max_ns must be in [1, 2^20]");
   if (d->nr_batch < 0) return bad("nr_batch must be >= 0");
+  if (d->weighting != EHI_WEIGHT_LONG_RECORD && d->weighting != EHI_WEIGHT_FINITE_RECORD)
+    return bad("unknown weighting");
+  if (d->weighting == EHI_WEIGHT_FINITE_RECORD) {
+    if (d->precision != EHI_PREC_SPLIT_BF16) return bad("the finite-record weighting needs the split-BF16 form");
+    if (d->nr_batch != 0 && d->nr_batch < d->nr)
+      return bad("the finite-record weighting needs all receivers stepped together");
+  }
   long long Z = (long long)d->nz + 2LL * d->nb, X = (long long)d->nx + 2LL * d->nb;
   // buffer resources address one plane / one staging block with 31-bit byte offsets
   if ((Z + 4) * (X + 4 + ehi::kRowAlign) > (1LL << 28)) return bad("grid too large");
@@ -91,6 +98,7 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   g.h = d->h;
   g.dt = d->dt;
   g.split_bf16 = d->precision == EHI_PREC_SPLIT_BF16 ? 1 : 0;
+  g.weighting = d->weighting;
   int ntile = ehi::cdiv(g.nr, g.split_bf16 ? 64 : ehi::kHerkTile);
   int pairs = ntile * (ntile + 1) / 2;
   int want = ehi::cdiv(2048, pairs * g.nf);
@@ -143,6 +151,7 @@ ehi::Layout make_layout(const ehi::Geometry& g) {
   L.stage = take(sizeof(float) * (size_t)g.nrb * g.chunk * g.nsub_p);
   L.ghat = take(sizeof(float2) * (size_t)g.nf * g.nr * g.nsub);
   L.hpart = take(sizeof(float2) * (size_t)g.herk_split * g.nf * nn);
+  L.hpart64 = take(g.weighting == EHI_WEIGHT_FINITE_RECORD ? sizeof(double2) * (size_t)g.herk_split * g.nf * nn : 0);
   L.hhat = take(sizeof(double2) * g.nf * nn);
   L.qhat = take(sizeof(double2) * g.nf * nn);
   L.lfac = take(sizeof(double2) * g.nf * nn);
@@ -344,6 +353,14 @@ ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev) {
     for (;;) {
       if (n_cur % g.chunk == 0 || n_cur == g.nt) {
         const int n0 = (n_cur - 1) / g.chunk * g.chunk + 1;
+        if (g.weighting == EHI_WEIGHT_FINITE_RECORD) {
+          // the running spectra of this window, before the DFT advances them
+          PROF(EHI_PROF_HERK, st);
+          EHI_TRY(ehi::launch_herk_r2_chunk(g, stage, tw, ghat, n0, n_cur - n0 + 1, n0 == 1,
+                                            s->ptr<double2>(L.hpart64), st),
+                  "finite-record contraction");
+          PROF_N(1);
+        }
         PROF(EHI_PROF_DFT, st);
         EHI_TRY(ehi::launch_dft_chunk(g, stage, tw, n0, n_cur - n0 + 1, n0 == 1, r0, nb_now, ghat, st),
                 "dft chunk");
@@ -374,6 +391,15 @@ ehi_status ehi_build_hessian(ehi_survey* s) {
   const ehi::Layout& L = s->L;
   float2* hpart = s->ptr<float2>(L.hpart);
   PROF(EHI_PROF_HERK, s->stream);
+  if (g.weighting == EHI_WEIGHT_FINITE_RECORD) {
+    // accumulated during build_green; only the reduction remains
+    EHI_TRY(ehi::launch_herk_r2_reduce(g, s->ptr<double2>(L.hpart64), s->ptr<double2>(L.hhat), s->stream),
+            "finite-record reduce");
+    PROF_N(1);
+    PROF_END();
+    s->state = ehi::State::Hessian;
+    return EHI_OK;
+  }
   if (s->precision == EHI_PREC_SPLIT_BF16) {
     EHI_TRY(ehi::launch_herk_split_bf16(g, s->ptr<float2>(L.ghat), hpart, s->stream), "herk bf16");
   } else {
@@ -577,6 +603,8 @@ ehi_status ehi_copy_green_dft(ehi_survey* s, void* out_dev) {
 ehi_status ehi_load_green_dft(ehi_survey* s, const void* in_dev) {
   g_err.clear();
   if (!s || !in_dev) return fail(EHI_EINVAL, "NULL argument");
+  if (s->g.weighting == EHI_WEIGHT_FINITE_RECORD)
+    return fail(EHI_ESTATE, "the finite-record weighting is built from the time samples (ehi_build_green)");
   size_t bytes = sizeof(float2) * (size_t)s->g.nf * s->g.nr * s->g.nsub;
   EHI_TRY(hipMemcpyAsync(s->ws + s->L.ghat, in_dev, bytes, hipMemcpyDeviceToDevice, s->stream),
           "load green");

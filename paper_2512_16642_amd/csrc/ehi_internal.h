@@ -34,6 +34,7 @@ struct Geometry {
   int nt, nr, nf, nrb, max_ns;
   int herk_split;  // split-K partitions
   int split_bf16;  // 1: split-BF16 contraction, 0: plain FP32
+  int weighting;   // EHI_WEIGHT_LONG_RECORD or EHI_WEIGHT_FINITE_RECORD
   int tblock;      // time levels per marching launch (2, 4 or 8; divides chunk)
   int seg_rows;    // output rows per marching segment
   int band;        // columns per marching workgroup (256, 384, 448 or 512)
@@ -56,6 +57,7 @@ struct Layout {
   size_t stage;     // float [nrb][chunk][nsub_p]
   size_t ghat;      // float2 [nf][nr][nsub]
   size_t hpart;     // float2 [split][nf][nr][nr]
+  size_t hpart64;   // double2 [split][nf][nr][nr]  finite-record partial sums (else empty)
   size_t hhat;      // double2 [nf][nr][nr]
   size_t qhat;      // double2 [nf][nr][nr]   Hhat + mu I (Hermitian, full)
   size_t lfac;      // double2 [nf][nr][nr]   lower Cholesky factor (FP64 mode)
@@ -164,6 +166,11 @@ hipError_t launch_dft_chunk(const Geometry& g, const float* stage, const float2*
 hipError_t launch_herk_fp32(const Geometry& g, const float2* ghat, float2* hpart, hipStream_t st);
 hipError_t launch_herk_split_bf16(const Geometry& g, const float2* ghat, float2* hpart,
                                   hipStream_t st);
+hipError_t launch_herk_r2_chunk(const Geometry& g, const float* stage, const float2* tw,
+                                const float2* ghat, int n0, int cnt, bool first, double2* hpart64,
+                                hipStream_t st);
+hipError_t launch_herk_r2_reduce(const Geometry& g, const double2* hpart64, double2* hhat,
+                                 hipStream_t st);
 hipError_t launch_herk_reduce(const Geometry& g, const float2* hpart, double2* hhat,
                               hipStream_t st);
 hipError_t launch_factor_jobs(const FactorJob* jobs, int njobs, hipStream_t st);

@@ -273,6 +273,215 @@ __global__ void __launch_bounds__(256)
       }
 }
 
+// Finite-record weighting (the paper's weighting function W(m, n) =
+// min(Nt - m, Nt - n) in the algorithm for the Fourier block-diagonal Hessian):
+// Hhat_W(w) = (1/Nt) sum_{p=1}^{Nt} Ghat_p(w) Ghat_p(w)^H, Ghat_p the DFT
+// truncated after sample p.  One launch per staging window (samples
+// n0 .. n0 + cnt - 1), before the DFT advances the spectra: a workgroup owns one
+// (frequency, 64 x 64 tile pair, grid partition); for every 32-point block of
+// its partition it starts from the running spectrum Ghat_{n0-1} (zero for the
+// first window), adds one staged sample times its twiddle per step, and after
+// every step contracts the running spectra of its 128 rows exactly as the
+// final-spectrum contraction does (hi/lo BF16 planes, four products, 32-point
+// MFMA chains from zero).  Sums: 16 steps in FP32, then in FP64 over steps,
+// blocks and windows (hpart64, read-modify-written by the one workgroup that
+// owns the entry).  All receivers must be stepped together.
+__global__ void __launch_bounds__(256)
+    k_herk_r2(Geometry g, const float* __restrict__ stage, const float2* __restrict__ tw,
+              const float2* __restrict__ ghat, int n0, int cnt, int first,
+              double2* __restrict__ hpart64) {
+  __shared__ u32x4 pl[2][4][kBk / 8][2 * kBt];
+  const int nblk = cdiv(g.nr, kBt);
+  const int npair = nblk * (nblk + 1) / 2;
+  const int split = g.herk_split;
+  // XCD-aware work item; the frequency varies fastest, so the workgroups that
+  // read the same staged rows share an XCD's L2
+  const int n = blockIdx.x;
+  const int n8 = gridDim.x / kXcd * kXcd;
+  const int item = n < n8 ? (n % kXcd) * (n8 / kXcd) + n / kXcd : n;
+  const int f = item % g.nf;
+  const int rest = item / g.nf;
+  int bi, bj;
+  {
+    int p = rest % npair, i = 0;
+    while (p >= nblk - i) {
+      p -= nblk - i;
+      ++i;
+    }
+    bi = i;
+    bj = i + p;
+  }
+  const int ks = rest / npair;
+  const int kchunk = cdiv(cdiv(g.nsub, split), kBk) * kBk;
+  const int k0 = ks * kchunk;
+  const int k1 = min(g.nsub, k0 + kchunk);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int lrow = tid & (2 * kBt - 1);
+  const int grow = lrow < kBt ? bi * kBt + lrow : bj * kBt + (lrow - kBt);
+  const bool rowv = grow < g.nr;
+  const float2* Gprev = ghat + ((size_t)f * g.nr + (rowv ? grow : 0)) * g.nsub;
+  const float* Srow = stage + (size_t)(rowv ? grow : 0) * g.chunk * g.nsub_p;
+  const int fr = lane & 15, fg = lane >> 4;
+
+  double acc[2][2][2][4];  // [a][b][re/im][v], FP64 over blocks (and windows via hpart64)
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int v4 = 0; v4 < 4; ++v4) acc[a][b][c][v4] = 0.0;
+
+  for (int kb = k0; kb < k1; kb += kBk) {
+    // running spectra of this thread's two 8-point groups
+    float2 S[2][8];
+    int kx[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      kx[p] = kb + 8 * ((tid >> 7) + 2 * p);
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        S[p][e] = (!first && rowv && kx[p] + e < k1) ? Gprev[kx[p] + e] : make_float2(0.f, 0.f);
+    }
+    floatx4 grp[2][2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) grp[a][b][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < cnt; ++t) {
+      const int buf = t & 1;
+      const float2 w = tw[(size_t)(n0 - 1 + t) * g.nf + f];
+      // add sample n0 + t and publish the hi/lo planes of the running spectra
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const float* src = Srow + (size_t)t * g.nsub_p + kx[p];
+        const floatx4 q0 = *reinterpret_cast<const floatx4*>(src);
+        const floatx4 q1 = *reinterpret_cast<const floatx4*>(src + 4);
+        const float gv[8] = {q0[0], q0[1], q0[2], q0[3], q1[0], q1[1], q1[2], q1[3]};
+        unsigned wd[4][4];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float x = (rowv && kx[p] + e < k1) ? gv[e] : 0.f;
+          S[p][e].x = fmaf(w.x, x, S[p][e].x);
+          S[p][e].y = fmaf(w.y, x, S[p][e].y);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; e += 2) {
+          const float2 z0 = S[p][e], z1 = S[p][e + 1];
+          const bf16x2 rh = {(__bf16)z0.x, (__bf16)z1.x};
+          const bf16x2 ih = {(__bf16)z0.y, (__bf16)z1.y};
+          const bf16x2 rl = {(__bf16)(z0.x - (float)rh[0]), (__bf16)(z1.x - (float)rh[1])};
+          const bf16x2 il = {(__bf16)(z0.y - (float)ih[0]), (__bf16)(z1.y - (float)ih[1])};
+          wd[0][e >> 1] = __builtin_bit_cast(unsigned, rh);
+          wd[1][e >> 1] = __builtin_bit_cast(unsigned, rl);
+          wd[2][e >> 1] = __builtin_bit_cast(unsigned, ih);
+          wd[3][e >> 1] = __builtin_bit_cast(unsigned, il);
+        }
+        const int gq = (tid >> 7) + 2 * p;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pl[buf][q][gq][lrow] = u32x4{wd[q][0], wd[q][1], wd[q][2], wd[q][3]};
+      }
+      __syncthreads();
+      bf16x8 ai[2][4], aj[2][4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          ai[a][q] = __builtin_bit_cast(bf16x8, pl[buf][q][fg][wi * 32 + a * 16 + fr]);
+          aj[a][q] = __builtin_bit_cast(bf16x8, pl[buf][q][fg][kBt + wj * 32 + a * 16 + fr]);
+        }
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const u32x4 sgn = u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+        const bf16x8 nrh = __builtin_bit_cast(bf16x8, __builtin_bit_cast(u32x4, ai[a][0]) ^ sgn);
+        const bf16x8 nrl = __builtin_bit_cast(bf16x8, __builtin_bit_cast(u32x4, ai[a][1]) ^ sgn);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          floatx4 r = floatx4{0.f, 0.f, 0.f, 0.f}, m = floatx4{0.f, 0.f, 0.f, 0.f};
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][0], aj[b][0], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][0], aj[b][1], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][1], aj[b][0], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][1], aj[b][1], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][2], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][3], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][2], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][3], r, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][0], m, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][1], m, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][0], m, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][1], m, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrh, aj[b][2], m, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrh, aj[b][3], m, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrl, aj[b][2], m, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrl, aj[b][3], m, 0, 0, 0);
+          grp[a][b][0] += r;
+          grp[a][b][1] += m;
+        }
+      }
+      if ((t & 15) == 15 || t == cnt - 1) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+#pragma unroll
+              for (int v4 = 0; v4 < 4; ++v4) acc[a][b][c][v4] += (double)grp[a][b][c][v4];
+              grp[a][b][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+      }
+    }
+    __syncthreads();  // the next block overwrites both LDS buffers
+  }
+  double2* out = hpart64 + ((size_t)ks * g.nf + f) * g.nr * g.nr;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v4 = 0; v4 < 4; ++v4) {
+        const int i = bi * kBt + wi * 32 + a * 16 + 4 * (lane >> 4) + v4;
+        const int j = bj * kBt + wj * 32 + b * 16 + (lane & 15);
+        if (i < g.nr && j < g.nr) {
+          double2* o = out + (size_t)i * g.nr + j;
+          double2 v = first ? make_double2(0.0, 0.0) : *o;
+          v.x += acc[a][b][0][v4];
+          v.y += acc[a][b][1][v4];
+          *o = v;
+        }
+      }
+}
+
+// hhat = (1/nt) sum_ks hpart64[ks] (FP64, ascending ks), mirrored, Im(diag) = 0.
+__global__ void k_herk_r2_reduce(Geometry g, const double2* __restrict__ hpart64,
+                                 double2* __restrict__ hhat) {
+  const int f = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.nr * g.nr) return;
+  const int i = e / g.nr, j = e % g.nr;
+  if (j < i) return;
+  double sr = 0.0, si = 0.0;
+  for (int ks = 0; ks < g.herk_split; ++ks) {
+    const double2 v = hpart64[((size_t)ks * g.nf + f) * g.nr * g.nr + e];
+    sr += v.x;
+    si += v.y;
+  }
+  sr /= (double)g.nt;
+  si /= (double)g.nt;
+  double2* H = hhat + (size_t)f * g.nr * g.nr;
+  if (i == j) {
+    H[(size_t)i * g.nr + i] = make_double2(sr, 0.0);
+  } else {
+    H[(size_t)i * g.nr + j] = make_double2(sr, si);
+    H[(size_t)j * g.nr + i] = make_double2(sr, -si);
+  }
+}
+
 // hhat[f][i][j] = sum_ks hpart[ks][f][i][j] (FP64, ascending ks) for j >= i,
 // mirrored to [j][i] as the conjugate; the diagonal's imaginary part is 0.
 __global__ void k_herk_reduce(Geometry g, const float2* __restrict__ hpart, double2* __restrict__ hhat,
@@ -320,6 +529,23 @@ hipError_t launch_herk_split_bf16(const Geometry& g, const float2* ghat, float2*
     hipLaunchKernelGGL(k_herk_bf16<true>, grid, dim3(256), 0, st, g, ghat, hpart, g.herk_split);
   else
     hipLaunchKernelGGL(k_herk_bf16<false>, grid, dim3(256), 0, st, g, ghat, hpart, g.herk_split);
+  return hipGetLastError();
+}
+
+hipError_t launch_herk_r2_chunk(const Geometry& g, const float* stage, const float2* tw,
+                                const float2* ghat, int n0, int cnt, bool first, double2* hpart64,
+                                hipStream_t st) {
+  const long long items = (long long)herk_bf16_blocks(g) * g.herk_split * g.nf;
+  if (items > 0x7fffffffLL || cnt < 1 || cnt > g.chunk || g.nrb < g.nr) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_herk_r2, dim3((unsigned)items), dim3(256), 0, st, g, stage, tw, ghat, n0, cnt,
+                     first ? 1 : 0, hpart64);
+  return hipGetLastError();
+}
+
+hipError_t launch_herk_r2_reduce(const Geometry& g, const double2* hpart64, double2* hhat,
+                                 hipStream_t st) {
+  dim3 grid(cdiv(g.nr * g.nr, 256), g.nf);
+  hipLaunchKernelGGL(k_herk_r2_reduce, grid, dim3(256), 0, st, g, hpart64, hhat);
   return hipGetLastError();
 }
 

@@ -24,6 +24,8 @@ EHI_OK, EHI_EINVAL, EHI_ENOMEM, EHI_EHIP, EHI_ENOTPD, EHI_ESTATE = range(6)
 PREC_PLAIN_FP32 = 0
 PREC_SPLIT_BF16 = 1
 _PREC = {"plain_fp32": PREC_PLAIN_FP32, "split_bf16": PREC_SPLIT_BF16}
+WEIGHT_LONG_RECORD, WEIGHT_FINITE_RECORD = 0, 1
+_WEIGHT = {"long_record": WEIGHT_LONG_RECORD, "finite_record": WEIGHT_FINITE_RECORD}
 
 # every symbol declared in include/ehi.h
 SYMBOLS = (
@@ -52,6 +54,7 @@ class SurveyDesc(ctypes.Structure):
         ("rec_iz", ctypes.POINTER(ctypes.c_int32)), ("rec_ix", ctypes.POINTER(ctypes.c_int32)),
         ("nf", ctypes.c_int32), ("freq_hz", ctypes.POINTER(ctypes.c_double)),
         ("precision", ctypes.c_int32), ("max_ns", ctypes.c_int32), ("nr_batch", ctypes.c_int32),
+        ("weighting", ctypes.c_int32),
     ]
 
 
@@ -134,7 +137,7 @@ def _require(t: torch.Tensor, dtype, shape, name: str, device: torch.device):
 
 
 def make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision, max_ns,
-              nr_batch):
+              nr_batch, weighting="long_record"):
     riz = np.ascontiguousarray(rec_iz, dtype=np.int32)
     rix = np.ascontiguousarray(rec_ix, dtype=np.int32)
     fr = np.ascontiguousarray(freqs_hz, dtype=np.float64)
@@ -145,7 +148,8 @@ def make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision
                    rec_iz=riz.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                    rec_ix=rix.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                    nf=len(fr), freq_hz=fr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                   precision=prec, max_ns=max_ns, nr_batch=nr_batch)
+                   precision=prec, max_ns=max_ns, nr_batch=nr_batch,
+                   weighting=_WEIGHT[weighting] if isinstance(weighting, str) else int(weighting))
     return d, (riz, rix, fr)   # keep the arrays alive with the descriptor
 
 
@@ -163,7 +167,7 @@ class Survey:
     def __init__(self, *, nz: int, nx: int, nb: int, h: float, dt: float, nt: int, stride: int,
                  rec_iz: Sequence[int], rec_ix: Sequence[int], freqs_hz: Sequence[float],
                  precision="split_bf16", max_ns: int = 256, nr_batch: int = 0,
-                 device=None, stream: Optional[torch.cuda.Stream] = None):
+                 weighting="long_record", device=None, stream: Optional[torch.cuda.Stream] = None):
         self._h = None
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.nz, self.nx, self.nb, self.nt, self.stride = nz, nx, nb, nt, stride
@@ -174,7 +178,8 @@ class Survey:
         self.max_ns = max_ns
         self.nr_batch = nr_batch
         d, keep = make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision,
-                            max_ns, nr_batch)
+                            max_ns, nr_batch, weighting)
+        self.weighting = weighting
         L = lib()
         nbytes = L.ehi_workspace_bytes(ctypes.byref(d))
         if nbytes == 0:

@@ -49,13 +49,22 @@ def test_workspace_bytes_valid(ehi):
     dict(nz=2), dict(nb=-1), dict(h=0.0), dict(dt=-1.0), dict(nt=0), dict(stride=0), dict(stride=9),
     dict(stride=3), dict(nb=513),
     dict(rec_iz=[1, 20]), dict(rec_ix=[-1, 4]), dict(freqs_hz=[]), dict(freqs_hz=[float("nan")]),
-    dict(precision=7), dict(max_ns=0), dict(nr_batch=-3),
+    dict(precision=7), dict(max_ns=0), dict(nr_batch=-3), dict(weighting=2),
+    dict(weighting="finite_record", precision="plain_fp32"),
+    dict(weighting="finite_record", nr_batch=1),
 ])
 def test_workspace_bytes_rejects(ehi, bad):
     with pytest.raises(ehi.EhiError) as ei:
         ehi.workspace_bytes(**_desc_kw(**bad))
     assert ei.value.status == ehi.EHI_EINVAL
     assert ehi.lib().ehi_last_error().decode()
+
+
+def test_finite_record_weighting_accepted_with_all_receivers(ehi):
+    a = ehi.workspace_bytes(**_desc_kw())
+    b = ehi.workspace_bytes(**_desc_kw(weighting="finite_record"))
+    c = ehi.workspace_bytes(**_desc_kw(weighting="finite_record", nr_batch=2))
+    assert b > a and c == b   # FP64 partial sums of the finite-record contraction
 
 
 def test_workspace_grows_with_sizes(ehi):
