@@ -46,6 +46,8 @@ def parse():
                          "(Poisson request mix over the eight surveys)")
     ap.add_argument("--batch-nt", type=int, default=4000, help="time steps of the batch8 surveys")
     ap.add_argument("--precision", default="split_bf16", choices=["split_bf16", "plain_fp32"])
+    ap.add_argument("--weighting", default="long_record", choices=["long_record", "finite_record"],
+                    help="Fourier-diagonal weighting: final-spectrum Gram (default) or the finite-record W")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: mean arrivals per second")
     ap.add_argument("--p-build", type=float, default=0.02, help="serve: probability a request is a build")
     ap.add_argument("--duration", type=float, default=120.0, help="serve: seconds of arrivals")
@@ -271,7 +273,8 @@ def main():
     vel = torch.from_numpy(s.velocity()).to(dev)
     R = torch.from_numpy(s.residuals()).to(dev)
     X = torch.empty_like(R)
-    sv = ehi.survey_from(s, precision=args.precision, max_ns=s.ns, nr_batch=args.nr_batch)
+    sv = ehi.survey_from(s, precision=args.precision, max_ns=s.ns, nr_batch=args.nr_batch,
+                         weighting=args.weighting)
     print(f"# workload {s.name} precision {args.precision} workspace {sv.workspace_bytes / 1e9:.2f} GB",
           file=sys.stderr, flush=True)
 
@@ -344,7 +347,10 @@ def main():
     dft_ms = prof["dft"][0] / K
     dft_bytes = costs.dft_bytes_per_survey(s.nz, s.nx, s.stride, s.nr, s.nt, s.nf, 256)
     dft_flops = costs.dft_flops_per_survey(s.nz, s.nx, s.stride, s.nr, s.nt, s.nf)
-    herk_flops = costs.herk_flops_per_survey(s.nz, s.nx, s.stride, s.nr, s.nf)
+    # the finite-record form contracts the running spectra after every step: nt
+    # times the final-spectrum contraction
+    rep = s.nt if args.weighting == "finite_record" else 1
+    herk_flops = costs.herk_flops_per_survey(s.nz, s.nx, s.stride, s.nr, s.nf) * rep
     herk_ms = prof["herk"][0] / K
     out = {
         "metric": METRIC,
@@ -359,7 +365,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": s.name, "precision": args.precision, "nz": s.nz, "nx": s.nx,
+        "config": {"workload": s.name, "precision": args.precision, "weighting": args.weighting,
+                   "nz": s.nz, "nx": s.nx,
                    "nb": s.nb, "nr": s.nr, "nt": s.nt, "nf": s.nf, "ns": s.ns, "stride": s.stride,
                    "nr_batch": nrb},
         "solves_per_s": round(solves_per_s, 1),
@@ -368,7 +375,7 @@ def main():
         "kernel_ms": {k: round(v[0] / K, 3) for k, v in prof.items()},
         "gcell_updates_per_s": round(cell_updates / (prof["step"][0] / K / 1e3) / 1e9, 2),
         "herk_tflops": round(herk_flops / (herk_ms / 1e3) / 1e12, 2) if herk_ms > 0 else None,
-        "herk_mfma_bf16_tflops": (round(costs.herk_bf16_mfma_flops_per_survey(s.nr, s.nsub, s.nf)
+        "herk_mfma_bf16_tflops": (round(costs.herk_bf16_mfma_flops_per_survey(s.nr, s.nsub, s.nf) * rep
                                         / (herk_ms / 1e3) / 1e12, 1)
                                   if herk_ms > 0 and args.precision == "split_bf16" else None),
         "dft_gbs": round(dft_bytes / (dft_ms / 1e3) / 1e9, 1) if dft_ms > 0 else None,

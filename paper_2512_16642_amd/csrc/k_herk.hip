@@ -278,19 +278,23 @@ __global__ void __launch_bounds__(256)
 // Hhat_W(w) = (1/Nt) sum_{p=1}^{Nt} Ghat_p(w) Ghat_p(w)^H, Ghat_p the DFT
 // truncated after sample p.  One launch per staging window (samples
 // n0 .. n0 + cnt - 1), before the DFT advances the spectra: a workgroup owns one
-// (frequency, 64 x 64 tile pair, grid partition); for every 32-point block of
-// its partition it starts from the running spectrum Ghat_{n0-1} (zero for the
-// first window), adds one staged sample times its twiddle per step, and after
-// every step contracts the running spectra of its 128 rows exactly as the
-// final-spectrum contraction does (hi/lo BF16 planes, four products, 32-point
-// MFMA chains from zero).  Sums: 16 steps in FP32, then in FP64 over steps,
-// blocks and windows (hpart64, read-modify-written by the one workgroup that
-// owns the entry).  All receivers must be stepped together.
+// (frequency, 64 x 64 tile pair, grid partition), each wave a 32 x 32 quarter.
+// For every 32-point block of the partition a wave starts from the running
+// spectra Ghat_{n0-1} of its 32 i-rows and 32 j-rows (zero for the first
+// window), adds one staged sample times its twiddle per step and contracts
+// them as the final-spectrum contraction does (hi/lo BF16 planes, four
+// products, 32-point MFMA chains from zero).  A lane keeps the running spectra
+// of the row and 8-point group its MFMA operands cover (row lane % 16, points
+// 8 (lane / 16) ..), so the step loop needs no data exchange between waves;
+// rows shared by two waves are updated by both.  Sums: 16 steps in FP32, then
+// FP64 (per-lane LDS slots) over steps and blocks, then FP64 over windows
+// (hpart64, read-modify-written by the one workgroup that owns the entry).
+// All receivers must be stepped together.
 __global__ void __launch_bounds__(256)
     k_herk_r2(Geometry g, const float* __restrict__ stage, const float2* __restrict__ tw,
               const float2* __restrict__ ghat, int n0, int cnt, int first,
               double2* __restrict__ hpart64) {
-  __shared__ u32x4 pl[2][4][kBk / 8][2 * kBt];
+  __shared__ double acc_s[32][256];  // per lane: [a][b][re/im][v] FP64 sums
   const int nblk = cdiv(g.nr, kBt);
   const int npair = nblk * (nblk + 1) / 2;
   const int split = g.herk_split;
@@ -318,34 +322,30 @@ __global__ void __launch_bounds__(256)
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
-  const int lrow = tid & (2 * kBt - 1);
-  const int grow = lrow < kBt ? bi * kBt + lrow : bj * kBt + (lrow - kBt);
-  const bool rowv = grow < g.nr;
-  const float2* Gprev = ghat + ((size_t)f * g.nr + (rowv ? grow : 0)) * g.nsub;
-  const float* Srow = stage + (size_t)(rowv ? grow : 0) * g.chunk * g.nsub_p;
   const int fr = lane & 15, fg = lane >> 4;
-
-  double acc[2][2][2][4];  // [a][b][re/im][v], FP64 over blocks (and windows via hpart64)
+  // this lane's four rows: i-rows (a = 0, 1), then j-rows (b = 0, 1)
+  int row[4];
+  bool rv[4];
+  const float* Srow[4];
+  const float2* Grow[4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int u = 0; u < 4; ++u) {
+    row[u] = u < 2 ? bi * kBt + wi * 32 + u * 16 + fr : bj * kBt + wj * 32 + (u - 2) * 16 + fr;
+    rv[u] = row[u] < g.nr;
+    Srow[u] = stage + (size_t)(rv[u] ? row[u] : 0) * g.chunk * g.nsub_p;
+    Grow[u] = ghat + ((size_t)f * g.nr + (rv[u] ? row[u] : 0)) * g.nsub;
+  }
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int v4 = 0; v4 < 4; ++v4) acc[a][b][c][v4] = 0.0;
+  for (int e = 0; e < 32; ++e) acc_s[e][tid] = 0.0;
 
   for (int kb = k0; kb < k1; kb += kBk) {
-    // running spectra of this thread's two 8-point groups
-    float2 S[2][8];
-    int kx[2];
+    const int kx = kb + 8 * fg;
+    float2 S[4][8];
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      kx[p] = kb + 8 * ((tid >> 7) + 2 * p);
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int e = 0; e < 8; ++e)
-        S[p][e] = (!first && rowv && kx[p] + e < k1) ? Gprev[kx[p] + e] : make_float2(0.f, 0.f);
-    }
+        S[u][e] = (!first && rv[u] && kx + e < k1) ? Grow[u][kx + e] : make_float2(0.f, 0.f);
     floatx4 grp[2][2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -353,26 +353,32 @@ __global__ void __launch_bounds__(256)
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int c = 0; c < 2; ++c) grp[a][b][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int t = 0; t < cnt; ++t) {
-      const int buf = t & 1;
-      const float2 w = tw[(size_t)(n0 - 1 + t) * g.nf + f];
-      // add sample n0 + t and publish the hi/lo planes of the running spectra
+
+    auto gload = [&](floatx4 (&q)[4][2], int t) {
 #pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        const float* src = Srow + (size_t)t * g.nsub_p + kx[p];
-        const floatx4 q0 = *reinterpret_cast<const floatx4*>(src);
-        const floatx4 q1 = *reinterpret_cast<const floatx4*>(src + 4);
-        const float gv[8] = {q0[0], q0[1], q0[2], q0[3], q1[0], q1[1], q1[2], q1[3]};
+      for (int u = 0; u < 4; ++u) {
+        const float* src = Srow[u] + (size_t)t * g.nsub_p + kx;
+        q[u][0] = *reinterpret_cast<const floatx4*>(src);
+        q[u][1] = *reinterpret_cast<const floatx4*>(src + 4);
+      }
+    };
+    auto step = [&](int t, const floatx4 (&q)[4][2]) {
+      const float2 w = tw[(size_t)(n0 - 1 + t) * g.nf + f];
+      bf16x8 fr4[4][4];  // [row][plane]
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float gv[8] = {q[u][0][0], q[u][0][1], q[u][0][2], q[u][0][3],
+                             q[u][1][0], q[u][1][1], q[u][1][2], q[u][1][3]};
         unsigned wd[4][4];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const float x = (rowv && kx[p] + e < k1) ? gv[e] : 0.f;
-          S[p][e].x = fmaf(w.x, x, S[p][e].x);
-          S[p][e].y = fmaf(w.y, x, S[p][e].y);
+          const float x = (rv[u] && kx + e < k1) ? gv[e] : 0.f;
+          S[u][e].x = fmaf(w.x, x, S[u][e].x);
+          S[u][e].y = fmaf(w.y, x, S[u][e].y);
         }
 #pragma unroll
         for (int e = 0; e < 8; e += 2) {
-          const float2 z0 = S[p][e], z1 = S[p][e + 1];
+          const float2 z0 = S[u][e], z1 = S[u][e + 1];
           const bf16x2 rh = {(__bf16)z0.x, (__bf16)z1.x};
           const bf16x2 ih = {(__bf16)z0.y, (__bf16)z1.y};
           const bf16x2 rl = {(__bf16)(z0.x - (float)rh[0]), (__bf16)(z1.x - (float)rh[1])};
@@ -382,43 +388,36 @@ __global__ void __launch_bounds__(256)
           wd[2][e >> 1] = __builtin_bit_cast(unsigned, ih);
           wd[3][e >> 1] = __builtin_bit_cast(unsigned, il);
         }
-        const int gq = (tid >> 7) + 2 * p;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) pl[buf][q][gq][lrow] = u32x4{wd[q][0], wd[q][1], wd[q][2], wd[q][3]};
+        for (int qq = 0; qq < 4; ++qq)
+          fr4[u][qq] = __builtin_bit_cast(bf16x8, u32x4{wd[qq][0], wd[qq][1], wd[qq][2], wd[qq][3]});
       }
-      __syncthreads();
-      bf16x8 ai[2][4], aj[2][4];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          ai[a][q] = __builtin_bit_cast(bf16x8, pl[buf][q][fg][wi * 32 + a * 16 + fr]);
-          aj[a][q] = __builtin_bit_cast(bf16x8, pl[buf][q][fg][kBt + wj * 32 + a * 16 + fr]);
-        }
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
         const u32x4 sgn = u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
-        const bf16x8 nrh = __builtin_bit_cast(bf16x8, __builtin_bit_cast(u32x4, ai[a][0]) ^ sgn);
-        const bf16x8 nrl = __builtin_bit_cast(bf16x8, __builtin_bit_cast(u32x4, ai[a][1]) ^ sgn);
+        const bf16x8 nrh = __builtin_bit_cast(bf16x8, __builtin_bit_cast(u32x4, fr4[a][0]) ^ sgn);
+        const bf16x8 nrl = __builtin_bit_cast(bf16x8, __builtin_bit_cast(u32x4, fr4[a][1]) ^ sgn);
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
+          const bf16x8* ai = fr4[a];
+          const bf16x8* aj = fr4[2 + b];
           floatx4 r = floatx4{0.f, 0.f, 0.f, 0.f}, m = floatx4{0.f, 0.f, 0.f, 0.f};
-          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][0], aj[b][0], r, 0, 0, 0);
-          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][0], aj[b][1], r, 0, 0, 0);
-          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][1], aj[b][0], r, 0, 0, 0);
-          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][1], aj[b][1], r, 0, 0, 0);
-          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][2], r, 0, 0, 0);
-          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][3], r, 0, 0, 0);
-          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][2], r, 0, 0, 0);
-          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][3], r, 0, 0, 0);
-          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][0], m, 0, 0, 0);
-          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][1], m, 0, 0, 0);
-          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][0], m, 0, 0, 0);
-          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][1], m, 0, 0, 0);
-          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrh, aj[b][2], m, 0, 0, 0);
-          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrh, aj[b][3], m, 0, 0, 0);
-          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrl, aj[b][2], m, 0, 0, 0);
-          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrl, aj[b][3], m, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[0], aj[0], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[0], aj[1], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[1], aj[0], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[1], aj[1], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[2], aj[2], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[2], aj[3], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[3], aj[2], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[3], aj[3], r, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[2], aj[0], m, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[2], aj[1], m, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[3], aj[0], m, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[3], aj[1], m, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrh, aj[2], m, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrh, aj[3], m, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrl, aj[2], m, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrl, aj[3], m, 0, 0, 0);
           grp[a][b][0] += r;
           grp[a][b][1] += m;
         }
@@ -431,12 +430,16 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
 #pragma unroll
-              for (int v4 = 0; v4 < 4; ++v4) acc[a][b][c][v4] += (double)grp[a][b][c][v4];
+              for (int v4 = 0; v4 < 4; ++v4) acc_s[((a * 2 + b) * 2 + c) * 4 + v4][tid] += (double)grp[a][b][c][v4];
               grp[a][b][c] = floatx4{0.f, 0.f, 0.f, 0.f};
             }
       }
+    };
+    for (int t = 0; t < cnt; ++t) {
+      floatx4 q[4][2];
+      gload(q, t);
+      step(t, q);
     }
-    __syncthreads();  // the next block overwrites both LDS buffers
   }
   double2* out = hpart64 + ((size_t)ks * g.nf + f) * g.nr * g.nr;
 #pragma unroll
@@ -450,8 +453,8 @@ __global__ void __launch_bounds__(256)
         if (i < g.nr && j < g.nr) {
           double2* o = out + (size_t)i * g.nr + j;
           double2 v = first ? make_double2(0.0, 0.0) : *o;
-          v.x += acc[a][b][0][v4];
-          v.y += acc[a][b][1][v4];
+          v.x += acc_s[((a * 2 + b) * 2 + 0) * 4 + v4][tid];
+          v.y += acc_s[((a * 2 + b) * 2 + 1) * 4 + v4][tid];
           *o = v;
         }
       }
