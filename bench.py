@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: HBM budget")
     ap.add_argument("--build-slots", type=int, default=2, help="serve: concurrent builds")
     ap.add_argument("--nr-batch", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=512, choices=[256, 512],
+                    help="time samples per DFT staging window")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=300, help="FD steps in the CPU sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -274,7 +276,7 @@ def main():
     R = torch.from_numpy(s.residuals()).to(dev)
     X = torch.empty_like(R)
     sv = ehi.survey_from(s, precision=args.precision, max_ns=s.ns, nr_batch=args.nr_batch,
-                         weighting=args.weighting)
+                         weighting=args.weighting, chunk=args.chunk)
     print(f"# workload {s.name} precision {args.precision} workspace {sv.workspace_bytes / 1e9:.2f} GB",
           file=sys.stderr, flush=True)
 
@@ -345,7 +347,7 @@ def main():
         "bytes_per_cell_update": round(bpc, 4),
     }
     dft_ms = prof["dft"][0] / K
-    dft_bytes = costs.dft_bytes_per_survey(s.nz, s.nx, s.stride, s.nr, s.nt, s.nf, 256)
+    dft_bytes = costs.dft_bytes_per_survey(s.nz, s.nx, s.stride, s.nr, s.nt, s.nf, args.chunk)
     dft_flops = costs.dft_flops_per_survey(s.nz, s.nx, s.stride, s.nr, s.nt, s.nf)
     # the finite-record form contracts the running spectra after every step: nt
     # times the final-spectrum contraction
@@ -366,6 +368,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": s.name, "precision": args.precision, "weighting": args.weighting,
+                   "chunk": args.chunk,
                    "nz": s.nz, "nx": s.nx,
                    "nb": s.nb, "nr": s.nr, "nt": s.nt, "nf": s.nf, "ns": s.ns, "stride": s.stride,
                    "nr_batch": nrb},

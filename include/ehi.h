@@ -100,6 +100,10 @@ typedef enum {
  *   nr_batch  receivers time-stepped together (0 = all).  Sizes the
  *             wavefield buffers.
  *   weighting an ehi_weighting value.
+ *   chunk     time samples per staging window of the DFT (0 = 256; 256 or
+ *             512).  A longer window halves the accumulator traffic of the
+ *             DFT and doubles the staging buffer (nr_batch x chunk x subgrid
+ *             floats).
  */
 typedef struct {
   int32_t nz, nx, nb;
@@ -115,6 +119,7 @@ typedef struct {
   int32_t max_ns;
   int32_t nr_batch;
   int32_t weighting;
+  int32_t chunk;
 } ehi_survey_desc;
 
 typedef struct ehi_survey ehi_survey;

@@ -70,7 +70,9 @@ bool validate(const ehi_survey_desc* d, std::string* why) {
   // buffer resources address one plane / one staging block with 31-bit byte offsets
   if ((Z + 4) * (X + 4 + ehi::kRowAlign) > (1LL << 28)) return bad("grid too large");
   long long nsub = (long long)((d->nz + d->stride - 1) / d->stride) * ((d->nx + d->stride - 1) / d->stride);
-  if ((nsub + 256) * 256LL * 4 >= (1LL << 31)) return bad("subgrid too large for the staging buffer");
+  if (d->chunk != 0 && d->chunk != 256 && d->chunk != 512) return bad("chunk must be 0, 256 or 512");
+  const long long chunk = d->chunk ? d->chunk : 256;
+  if ((nsub + 256) * chunk * 4 >= (1LL << 31)) return bad("subgrid too large for the staging buffer");
   return true;
 }
 
@@ -89,7 +91,7 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   g.nxs = ehi::cdiv(d->nx, d->stride);
   g.nsub = g.nzs * g.nxs;
   g.nsub_p = (int)ehi::align_up((size_t)g.nsub, 256);  // the DFT reads whole 256-point blocks
-  g.chunk = 256;
+  g.chunk = d->chunk ? d->chunk : 256;
   g.nt = d->nt;
   g.nr = d->nr;
   g.nf = d->nf;

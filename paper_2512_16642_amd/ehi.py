@@ -54,7 +54,7 @@ class SurveyDesc(ctypes.Structure):
         ("rec_iz", ctypes.POINTER(ctypes.c_int32)), ("rec_ix", ctypes.POINTER(ctypes.c_int32)),
         ("nf", ctypes.c_int32), ("freq_hz", ctypes.POINTER(ctypes.c_double)),
         ("precision", ctypes.c_int32), ("max_ns", ctypes.c_int32), ("nr_batch", ctypes.c_int32),
-        ("weighting", ctypes.c_int32),
+        ("weighting", ctypes.c_int32), ("chunk", ctypes.c_int32),
     ]
 
 
@@ -137,7 +137,7 @@ def _require(t: torch.Tensor, dtype, shape, name: str, device: torch.device):
 
 
 def make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision, max_ns,
-              nr_batch, weighting="long_record"):
+              nr_batch, weighting="long_record", chunk=0):
     riz = np.ascontiguousarray(rec_iz, dtype=np.int32)
     rix = np.ascontiguousarray(rec_ix, dtype=np.int32)
     fr = np.ascontiguousarray(freqs_hz, dtype=np.float64)
@@ -149,7 +149,8 @@ def make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision
                    rec_ix=rix.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                    nf=len(fr), freq_hz=fr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                    precision=prec, max_ns=max_ns, nr_batch=nr_batch,
-                   weighting=_WEIGHT[weighting] if isinstance(weighting, str) else int(weighting))
+                   weighting=_WEIGHT[weighting] if isinstance(weighting, str) else int(weighting),
+                   chunk=int(chunk))
     return d, (riz, rix, fr)   # keep the arrays alive with the descriptor
 
 
@@ -167,7 +168,8 @@ class Survey:
     def __init__(self, *, nz: int, nx: int, nb: int, h: float, dt: float, nt: int, stride: int,
                  rec_iz: Sequence[int], rec_ix: Sequence[int], freqs_hz: Sequence[float],
                  precision="split_bf16", max_ns: int = 256, nr_batch: int = 0,
-                 weighting="long_record", device=None, stream: Optional[torch.cuda.Stream] = None):
+                 weighting="long_record", chunk: int = 0, device=None,
+                 stream: Optional[torch.cuda.Stream] = None):
         self._h = None
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.nz, self.nx, self.nb, self.nt, self.stride = nz, nx, nb, nt, stride
@@ -178,7 +180,7 @@ class Survey:
         self.max_ns = max_ns
         self.nr_batch = nr_batch
         d, keep = make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision,
-                            max_ns, nr_batch, weighting)
+                            max_ns, nr_batch, weighting, chunk)
         self.weighting = weighting
         L = lib()
         nbytes = L.ehi_workspace_bytes(ctypes.byref(d))

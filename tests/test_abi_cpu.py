@@ -51,7 +51,7 @@ def test_workspace_bytes_valid(ehi):
     dict(rec_iz=[1, 20]), dict(rec_ix=[-1, 4]), dict(freqs_hz=[]), dict(freqs_hz=[float("nan")]),
     dict(precision=7), dict(max_ns=0), dict(nr_batch=-3), dict(weighting=2),
     dict(weighting="finite_record", precision="plain_fp32"),
-    dict(weighting="finite_record", nr_batch=1),
+    dict(weighting="finite_record", nr_batch=1), dict(chunk=128), dict(chunk=300),
 ])
 def test_workspace_bytes_rejects(ehi, bad):
     with pytest.raises(ehi.EhiError) as ei:
@@ -65,6 +65,12 @@ def test_finite_record_weighting_accepted_with_all_receivers(ehi):
     b = ehi.workspace_bytes(**_desc_kw(weighting="finite_record"))
     c = ehi.workspace_bytes(**_desc_kw(weighting="finite_record", nr_batch=2))
     assert b > a and c == b   # FP64 partial sums of the finite-record contraction
+
+
+def test_longer_staging_window(ehi):
+    a = ehi.workspace_bytes(**_desc_kw())
+    assert ehi.workspace_bytes(**_desc_kw(chunk=256)) == a
+    assert ehi.workspace_bytes(**_desc_kw(chunk=512)) > a
 
 
 def test_workspace_grows_with_sizes(ehi):

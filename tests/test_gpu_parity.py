@@ -117,6 +117,18 @@ def test_launch_shapes_bitwise_identical(ehi):
     assert max(errs) < 5e-6
 
 
+def test_green_dft_512_sample_window(ehi, tiny_ref):
+    # the longer staging window changes only the grouping of the DFT sums
+    s = tiny_ref["s"]
+    sv = ehi.survey_from(s, chunk=512)
+    sv.build_green(dev(tiny_ref["v"]))
+    G = sv.copy_green_dft().reshape(s.nf, s.nr, -1).cpu().numpy()
+    sv.close()
+    errs = per_freq_rel(G, tiny_ref["G"])
+    print("512-sample window ghat rel err per freq", errs)
+    assert max(errs) < 5e-6
+
+
 def test_green_single_step_and_chunk_edges(ehi):
     # nt = 1 (only the impulse sample), nt = 64 and 65 (DFT chunk edge)
     base = synth.ragged(nt=1)
