@@ -19,6 +19,9 @@ Forms computed here (all for one survey; receivers i, j; grid points x):
   function.  This is the algorithm with W replaced by a constant (the long-record
   Toeplitz limit the paper invokes when it lets t grow), written with the
   transfer-function normalisation (no 1/2Nt, and W = 1): Hhat = 2Nt qhat|_{W=1}.
+* ``hessian_compressed``: Ĝ Ψᵀ (Ĝ Ψᵀ)ᴴ with Ψ the leading rows of the
+  orthonormal 2D DCT-II of the subgrid (the spatial compression the discussion
+  proposes); every coefficient kept gives ``hessian_r1`` exactly.
 * ``hessian_r2``: the finite-record weighting kept exactly, evaluated without
   the 2Nt transform as the time average of running-DFT Gram matrices:
   Hhat_W(w) = (1/Nt) sum_{p=1}^{Nt} Ghat_p(w) Ghat_p(w)^H with Ghat_p the DFT
@@ -111,6 +114,34 @@ def hessian_r1(ghat: np.ndarray) -> np.ndarray:
     ``[nf][nr][nsub]`` complex.  Returns ``[nf][nr][nr]`` complex128."""
     g = np.asarray(ghat, dtype=np.complex128)
     return np.einsum("fix,fjx->fij", g, np.conj(g), optimize=True)
+
+
+def dct_matrix(n: int, keep: int) -> np.ndarray:
+    """Leading ``keep`` rows of the orthonormal DCT-II matrix of size n:
+    D[k][m] = s_k cos(pi k (2m + 1) / (2n)), s_0 = sqrt(1/n), s_k = sqrt(2/n)."""
+    k = np.arange(keep)[:, None]
+    m = np.arange(n)[None, :]
+    s = np.where(k == 0, math.sqrt(1.0 / n), math.sqrt(2.0 / n))
+    return s * np.cos(math.pi * k * (2 * m + 1) / (2.0 * n))
+
+
+def compress_spectra(ghat: np.ndarray, nzs: int, nxs: int, keep_z: int, keep_x: int) -> np.ndarray:
+    """Spatially compressed spectra (Discussion: an orthonormal transform Psi
+    of the spatial axis, keeping the leading coefficients): each spectrum row,
+    seen as an nzs x nxs image, is transformed by the 2D DCT-II and cropped to
+    the leading keep_z x keep_x coefficients.  ``ghat`` is ``[nf][nr][nzs*nxs]``;
+    returns ``[nf][nr][keep_z*keep_x]`` (kz-major)."""
+    g = np.asarray(ghat, dtype=np.complex128).reshape(ghat.shape[0], ghat.shape[1], nzs, nxs)
+    Dz = dct_matrix(nzs, keep_z)
+    Dx = dct_matrix(nxs, keep_x)
+    c = np.einsum("az,frzx,bx->frab", Dz, g, Dx, optimize=True)
+    return c.reshape(ghat.shape[0], ghat.shape[1], keep_z * keep_x)
+
+
+def hessian_compressed(ghat: np.ndarray, nzs: int, nxs: int, keep_z: int, keep_x: int) -> np.ndarray:
+    """Hhat ~ (Ghat Psi^T)(Ghat Psi^T)^H with Psi the cropped 2D DCT-II; exact
+    (= hessian_r1) when every coefficient is kept."""
+    return hessian_r1(compress_spectra(ghat, nzs, nxs, keep_z, keep_x))
 
 
 def running_dft_gram(gt: np.ndarray, freqs_hz, dt: float) -> np.ndarray:

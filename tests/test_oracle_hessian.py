@@ -139,3 +139,36 @@ def test_block_diagonal_after_permutation():
         off = P[k * nr:(k + 1) * nr].copy()
         off[:, k * nr:(k + 1) * nr] = 0
         assert not off.any()
+
+
+def test_dct_matrix_is_the_definition_and_orthonormal():
+    # against scipy's orthonormal DCT-II of the identity (an independent routine)
+    import scipy.fft
+    for n in (1, 5, 16, 33):
+        D = hessian.dct_matrix(n, n)
+        ref = scipy.fft.dct(np.eye(n), type=2, norm="ortho", axis=0)
+        np.testing.assert_allclose(D, ref, atol=1e-13)
+        np.testing.assert_allclose(D @ D.T, np.eye(n), atol=1e-13)
+
+
+def test_compression_exact_with_all_coefficients_and_converges():
+    rng = np.random.default_rng(4)
+    nf, nr, nzs, nxs = 2, 5, 9, 12
+    # smooth fields (decaying spectrum) plus a little noise
+    z = np.arange(nzs)[:, None] / nzs
+    x = np.arange(nxs)[None, :] / nxs
+    g = np.empty((nf, nr, nzs * nxs), dtype=np.complex128)
+    for f in range(nf):
+        for r in range(nr):
+            a, b = rng.uniform(0.5, 2.0, 2)
+            field = np.exp(-((z - 0.3 * a) ** 2 + (x - 0.2 * b) ** 2) * 8) * np.exp(1j * (a * z + b * x))
+            g[f, r] = (field + 1e-3 * rng.standard_normal((nzs, nxs))).ravel()
+    full = hessian.hessian_r1(g)
+    np.testing.assert_allclose(hessian.hessian_compressed(g, nzs, nxs, nzs, nxs), full, rtol=1e-12, atol=1e-12)
+    errs = [np.linalg.norm(hessian.hessian_compressed(g, nzs, nxs, k, k + 3) - full) / np.linalg.norm(full)
+            for k in (2, 4, 6, 8)]
+    assert all(a > b for a, b in zip(errs, errs[1:])), errs
+    # Parseval: the kept energy never exceeds the full energy (diagonal of H)
+    for k in (2, 5):
+        c = hessian.hessian_compressed(g, nzs, nxs, k, k)
+        assert np.all(np.diagonal(c, axis1=1, axis2=2).real <= np.diagonal(full, axis1=1, axis2=2).real + 1e-12)
