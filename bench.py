@@ -42,8 +42,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="layered_1000x300",
-                    help="layered_1000x300 (default), tiny, batch8 (the eight uneven surveys) or serve "
-                         "(Poisson request mix over the eight surveys)")
+                    help="layered_1000x300 (default), tiny, batch8 (the eight uneven surveys), serve "
+                         "(Poisson request mix over the eight surveys) or accuracy (the Hessian "
+                         "accuracy test on the 1000 x 300 survey)")
     ap.add_argument("--batch-nt", type=int, default=4000, help="time steps of the batch8 surveys")
     ap.add_argument("--precision", default="split_bf16", choices=["split_bf16", "plain_fp32"])
     ap.add_argument("--weighting", default="long_record", choices=["long_record", "finite_record"],
@@ -54,6 +55,7 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serve: HBM budget")
     ap.add_argument("--build-slots", type=int, default=2, help="serve: concurrent builds")
     ap.add_argument("--nr-batch", type=int, default=0)
+    ap.add_argument("--acc-ns", type=int, default=16, help="accuracy: sources per step")
     ap.add_argument("--chunk", type=int, default=512, choices=[256, 512],
                     help="time samples per DFT staging window")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -244,13 +246,102 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def run_accuracy(args):
+    """The Hessian accuracy test on the 1000 x 300 layered survey: frequencies
+    moved to the nearest bins of the 2nt-point transform, factors of the
+    smoothed (starting) model built once, then per step, for args.acc_ns
+    surface sources: residual spectra, deblur, inverse transform, back-
+    propagation S^T, extended forward S and the misfit."""
+    import torch
+
+    import synth
+    from paper_2512_16642_amd import accuracy, ehi
+
+    base = synth.layered_1000x300()
+    s = base.with_(name=base.name + "-bins", freqs_hz=synth.nearest_bins(base.nt, base.dt, base.freqs_hz))
+    ns = args.acc_ns
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    v_true = s.velocity()
+    v0 = synth.smoothed(v_true, 10)
+    sv = ehi.survey_from(s, precision=args.precision, max_ns=ns)
+    t0 = time.perf_counter()
+    sv.build_green(torch.from_numpy(v0).to(dev))
+    sv.build_hessian()
+    sv.factor(1e-3 * sv.lambda_max())
+    # observed data from the true model, predicted data from the starting model:
+    # Ricker sources (8 Hz) at depth 20 m, spread across x, on the subgrid
+    src = torch.zeros((ns, s.nt, s.nzs, s.nxs), dtype=torch.float32, device=dev)
+    w = torch.from_numpy(synth.ricker(s.nt, s.dt, 8.0)).to(dev)
+    for k in range(ns):
+        src[k, :, 1, (k * (s.nxs - 1)) // max(1, ns - 1)] = w
+    sv.set_medium(torch.from_numpy(v_true).to(dev))
+    d_obs = sv.forward_subgrid(src)
+    sv.set_medium(torch.from_numpy(v0).to(dev))
+    dd = d_obs - sv.forward_subgrid(src)
+    del src
+    torch.cuda.synchronize()
+    print(f"# accuracy: factors and data ready in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    db = torch.empty((ns, s.nt, s.nzs, s.nxs), dtype=torch.float32, device=dev)
+    for _ in range(args.warmup):
+        accuracy.accuracy_test(sv, dd, d_obs, db_out=db)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    acc = [0.0] * 4
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        e[0].record(stream)
+        dde = accuracy.deblur_time(sv, dd)
+        e[1].record(stream)
+        sv.backpropagate(dde, out=db)
+        e[2].record(stream)
+        pred = sv.forward_subgrid(db)
+        e[3].record(stream)
+        err, rel = ehi.misfit(dd, pred, d_obs)
+        e[4].record(stream)
+        e[4].synchronize()
+        for j in range(4):
+            acc[j] += e[j].elapsed_time(e[j + 1])
+        print(f"# accuracy step {k} done", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    K = args.steps
+    tot = sum(acc) / K
+    relerr = rel.cpu().tolist()
+    cells = 2.0 * ns * s.nt * (s.nz + 2 * s.nb) * (s.nx + 2 * s.nb)
+    pde_ms = (acc[1] + acc[2]) / K
+    out = {
+        "metric": "Hessian accuracy test: sources/s (deblur in time + back-propagation + extended forward)",
+        "value": round(ns / (tot / 1e3), 3),
+        "unit": "sources/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / K * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": s.name, "sources": ns, "precision": args.precision, "nf_bins": s.nf,
+                   "starting_model": "true model box-smoothed over 21 cells"},
+        "stage_ms": {"deblur_time": round(acc[0] / K, 3), "backpropagate": round(acc[1] / K, 2),
+                     "forward": round(acc[2] / K, 2), "misfit": round(acc[3] / K, 3)},
+        "gcell_updates_per_s": round(cells / (pde_ms / 1e3) / 1e9, 1),
+        "relerr": {"min": round(min(relerr), 5), "max": round(max(relerr), 5),
+                   "mean": round(sum(relerr) / len(relerr), 5)},
+    }
+    sv.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
-    if args.workload in ("batch8", "serve"):
+    if args.workload in ("batch8", "serve", "accuracy"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        (run_batch if args.workload == "batch8" else run_serve)(args)
+        {"batch8": run_batch, "serve": run_serve, "accuracy": run_accuracy}[args.workload](args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "

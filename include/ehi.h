@@ -104,6 +104,13 @@ typedef enum {
  *             512).  A longer window halves the accumulator traffic of the
  *             DFT and doubles the staging buffer (nr_batch x chunk x subgrid
  *             floats).
+ *   keep_z, keep_x  spatial compression of the contraction (the orthonormal
+ *             transform of the spatial axis the paper's discussion proposes):
+ *             0, 0 = contract over the subgrid points; otherwise each
+ *             spectrum row, as an nzs x nxs image, is transformed by the
+ *             orthonormal 2D DCT-II and only the leading keep_z x keep_x
+ *             coefficients enter Hhat (exact when all are kept).  Long-record
+ *             weighting only.
  */
 typedef struct {
   int32_t nz, nx, nb;
@@ -120,6 +127,7 @@ typedef struct {
   int32_t nr_batch;
   int32_t weighting;
   int32_t chunk;
+  int32_t keep_z, keep_x;
 } ehi_survey_desc;
 
 typedef struct ehi_survey ehi_survey;
@@ -221,6 +229,74 @@ ehi_status ehi_load_hessian(ehi_survey* s, const void* in_dev);
  * (upper part zero), to out_dev.  Requires ehi_factor.  Asynchronous. */
 ehi_status ehi_copy_factor(ehi_survey* s, void* out_dev);
 
+/* ---- Steps either side of the deblur and the Hessian accuracy test ---------
+ *
+ * The paper's extended-source algorithm deblurs time-domain residuals:
+ * delta d^e = Q^{-1} delta d, back-propagates them as the source extension
+ * delta b = S^T delta d^e, and its Hessian accuracy test compares the data with
+ * the prediction of the extended wavefield, d - P u^e = delta d - S S^T
+ * delta d^e (Theory: S = P A(m)^{-1}, Q = S S^T + mu I; numerical examples,
+ * Hessian accuracy test).  The frequency-domain inversion carries the
+ * residuals over with a transform of length 2 nt and the multipliers back
+ * with its inverse, cropped to the record.
+ *
+ * S here is the forward operator of the Green functions' own scheme with its
+ * source side on the stride subgrid (the grid points the Hessian contraction
+ * runs over), so S S^T is the time-domain Hessian that Hhat approximates:
+ *   S: f [nt][nzs][nxs] -> traces d [nr][nt], f^n entering the step that
+ *      produces u^{n+1} (a u^{n+1} = 2u^n - b u^{n-1} + kappa (L4 u^n + f^n)),
+ *      d[r][n-1] = u^n at receiver r, n = 1..nt;
+ *   S^T: its transpose, a run in reversed time with the traces injected at the
+ *      receivers.
+ * Both time-step every field one level per launch in FP32 on the survey's
+ * stream, using the wavefield buffers of the workspace (no allocation), in
+ * batches of nr_batch fields. */
+
+/* Loads the medium (sponge and padded coefficients of vel_dev, float32
+ * [nz][nx] m/s) for ehi_forward_subgrid / ehi_backpropagate without time-
+ * stepping the Green functions (ehi_build_green loads it too).  Leaves the
+ * spectra, Hhat and the factors as they are.  Asynchronous. */
+ehi_status ehi_set_medium(ehi_survey* s, const float* vel_dev);
+
+/* data = S src for ns fields: src_dev float32 [ns][nt][nzs][nxs], data_dev
+ * float32 [ns][nr][nt] (device, caller-owned, not aliased).  EHI_ESTATE if no
+ * medium is loaded.  Asynchronous on the survey's stream. */
+ehi_status ehi_forward_subgrid(ehi_survey* s, const float* src_dev, int32_t ns, float* data_dev);
+
+/* src = S^T data for ns fields (the back-propagated source extension
+ * delta b = S^T delta d^e): data_dev float32 [ns][nr][nt], src_dev float32
+ * [ns][nt][nzs][nxs].  Receivers sharing a cell add.  EHI_ESTATE if no medium
+ * is loaded.  Asynchronous on the survey's stream. */
+ehi_status ehi_backpropagate(ehi_survey* s, const float* data_dev, int32_t ns, float* src_dev);
+
+/* Residual spectra R[f][s][r] = sum_{n=1}^{nt} dres[s][r][n-1]
+ * exp(-i 2 pi freq_hz[f] n dt) (the Green functions' sign and sample origin;
+ * at a bin k = freq 2 nt dt it is bin k of the 2nt-point DFT of the zero-padded
+ * record): dres_dev float32 [ns][nr][nt], resid_dev complex64 [nf][ns][nr],
+ * ready for ehi_apply_multipliers.  Sums in FP64 over the complex64 twiddle
+ * table.  Any frequencies.  Enqueued on stream (NULL = the survey's). */
+ehi_status ehi_residual_spectra(ehi_survey* s, const float* dres_dev, int32_t ns, void* resid_dev,
+                                void* stream);
+
+/* Multipliers back to time: the inverse 2nt-point transform of the bins held
+ * in mult_dev (complex64 [nf][ns][nr]; bins not among the survey's frequencies
+ * count as zero; the record is real, so bin k stands for itself and its
+ * conjugate 2nt - k), cropped to samples 1..nt:
+ *   out[s][r][n-1] = (1/2nt) sum_f c_f Re(X[f][s][r] exp(+i 2 pi freq_hz[f] n dt)),
+ * c_f = 1 for bins 0 and nt, 2 otherwise; out_dev float32 [ns][nr][nt].  Sums
+ * in FP64.  EHI_EINVAL unless every frequency is a distinct bin k = freq_hz 2
+ * nt dt in 0..nt (within 1e-6 of an integer).  Enqueued on stream (NULL = the
+ * survey's). */
+ehi_status ehi_multipliers_to_time(ehi_survey* s, const void* mult_dev, int32_t ns, float* out_dev,
+                                   void* stream);
+
+/* Misfit of the accuracy test for ns records of len values each (float32,
+ * device): err = dd - pred (err_dev may be NULL) and relerr[s] = sum err^2 /
+ * sum obs^2 (FP64, relerr_dev double [ns], device).  Enqueued on stream (NULL
+ * = the default stream). */
+ehi_status ehi_misfit(const float* dd_dev, const float* pred_dev, const float* obs_dev, int32_t ns,
+                      int64_t len, float* err_dev, double* relerr_dev, void* stream);
+
 /* Event-based timing of the kernels a survey launches.  Kinds: */
 enum {
   EHI_PROF_SETUP = 0,   /* medium, twiddle and wavefield set-up */
@@ -229,6 +305,7 @@ enum {
   EHI_PROF_HERK = 3,    /* Hessian contraction and its reduction */
   EHI_PROF_FACTOR = 4,  /* penalty and Cholesky */
   EHI_PROF_SOLVE = 5,   /* triangular solves and refinement */
+  EHI_PROF_MODEL = 6,   /* forward/adjoint modelling and time/frequency transfer */
   EHI_PROF_KINDS = 8
 };
 

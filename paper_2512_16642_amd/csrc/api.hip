@@ -9,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "ehi_internal.h"
 
@@ -71,6 +72,14 @@ bool validate(const ehi_survey_desc* d, std::string* why) {
   if ((Z + 4) * (X + 4 + ehi::kRowAlign) > (1LL << 28)) return bad("grid too large");
   long long nsub = (long long)((d->nz + d->stride - 1) / d->stride) * ((d->nx + d->stride - 1) / d->stride);
   if (d->chunk != 0 && d->chunk != 256 && d->chunk != 512) return bad("chunk must be 0, 256 or 512");
+  {
+    const int nzs = (d->nz + d->stride - 1) / d->stride, nxs = (d->nx + d->stride - 1) / d->stride;
+    if ((d->keep_z == 0) != (d->keep_x == 0)) return bad("keep_z and keep_x must both be 0 or both positive");
+    if (d->keep_z < 0 || d->keep_z > nzs || d->keep_x < 0 || d->keep_x > nxs)
+      return bad("keep_z / keep_x must be within the subgrid (0 = no compression)");
+    if (d->keep_z > 0 && d->weighting == EHI_WEIGHT_FINITE_RECORD)
+      return bad("spatial compression applies to the final-spectrum contraction only");
+  }
   const long long chunk = d->chunk ? d->chunk : 256;
   if ((nsub + 256) * chunk * 4 >= (1LL << 31)) return bad("subgrid too large for the staging buffer");
   return true;
@@ -101,6 +110,8 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   g.dt = d->dt;
   g.split_bf16 = d->precision == EHI_PREC_SPLIT_BF16 ? 1 : 0;
   g.weighting = d->weighting;
+  g.keep_z = d->keep_z;
+  g.keep_x = d->keep_x;
   int ntile = ehi::cdiv(g.nr, g.split_bf16 ? 64 : ehi::kHerkTile);
   int pairs = ntile * (ntile + 1) / 2;
   int want = ehi::cdiv(2048, pairs * g.nf);
@@ -154,6 +165,10 @@ ehi::Layout make_layout(const ehi::Geometry& g) {
   L.ghat = take(sizeof(float2) * (size_t)g.nf * g.nr * g.nsub);
   L.hpart = take(sizeof(float2) * (size_t)g.herk_split * g.nf * nn);
   L.hpart64 = take(g.weighting == EHI_WEIGHT_FINITE_RECORD ? sizeof(double2) * (size_t)g.herk_split * g.nf * nn : 0);
+  L.dctz = take(sizeof(float2) * (size_t)g.keep_z * g.nzs);
+  L.dctx = take(sizeof(float2) * (size_t)g.keep_x * g.nxs);
+  L.dtmp = take(sizeof(float2) * (size_t)g.nf * g.nr * g.nxs * g.keep_z);
+  L.gcomp = take(sizeof(float2) * (size_t)g.nf * g.nr * g.keep_z * g.keep_x);
   L.hhat = take(sizeof(double2) * g.nf * nn);
   L.qhat = take(sizeof(double2) * g.nf * nn);
   L.lfac = take(sizeof(double2) * g.nf * nn);
@@ -248,6 +263,7 @@ ehi_status ehi_create(const ehi_survey_desc* desc, void* workspace_dev, size_t w
   s->ws_bytes = ws_bytes;
   s->stream = static_cast<hipStream_t>(stream);
   s->state = ehi::State::Created;
+  s->medium = false;
   s->mu = 0.0;
   hipError_t e = hipGetDevice(&s->device);
   if (e != hipSuccess) {
@@ -263,6 +279,10 @@ ehi_status ehi_create(const ehi_survey_desc* desc, void* workspace_dev, size_t w
     e = hipMemcpyAsync(s->ptr<int32_t>(L.rec), rec.data(), sizeof(int32_t) * 2 * g.nr,
                        hipMemcpyHostToDevice, s->stream);
   if (e == hipSuccess) e = ehi::launch_twiddles(g, s->ptr<double>(L.freq), s->ptr<float2>(L.tw), s->stream);
+  if (e == hipSuccess && g.keep_z > 0) {
+    e = ehi::launch_dct_matrix(g.nzs, g.keep_z, s->ptr<float2>(L.dctz), s->stream);
+    if (e == hipSuccess) e = ehi::launch_dct_matrix(g.nxs, g.keep_x, s->ptr<float2>(L.dctx), s->stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) {
     delete s;
@@ -330,6 +350,7 @@ ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev) {
   PROF(EHI_PROF_SETUP, st);
   EHI_TRY(ehi::launch_vmax(vel_dev, g.nz * g.nx, vmax, st), "vmax");
   EHI_TRY(ehi::launch_coefficients(g, vel_dev, vmax, ca, bd, st), "coefficients");
+  s->medium = true;
   ehi::RowEntry* rowtab = s->ptr<ehi::RowEntry>(L.rowtab);
   EHI_TRY(ehi::launch_row_table(g, bd, rowtab, st), "row table");
   PROF_N(4);
@@ -402,10 +423,28 @@ ehi_status ehi_build_hessian(ehi_survey* s) {
     s->state = ehi::State::Hessian;
     return EHI_OK;
   }
+  const float2* spectra = s->ptr<float2>(L.ghat);
+  if (g.keep_z > 0) {
+    // over the leading 2D DCT-II coefficients of each spectrum row; they hold
+    // the energy in few terms, where the split-BF16 form's per-term rounding no
+    // longer averages out, so this contraction sums FP32 products in FP64
+    // (either precision mode)
+    EHI_TRY(ehi::launch_dct_compress(g, spectra, s->ptr<float2>(L.dctz), s->ptr<float2>(L.dctx),
+                                     s->ptr<float2>(L.dtmp), s->ptr<float2>(L.gcomp), s->stream),
+            "spatial compression");
+    EHI_TRY(ehi::launch_herk_compressed(g, s->ptr<float2>(L.gcomp), g.keep_z * g.keep_x,
+                                        s->ptr<double2>(L.hhat), s->stream),
+            "compressed contraction");
+    PROF_N(4);
+    PROF_END();
+    s->state = ehi::State::Hessian;
+    return EHI_OK;
+  }
+  // over the subgrid points
   if (s->precision == EHI_PREC_SPLIT_BF16) {
-    EHI_TRY(ehi::launch_herk_split_bf16(g, s->ptr<float2>(L.ghat), hpart, s->stream), "herk bf16");
+    EHI_TRY(ehi::launch_herk_split_bf16(g, spectra, hpart, s->stream), "herk bf16");
   } else {
-    EHI_TRY(ehi::launch_herk_fp32(g, s->ptr<float2>(L.ghat), hpart, s->stream), "herk fp32");
+    EHI_TRY(ehi::launch_herk_fp32(g, spectra, hpart, s->stream), "herk fp32");
   }
   EHI_TRY(ehi::launch_herk_reduce(g, hpart, s->ptr<double2>(L.hhat), s->stream), "herk reduce");
   PROF_N(2);
@@ -648,6 +687,180 @@ ehi_status ehi_copy_factor(ehi_survey* s, void* out_dev) {
                                       s->stream),
             "copy factor");
   }
+  return EHI_OK;
+}
+
+ehi_status ehi_set_medium(ehi_survey* s, const float* vel_dev) {
+  g_err.clear();
+  if (!s) return fail(EHI_EINVAL, "survey is NULL");
+  if (!vel_dev) return fail(EHI_EINVAL, "velocity is NULL");
+  const ehi::Geometry& g = s->g;
+  const ehi::Layout& L = s->L;
+  hipStream_t st = s->stream;
+  uint32_t* vmax = s->ptr<uint32_t>(L.vmax);
+  PROF(EHI_PROF_SETUP, st);
+  EHI_TRY(ehi::launch_vmax(vel_dev, g.nz * g.nx, vmax, st), "vmax");
+  EHI_TRY(ehi::launch_coefficients(g, vel_dev, vmax, s->ptr<float>(L.ca), s->ptr<float>(L.bd), st),
+          "coefficients");
+  PROF_N(2);
+  PROF_END();
+  s->medium = true;
+  return EHI_OK;
+}
+
+namespace {
+
+// Shared checks of the modelling calls (the message is set on failure).
+ehi_status model_check(ehi_survey* s, const void* in, const void* out, int32_t ns) {
+  if (!s) return fail(EHI_EINVAL, "survey is NULL");
+  if (!s->medium) return fail(EHI_ESTATE, "no medium: call build_green or set_medium first");
+  if (ns < 0 || ns > (1 << 20)) return fail(EHI_EINVAL, "ns must be in [0, 2^20]");
+  if (ns > 0 && (!in || !out)) return fail(EHI_EINVAL, "input or output is NULL");
+  if (ns > 0 && in == out) return fail(EHI_EINVAL, "input and output may not alias");
+  if (s->g.Z > 65535) return fail(EHI_EINVAL, "padded grid taller than 65535 rows");
+  return EHI_OK;
+}
+
+}  // namespace
+
+ehi_status ehi_forward_subgrid(ehi_survey* s, const float* src_dev, int32_t ns, float* data_dev) {
+  g_err.clear();
+  ehi_status chk = model_check(s, src_dev, data_dev, ns);
+  if (chk != EHI_OK || ns == 0) return chk;
+  const ehi::Geometry& g = s->g;
+  const ehi::Layout& L = s->L;
+  hipStream_t st = s->stream;
+  const float* ca = s->ptr<float>(L.ca);
+  const float* bd = s->ptr<float>(L.bd);
+  const int32_t* rec = s->ptr<int32_t>(L.rec);
+  float* ub[2] = {s->ptr<float>(L.u0), s->ptr<float>(L.u1)};
+  float* w = s->ptr<float>(L.w0);
+  const size_t src_field = (size_t)g.nt * g.nsub, d_field = (size_t)g.nr * g.nt;
+  PROF(EHI_PROF_MODEL, st);
+  for (int s0 = 0; s0 < ns; s0 += g.nrb) {
+    const int nb = std::min(g.nrb, ns - s0);
+    const size_t nplane = (size_t)nb * g.plane();
+    for (int b = 0; b < 2; ++b)
+      EHI_TRY(ehi::launch_fill_u32(reinterpret_cast<uint32_t*>(ub[b]), 0u, nplane, st), "fill");
+    EHI_TRY(ehi::launch_fill_u32(reinterpret_cast<uint32_t*>(w), 0u, nplane, st), "fill");
+    PROF_N(3);
+    const float* src = src_dev + (size_t)s0 * src_field;
+    float* d = data_dev + (size_t)s0 * d_field;
+    int cur = 0;
+    for (int n = 0; n < g.nt; ++n) {
+      // f^n enters u^{n+1}; trace sample n + 1 is stored at column n
+      EHI_TRY(ehi::launch_fd_step(g, ca, bd, ub[cur], ub[1 - cur], w, nb, src + (size_t)n * g.nsub,
+                                  src_field, st),
+              "forward step");
+      EHI_TRY(ehi::launch_record_points(g, rec, ub[1 - cur], d, d_field, n, nb, st), "record traces");
+      PROF_N(2);
+      cur = 1 - cur;
+    }
+  }
+  PROF_END();
+  return EHI_OK;
+}
+
+ehi_status ehi_backpropagate(ehi_survey* s, const float* data_dev, int32_t ns, float* src_dev) {
+  g_err.clear();
+  ehi_status chk = model_check(s, data_dev, src_dev, ns);
+  if (chk != EHI_OK || ns == 0) return chk;
+  const ehi::Geometry& g = s->g;
+  const ehi::Layout& L = s->L;
+  hipStream_t st = s->stream;
+  const float* ca = s->ptr<float>(L.ca);
+  const float* bd = s->ptr<float>(L.bd);
+  const int32_t* rec = s->ptr<int32_t>(L.rec);
+  float* ub[2] = {s->ptr<float>(L.u0), s->ptr<float>(L.u1)};
+  float* w = s->ptr<float>(L.w0);
+  const size_t src_field = (size_t)g.nt * g.nsub, d_field = (size_t)g.nr * g.nt;
+  PROF(EHI_PROF_MODEL, st);
+  for (int s0 = 0; s0 < ns; s0 += g.nrb) {
+    const int nb = std::min(g.nrb, ns - s0);
+    const size_t nplane = (size_t)nb * g.plane();
+    for (int b = 0; b < 2; ++b)
+      EHI_TRY(ehi::launch_fill_u32(reinterpret_cast<uint32_t*>(ub[b]), 0u, nplane, st), "fill");
+    EHI_TRY(ehi::launch_fill_u32(reinterpret_cast<uint32_t*>(w), 0u, nplane, st), "fill");
+    PROF_N(3);
+    const float* d = data_dev + (size_t)s0 * d_field;
+    float* out = src_dev + (size_t)s0 * src_field;
+    int cur = 0;
+    for (int k = 0; k < g.nt; ++k) {
+      // reversed time: step k injects trace sample nt - k (column nt - 1 - k);
+      // u^{k+1} is the source-side field of step nt - 1 - k
+      EHI_TRY(ehi::launch_fd_step(g, ca, bd, ub[cur], ub[1 - cur], w, nb, nullptr, 0, st), "adjoint step");
+      EHI_TRY(ehi::launch_inject_points(g, ca, rec, d, d_field, g.nt - 1 - k, nb, ub[1 - cur], w, st),
+              "inject traces");
+      EHI_TRY(ehi::launch_record_subgrid(g, ub[1 - cur], out, src_field, g.nt - 1 - k, nb, st),
+              "record subgrid");
+      PROF_N(3);
+      cur = 1 - cur;
+    }
+  }
+  PROF_END();
+  return EHI_OK;
+}
+
+ehi_status ehi_residual_spectra(ehi_survey* s, const float* dres_dev, int32_t ns, void* resid_dev,
+                                void* stream) {
+  g_err.clear();
+  if (!s) return fail(EHI_EINVAL, "survey is NULL");
+  if (ns < 0 || ns > (1 << 20)) return fail(EHI_EINVAL, "ns must be in [0, 2^20]");
+  if (ns == 0) return EHI_OK;
+  if (!dres_dev || !resid_dev) return fail(EHI_EINVAL, "input or output is NULL");
+  const ehi::Geometry& g = s->g;
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : s->stream;
+  PROF(EHI_PROF_MODEL, st);
+  EHI_TRY(ehi::launch_resid_spectra(g, dres_dev, ns * g.nr, s->ptr<float2>(s->L.tw),
+                                    static_cast<float2*>(resid_dev), st),
+          "residual spectra");
+  PROF_N(1);
+  PROF_END();
+  return EHI_OK;
+}
+
+ehi_status ehi_multipliers_to_time(ehi_survey* s, const void* mult_dev, int32_t ns, float* out_dev,
+                                   void* stream) {
+  g_err.clear();
+  if (!s) return fail(EHI_EINVAL, "survey is NULL");
+  if (ns < 0 || ns > (1 << 20)) return fail(EHI_EINVAL, "ns must be in [0, 2^20]");
+  const ehi::Geometry& g = s->g;
+  // the frequencies must be distinct bins 0..nt of the 2nt-point transform
+  unsigned long long edge = 0;
+  std::vector<long long> seen;
+  for (int f = 0; f < g.nf; ++f) {
+    const double k = s->freq[f] * 2.0 * g.nt * g.dt;
+    const double kr = std::nearbyint(k);
+    if (std::fabs(k - kr) > 1e-6 || kr < 0 || kr > g.nt)
+      return fail(EHI_EINVAL, "frequencies are not bins 0..nt of the 2nt-point transform");
+    const long long ki = (long long)kr;
+    if (std::find(seen.begin(), seen.end(), ki) != seen.end())
+      return fail(EHI_EINVAL, "a frequency bin occurs twice");
+    seen.push_back(ki);
+    if (ki == 0 || ki == g.nt) edge |= 1ull << f;
+  }
+  if (ns == 0) return EHI_OK;
+  if (!mult_dev || !out_dev) return fail(EHI_EINVAL, "input or output is NULL");
+  if (g.nt > 65535 * 64) return fail(EHI_EINVAL, "nt too large for the inverse transform");
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : s->stream;
+  PROF(EHI_PROF_MODEL, st);
+  EHI_TRY(ehi::launch_to_time(g, static_cast<const float2*>(mult_dev), ns * g.nr, s->ptr<float2>(s->L.tw),
+                              edge, out_dev, st),
+          "inverse transform");
+  PROF_N(1);
+  PROF_END();
+  return EHI_OK;
+}
+
+ehi_status ehi_misfit(const float* dd_dev, const float* pred_dev, const float* obs_dev, int32_t ns,
+                      int64_t len, float* err_dev, double* relerr_dev, void* stream) {
+  g_err.clear();
+  if (ns < 0 || len < 1) return fail(EHI_EINVAL, "need ns >= 0 and len >= 1");
+  if (ns == 0) return EHI_OK;
+  if (!dd_dev || !pred_dev || !obs_dev || !relerr_dev) return fail(EHI_EINVAL, "NULL argument");
+  EHI_TRY(ehi::launch_misfit(dd_dev, pred_dev, obs_dev, ns, (size_t)len, err_dev, relerr_dev,
+                             static_cast<hipStream_t>(stream)),
+          "misfit");
   return EHI_OK;
 }
 

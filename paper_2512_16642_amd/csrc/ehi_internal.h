@@ -35,6 +35,7 @@ struct Geometry {
   int herk_split;  // split-K partitions
   int split_bf16;  // 1: split-BF16 contraction, 0: plain FP32
   int weighting;   // EHI_WEIGHT_LONG_RECORD or EHI_WEIGHT_FINITE_RECORD
+  int keep_z, keep_x;  // leading DCT-II coefficients kept along z and x of the subgrid (0 = no transform)
   int tblock;      // time levels per marching launch (2, 4 or 8; divides chunk)
   int seg_rows;    // output rows per marching segment
   int band;        // columns per marching workgroup (256, 384, 448 or 512)
@@ -58,6 +59,9 @@ struct Layout {
   size_t ghat;      // float2 [nf][nr][nsub]
   size_t hpart;     // float2 [split][nf][nr][nr]
   size_t hpart64;   // double2 [split][nf][nr][nr]  finite-record partial sums (else empty)
+  size_t dctz, dctx;  // complex64 [keep_z][nzs], [keep_x][nxs] DCT-II rows (compression only)
+  size_t dtmp;      // complex64 [nf][nr][nxs][keep_z]  first pass of the 2D transform
+  size_t gcomp;     // complex64 [nf][nr][keep_z * keep_x]  compressed spectra
   size_t hhat;      // double2 [nf][nr][nr]
   size_t qhat;      // double2 [nf][nr][nr]   Hhat + mu I (Hermitian, full)
   size_t lfac;      // double2 [nf][nr][nr]   lower Cholesky factor (FP64 mode)
@@ -122,6 +126,7 @@ struct ehi_survey {
   hipStream_t stream;
   int device;
   ehi::State state;
+  bool medium;      // ca, bd hold a velocity model (build_green or set_medium)
   double mu;
   ehi::Profiler prof;
   template <class T>
@@ -171,8 +176,13 @@ hipError_t launch_herk_r2_chunk(const Geometry& g, const float* stage, const flo
                                 hipStream_t st);
 hipError_t launch_herk_r2_reduce(const Geometry& g, const double2* hpart64, double2* hhat,
                                  hipStream_t st);
+hipError_t launch_dct_matrix(int n, int keep, float2* d, hipStream_t st);
+hipError_t launch_dct_compress(const Geometry& g, const float2* ghat, const float2* dz, const float2* dx,
+                               float2* tmp, float2* gcomp, hipStream_t st);
 hipError_t launch_herk_reduce(const Geometry& g, const float2* hpart, double2* hhat,
                               hipStream_t st);
+hipError_t launch_herk_compressed(const Geometry& g, const float2* gcomp, int K, double2* hhat,
+                                  hipStream_t st);
 hipError_t launch_factor_jobs(const FactorJob* jobs, int njobs, hipStream_t st);
 hipError_t launch_minv_jobs(const FactorJob* jobs, int njobs, int max_nr, hipStream_t st);
 int solve_blocks(const Geometry& g);
@@ -182,6 +192,23 @@ hipError_t launch_apply(const Geometry& g, const float2* m32, const double2* qha
 hipError_t launch_power_iter(const Geometry& g, const double2* hhat, double* eig, int iters,
                              hipStream_t st);
 hipError_t launch_c128_from_c64(const float2* in, double2* out, size_t n, hipStream_t st);
+// forward modelling (S, S^T on the subgrid sources) and the time/frequency transfer
+hipError_t launch_fd_step(const Geometry& g, const float* ca, const float* bd, const float* uin,
+                          float* uout, float* w, int nb_now, const float* src, size_t src_field,
+                          hipStream_t st);
+hipError_t launch_inject_points(const Geometry& g, const float* ca, const int32_t* rec, const float* data,
+                                size_t data_field, int col, int nb_now, float* uout, float* w,
+                                hipStream_t st);
+hipError_t launch_record_subgrid(const Geometry& g, const float* u, float* dst, size_t dst_field, int slot,
+                                 int nb_now, hipStream_t st);
+hipError_t launch_record_points(const Geometry& g, const int32_t* rec, const float* u, float* d,
+                                size_t d_field, int col, int nb_now, hipStream_t st);
+hipError_t launch_resid_spectra(const Geometry& g, const float* dres, int nq, const float2* tw, float2* R,
+                                hipStream_t st);
+hipError_t launch_to_time(const Geometry& g, const float2* X, int nq, const float2* tw,
+                          unsigned long long edge_bins, float* x, hipStream_t st);
+hipError_t launch_misfit(const float* dd, const float* pred, const float* obs, int ns, size_t len,
+                         float* err, double* relerr, hipStream_t st);
 hipError_t launch_c64_from_c128(const double2* in, float2* out, size_t n, hipStream_t st);
 
 }  // namespace ehi

@@ -137,7 +137,24 @@ __global__ void k_c64_from_c128(const double2* __restrict__ in, float2* __restri
   if (i < n) out[i] = make_float2((float)in[i].x, (float)in[i].y);
 }
 
+// Leading keep rows of the orthonormal DCT-II matrix of size n, evaluated in
+// FP64: D[k][m] = s_k cos(pi k (2m + 1) / (2n)), s_0 = sqrt(1/n),
+// s_k = sqrt(2/n); stored as complex64 with a zero imaginary part.
+__global__ void k_dct_matrix(int n, int keep, float2* __restrict__ d) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * keep) return;
+  const int k = e / n, m = e % n;
+  const double s = k == 0 ? sqrt(1.0 / n) : sqrt(2.0 / n);
+  const double v = s * cos(M_PI * (double)k * (2.0 * m + 1.0) / (2.0 * n));
+  d[e] = make_float2((float)v, 0.f);
+}
+
 }  // namespace
+
+hipError_t launch_dct_matrix(int n, int keep, float2* d, hipStream_t st) {
+  hipLaunchKernelGGL(k_dct_matrix, dim3(cdiv(n * keep, 256)), dim3(256), 0, st, n, keep, d);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;

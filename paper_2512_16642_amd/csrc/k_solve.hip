@@ -14,6 +14,8 @@
 // FP64), X += M^H (M r) in FP32.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ehi_internal.h"
 
 namespace ehi {
@@ -151,12 +153,13 @@ __global__ void __launch_bounds__(256) k_tri_inv_cols(const FactorJob* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Batched complex products for the solves, one frequency per blockIdx.z:
-//   C(i, j) = sum_k op(A)(i, k) B(k, j),  i < n (receivers), j < ns (sources)
-// A: MODE 0: Qhat (FP64, n x n, row-major); MODE 1: M (lower, np x np);
-// MODE 2: M^H, i.e. A(i, k) = conj(M(k, i)).  Tiles of M that are zero by
-// triangularity are skipped.  B(k, j) = Bm[j * ldb + k] (source-major, as the
-// residuals are stored), read as zero for k >= n.
+// Batched complex products, one batch entry (frequency) per blockIdx.z:
+//   C(i, j) = sum_{k < kdim} op(A)(i, k) B(k, j),  i < n, j < ns
+// A (arows rows, row-major): MODE 0: A itself (Qhat, or a transform matrix);
+// MODE 1: M (lower, np x np); MODE 2: M^H, i.e. A(i, k) = conj(M(k, i)); MODE 3:
+// conj(A) elementwise.  Tiles of M that are zero by triangularity are skipped.  B(k, j) = Bm[j * ldb + k]
+// (BT = 0: source-major, as the residuals are stored) or Bm[k * ldb + j]
+// (BT = 1).  C(i, j) is stored at C[j * ldc + i].
 // Workgroup: a 64 x 64 tile of C, each thread a 4 x 4 register tile (rows
 // 4 ty + r, columns 4 tx + c); K in stages of 16 through LDS.  The LDS tiles
 // keep the register-tile index outermost (entry r * 16 + ty, c * 16 + tx), so
@@ -170,8 +173,9 @@ struct GemmArgs {
   const void* B;    // float2 (FP32) or double2 (FP64)
   size_t sB;
   int ldb;
-  int n, ns;        // rows of C (receivers), columns (sources)
-  int kmax;         // K extent (n for Qhat, np for M; B rows >= n read as zero)
+  int n, ns;        // rows of C, columns of C
+  int kdim;         // K extent
+  int arows;        // rows of A (n for Qhat, np for M)
   float2* C;        // float2 outputs (kEpiStore, kEpiResid, kEpiOut)
   size_t sC;
   int ldc;
@@ -189,9 +193,11 @@ template <> struct Cx<double> { typedef double2 t; };
 
 constexpr int kGm = 64, kGn = 64, kGk = 16;
 
-template <typename T, int MODE, int EPI>
+// T: type of the operands in memory and LDS; TA: type of the products and sums.
+template <typename T, int MODE, int EPI, int BT = 0, typename TA = T>
 __global__ void __launch_bounds__(256) k_cgemm(GemmArgs a) {
   typedef typename Cx<T>::t C2;
+  typedef typename Cx<TA>::t A2;
   __shared__ C2 As[kGk][kGm];
   __shared__ C2 Bs[kGk][kGn];
   const int f = blockIdx.z;
@@ -200,12 +206,12 @@ __global__ void __launch_bounds__(256) k_cgemm(GemmArgs a) {
   const int ty = tid >> 4, tx = tid & 15;
   const C2* A = static_cast<const C2*>(a.A) + (size_t)f * a.sA;
   const C2* B = static_cast<const C2*>(a.B) + (size_t)f * a.sB;
-  C2 acc[4][4];
+  A2 acc[4][4];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = C2{0, 0};
-  int kbeg = 0, kend = min(a.kmax, a.n);
+    for (int c = 0; c < 4; ++c) acc[r][c] = A2{0, 0};
+  int kbeg = 0, kend = a.kdim;
   if (MODE == 1) kend = min(kend, i0 + kGm);             // M(i, k) = 0 for k > i
   if (MODE == 2) kbeg = i0 / kGk * kGk;                  // conj(M(k, i)) = 0 for k < i
   for (int k0 = kbeg; k0 < kend; k0 += kGk) {
@@ -217,7 +223,7 @@ __global__ void __launch_bounds__(256) k_cgemm(GemmArgs a) {
         const int kk = e / kGm, ii = e % kGm;          // contiguous along i
         const int gk = k0 + kk, gi = i0 + ii;
         C2 v = C2{0, 0};
-        if (gk < kend && gi < a.kmax) {
+        if (gk < kend && gi < a.arows) {
           const C2 m = A[(size_t)gk * a.lda + gi];
           v = C2{m.x, -m.y};
         }
@@ -225,20 +231,34 @@ __global__ void __launch_bounds__(256) k_cgemm(GemmArgs a) {
       } else {
         const int ii = e / kGk, kk = e % kGk;          // contiguous along k
         const int gk = k0 + kk, gi = i0 + ii;
-        As[kk][(ii & 3) * 16 + (ii >> 2)] = (gk < kend && gi < a.kmax) ? A[(size_t)gi * a.lda + gk] : C2{0, 0};
+        C2 v = (gk < kend && gi < a.arows) ? A[(size_t)gi * a.lda + gk] : C2{0, 0};
+        if (MODE == 3) v.y = -v.y;                     // A(i, k) = conj(Am[i * lda + k])
+        As[kk][(ii & 3) * 16 + (ii >> 2)] = v;
       }
-      const int jj = e / kGk, kk = e % kGk;
-      const int gk = k0 + kk, gj = j0 + jj;
-      Bs[kk][(jj & 3) * 16 + (jj >> 2)] = (gk < kend && gj < a.ns) ? B[(size_t)gj * a.ldb + gk] : C2{0, 0};
+      if (BT) {
+        const int kk = e / kGn, jj = e % kGn;          // contiguous along j
+        const int gk = k0 + kk, gj = j0 + jj;
+        Bs[kk][(jj & 3) * 16 + (jj >> 2)] = (gk < kend && gj < a.ns) ? B[(size_t)gk * a.ldb + gj] : C2{0, 0};
+      } else {
+        const int jj = e / kGk, kk = e % kGk;          // contiguous along k
+        const int gk = k0 + kk, gj = j0 + jj;
+        Bs[kk][(jj & 3) * 16 + (jj >> 2)] = (gk < kend && gj < a.ns) ? B[(size_t)gj * a.ldb + gk] : C2{0, 0};
+      }
     }
     __syncthreads();
 #pragma unroll 4
     for (int kk = 0; kk < kGk; ++kk) {
-      C2 av[4], bv[4];
+      A2 av[4], bv[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) av[r] = As[kk][r * 16 + ty];
+      for (int r = 0; r < 4; ++r) {
+        const C2 v = As[kk][r * 16 + ty];
+        av[r] = A2{(TA)v.x, (TA)v.y};
+      }
 #pragma unroll
-      for (int c = 0; c < 4; ++c) bv[c] = Bs[kk][c * 16 + tx];
+      for (int c = 0; c < 4; ++c) {
+        const C2 v = Bs[kk][c * 16 + tx];
+        bv[c] = A2{(TA)v.x, (TA)v.y};
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -256,7 +276,7 @@ __global__ void __launch_bounds__(256) k_cgemm(GemmArgs a) {
     for (int r = 0; r < 4; ++r) {
       const int i = i0 + ty * 4 + r;
       if (i >= a.n) continue;
-      const C2 v = acc[r][c];
+      const A2 v = acc[r][c];
       if (EPI == kEpiStore) {
         a.C[(size_t)f * a.sC + (size_t)j * a.ldc + i] = make_float2((float)v.x, (float)v.y);
       } else if (EPI == kEpiResid) {
@@ -282,10 +302,10 @@ __global__ void __launch_bounds__(256) k_cgemm(GemmArgs a) {
   }
 }
 
-template <typename T, int MODE, int EPI>
+template <typename T, int MODE, int EPI, int BT = 0, typename TA = T>
 hipError_t run_gemm(const GemmArgs& a, int nf, hipStream_t st) {
   dim3 grid(cdiv(a.ns, kGn), cdiv(a.n, kGm), nf);
-  hipLaunchKernelGGL((k_cgemm<T, MODE, EPI>), grid, dim3(256), 0, st, a);
+  hipLaunchKernelGGL((k_cgemm<T, MODE, EPI, BT, TA>), grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -374,7 +394,7 @@ hipError_t launch_apply(const Geometry& g, const float2* m32, const double2* qha
   a.n = n;
   a.ns = cnt;
   // Y = M R
-  a.A = m32; a.sA = npp; a.lda = np; a.kmax = np;
+  a.A = m32; a.sA = npp; a.lda = np; a.arows = np; a.kdim = n;
   a.B = R + (size_t)s0 * n; a.sB = (size_t)rld * n; a.ldb = n;
   a.C = y32; a.sC = sv; a.ldc = n;
   hipError_t e = run_gemm<float, 1, kEpiStore>(a, g.nf, st);
@@ -391,7 +411,7 @@ hipError_t launch_apply(const Geometry& g, const float2* m32, const double2* qha
   for (int it = 0; it < refine; ++it) {
     // r = R - Qhat X (FP64)
     GemmArgs q = a;
-    q.A = qhat; q.sA = nn; q.lda = n; q.kmax = n;
+    q.A = qhat; q.sA = nn; q.lda = n; q.arows = n; q.kdim = n;
     q.B = x64; q.sB = sv; q.ldb = n;
     q.R = R + (size_t)s0 * n; q.sR = (size_t)rld * n; q.ldr = n;
     q.C = r32; q.sC = sv; q.ldc = n;
@@ -399,7 +419,7 @@ hipError_t launch_apply(const Geometry& g, const float2* m32, const double2* qha
     if (e != hipSuccess) return e;
     // Y = M r
     GemmArgs y = a;
-    y.A = m32; y.sA = npp; y.lda = np; y.kmax = np;
+    y.A = m32; y.sA = npp; y.lda = np; y.arows = np; y.kdim = n;
     y.B = r32; y.sB = sv; y.ldb = n;
     y.C = y32; y.sC = sv; y.ldc = n;
     e = run_gemm<float, 1, kEpiStore>(y, g.nf, st);
@@ -416,6 +436,64 @@ hipError_t launch_apply(const Geometry& g, const float2* m32, const double2* qha
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_dct_compress(const Geometry& g, const float2* ghat, const float2* dz, const float2* dx,
+                               float2* tmp, float2* gcomp, hipStream_t st) {
+  // per spectrum row (frequency, receiver), seen as an nzs x nxs image:
+  //   T(ix, kz) = sum_iz Dz(kz, iz) G(iz, ix),  stored [row][ix][kz]
+  //   C(kz, kx) = sum_ix Dx(kx, ix) T(ix, kz),  stored [row][kz][kx]
+  // (complex64 operands, products and sums in FP64)
+  const int rows = g.nf * g.nr;
+  for (int r0 = 0; r0 < rows; r0 += 65535) {
+    const int nb = std::min(65535, rows - r0);
+    GemmArgs p{};
+    p.A = dz; p.sA = 0; p.lda = g.nzs; p.arows = g.keep_z;
+    p.B = ghat + (size_t)r0 * g.nsub; p.sB = (size_t)g.nsub; p.ldb = g.nxs;
+    p.n = g.keep_z; p.ns = g.nxs; p.kdim = g.nzs;
+    p.C = tmp + (size_t)r0 * g.nxs * g.keep_z; p.sC = (size_t)g.nxs * g.keep_z; p.ldc = g.keep_z;
+    hipError_t e = run_gemm<float, 0, kEpiStore, 1, double>(p, nb, st);
+    if (e != hipSuccess) return e;
+    GemmArgs q{};
+    q.A = dx; q.sA = 0; q.lda = g.nxs; q.arows = g.keep_x;
+    q.B = tmp + (size_t)r0 * g.nxs * g.keep_z; q.sB = (size_t)g.nxs * g.keep_z; q.ldb = g.keep_z;
+    q.n = g.keep_x; q.ns = g.keep_z; q.kdim = g.nxs;
+    q.C = gcomp + (size_t)r0 * g.keep_z * g.keep_x; q.sC = (size_t)g.keep_z * g.keep_x; q.ldc = g.keep_x;
+    e = run_gemm<float, 0, kEpiStore, 1, double>(q, nb, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Hhat = (H + H^H) / 2 in place, one thread per pair i <= j: the product below
+// forms H(i, j) and H(j, i) from the same terms in different orders.
+__global__ void k_hermitize(int n, double2* __restrict__ H) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j < i || j >= n) return;
+  double2* M = H + (size_t)blockIdx.z * n * n;
+  const double2 a = M[(size_t)i * n + j], b = M[(size_t)j * n + i];
+  const double2 v = make_double2(0.5 * (a.x + b.x), i == j ? 0.0 : 0.5 * (a.y - b.y));
+  M[(size_t)i * n + j] = v;
+  M[(size_t)j * n + i] = make_double2(v.x, -v.y);
+}
+
+// Hhat of the compressed spectra C (complex64 [nf][nr][K]):
+//   Hhat(i, j) = sum_k C(i, k) conj(C(j, k)),
+// FP32 operands, FP64 products and sums.  The product computes
+// conj(Hhat(i, j)) = sum_k conj(C(i, k)) C(j, k) and stores it at [j][i], which
+// is where Hhat(j, i) = conj(Hhat(i, j)) belongs.
+hipError_t launch_herk_compressed(const Geometry& g, const float2* gcomp, int K, double2* hhat,
+                                  hipStream_t st) {
+  GemmArgs p{};
+  p.A = gcomp; p.sA = (size_t)g.nr * K; p.lda = K; p.arows = g.nr;
+  p.B = gcomp; p.sB = (size_t)g.nr * K; p.ldb = K;
+  p.n = g.nr; p.ns = g.nr; p.kdim = K;
+  p.X = hhat; p.sX = (size_t)g.nr * g.nr; p.ldx = g.nr;
+  hipError_t e = run_gemm<float, 3, kEpiX64Set, 0, double>(p, g.nf, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_hermitize, dim3(cdiv(g.nr, 256), g.nr, g.nf), dim3(256), 0, st, g.nr, hhat);
+  return hipGetLastError();
 }
 
 hipError_t launch_power_iter(const Geometry& g, const double2* hhat, double* eig, int iters,

@@ -34,8 +34,10 @@ SYMBOLS = (
     "ehi_copy_hessian", "ehi_load_hessian", "ehi_copy_factor", "ehi_destroy", "ehi_last_error",
     "ehi_version", "ehi_profile_enable", "ehi_profile_read", "ehi_batch_workspace_bytes",
     "ehi_factor_batch", "ehi_set_stream", "ehi_set_launch", "ehi_get_launch",
+    "ehi_set_medium", "ehi_forward_subgrid", "ehi_backpropagate", "ehi_residual_spectra",
+    "ehi_multipliers_to_time", "ehi_misfit",
 )
-PROF_KINDS = ("setup", "step", "dft", "herk", "factor", "solve")
+PROF_KINDS = ("setup", "step", "dft", "herk", "factor", "solve", "model")
 _PROF_N = 8
 
 
@@ -55,6 +57,7 @@ class SurveyDesc(ctypes.Structure):
         ("nf", ctypes.c_int32), ("freq_hz", ctypes.POINTER(ctypes.c_double)),
         ("precision", ctypes.c_int32), ("max_ns", ctypes.c_int32), ("nr_batch", ctypes.c_int32),
         ("weighting", ctypes.c_int32), ("chunk", ctypes.c_int32),
+        ("keep_z", ctypes.c_int32), ("keep_x", ctypes.c_int32),
     ]
 
 
@@ -103,6 +106,16 @@ def lib() -> ctypes.CDLL:
     L.ehi_set_launch.restype = st
     L.ehi_get_launch.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.ehi_get_launch.restype = st
+    L.ehi_set_medium.argtypes = [vp, vp]
+    L.ehi_set_medium.restype = st
+    for name in ("ehi_forward_subgrid", "ehi_backpropagate"):
+        getattr(L, name).argtypes = [vp, vp, i32, vp]
+        getattr(L, name).restype = st
+    for name in ("ehi_residual_spectra", "ehi_multipliers_to_time"):
+        getattr(L, name).argtypes = [vp, vp, i32, vp, vp]
+        getattr(L, name).restype = st
+    L.ehi_misfit.argtypes = [vp, vp, vp, i32, ctypes.c_int64, vp, vp, vp]
+    L.ehi_misfit.restype = st
     L.ehi_destroy.argtypes = [vp]
     L.ehi_destroy.restype = st
     L.ehi_last_error.argtypes = []
@@ -137,7 +150,7 @@ def _require(t: torch.Tensor, dtype, shape, name: str, device: torch.device):
 
 
 def make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision, max_ns,
-              nr_batch, weighting="long_record", chunk=0):
+              nr_batch, weighting="long_record", chunk=0, keep=(0, 0)):
     riz = np.ascontiguousarray(rec_iz, dtype=np.int32)
     rix = np.ascontiguousarray(rec_ix, dtype=np.int32)
     fr = np.ascontiguousarray(freqs_hz, dtype=np.float64)
@@ -150,7 +163,7 @@ def make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision
                    nf=len(fr), freq_hz=fr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                    precision=prec, max_ns=max_ns, nr_batch=nr_batch,
                    weighting=_WEIGHT[weighting] if isinstance(weighting, str) else int(weighting),
-                   chunk=int(chunk))
+                   chunk=int(chunk), keep_z=int(keep[0]), keep_x=int(keep[1]))
     return d, (riz, rix, fr)   # keep the arrays alive with the descriptor
 
 
@@ -168,7 +181,7 @@ class Survey:
     def __init__(self, *, nz: int, nx: int, nb: int, h: float, dt: float, nt: int, stride: int,
                  rec_iz: Sequence[int], rec_ix: Sequence[int], freqs_hz: Sequence[float],
                  precision="split_bf16", max_ns: int = 256, nr_batch: int = 0,
-                 weighting="long_record", chunk: int = 0, device=None,
+                 weighting="long_record", chunk: int = 0, keep=(0, 0), device=None,
                  stream: Optional[torch.cuda.Stream] = None):
         self._h = None
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
@@ -180,7 +193,7 @@ class Survey:
         self.max_ns = max_ns
         self.nr_batch = nr_batch
         d, keep = make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision,
-                            max_ns, nr_batch, weighting, chunk)
+                            max_ns, nr_batch, weighting, chunk, keep)
         self.weighting = weighting
         L = lib()
         nbytes = L.ehi_workspace_bytes(ctypes.byref(d))
@@ -230,6 +243,64 @@ class Survey:
         v = ctypes.c_double(0.0)
         _check(lib().ehi_lambda_max(self._h, ctypes.byref(v)))
         return float(v.value)
+
+    # -- steps either side of the deblur, forward/adjoint modelling --------------
+    def set_medium(self, vel: torch.Tensor):
+        """Load the medium for forward_subgrid / backpropagate only."""
+        _require(vel, torch.float32, (self.nz, self.nx), "vel", self.device)
+        self._vel = vel
+        _check(lib().ehi_set_medium(self._h, ctypes.c_void_p(vel.data_ptr())))
+
+    def forward_subgrid(self, src: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """S src: ``src`` float32 [ns][nt][nzs][nxs] -> traces [ns][nr][nt]."""
+        ns = src.shape[0]
+        _require(src, torch.float32, (ns, self.nt, self.nzs, self.nxs), "src", self.device)
+        if out is None:
+            out = torch.empty((ns, self.nr, self.nt), dtype=torch.float32, device=self.device)
+        _require(out, torch.float32, (ns, self.nr, self.nt), "out", self.device)
+        _check(lib().ehi_forward_subgrid(self._h, ctypes.c_void_p(src.data_ptr()), ns,
+                                         ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def backpropagate(self, data: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """S^T data: traces float32 [ns][nr][nt] -> subgrid source [ns][nt][nzs][nxs]."""
+        ns = data.shape[0]
+        _require(data, torch.float32, (ns, self.nr, self.nt), "data", self.device)
+        if out is None:
+            out = torch.empty((ns, self.nt, self.nzs, self.nxs), dtype=torch.float32, device=self.device)
+        _require(out, torch.float32, (ns, self.nt, self.nzs, self.nxs), "out", self.device)
+        _check(lib().ehi_backpropagate(self._h, ctypes.c_void_p(data.data_ptr()), ns,
+                                       ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def residual_spectra(self, dres: torch.Tensor, out: Optional[torch.Tensor] = None,
+                         stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+        """Time-domain residuals float32 [ns][nr][nt] -> complex64 [nf][ns][nr]."""
+        ns = dres.shape[0]
+        _require(dres, torch.float32, (ns, self.nr, self.nt), "dres", self.device)
+        if out is None:
+            out = torch.empty((self.nf, ns, self.nr), dtype=torch.complex64, device=self.device)
+        _require(out, torch.complex64, (self.nf, ns, self.nr), "out", self.device)
+        sp = 0 if stream is None else stream.cuda_stream
+        _check(lib().ehi_residual_spectra(self._h, ctypes.c_void_p(dres.data_ptr()), ns,
+                                          ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(sp)))
+        return out
+
+    def multipliers_to_time(self, X: torch.Tensor, out: Optional[torch.Tensor] = None,
+                            stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+        """Multipliers complex64 [nf][ns][nr] (frequencies = bins of the
+        2nt-point transform) -> float32 [ns][nr][nt]."""
+        if X.dim() != 3:
+            raise ValueError("X must be [nf][ns][nr]")
+        ns = X.shape[1]
+        _require(X, torch.complex64, (self.nf, ns, self.nr), "X", self.device)
+        if out is None:
+            out = torch.empty((ns, self.nr, self.nt), dtype=torch.float32, device=self.device)
+        _require(out, torch.float32, (ns, self.nr, self.nt), "out", self.device)
+        sp = 0 if stream is None else stream.cuda_stream
+        _check(lib().ehi_multipliers_to_time(self._h, ctypes.c_void_p(X.data_ptr()), ns,
+                                             ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(sp)))
+        return out
 
     # -- stage inputs/outputs ------------------------------------------------------
     def copy_green_dft(self) -> torch.Tensor:
@@ -307,6 +378,28 @@ class Survey:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def misfit(dd: torch.Tensor, pred: torch.Tensor, obs: torch.Tensor, err: Optional[torch.Tensor] = None,
+           stream: Optional[torch.cuda.Stream] = None):
+    """(err = dd - pred, relerr[s] = sum err^2 / sum obs^2) for float32 records
+    [ns][...] of equal shape on one device; relerr float64 [ns]."""
+    if dd.shape != pred.shape or dd.shape != obs.shape:
+        raise ValueError("dd, pred and obs must have the same shape")
+    ns = dd.shape[0]
+    dev = dd.device
+    for t, n in ((dd, "dd"), (pred, "pred"), (obs, "obs")):
+        _require(t, torch.float32, dd.shape, n, dev)
+    if err is None:
+        err = torch.empty_like(dd)
+    _require(err, torch.float32, dd.shape, "err", dev)
+    rel = torch.empty(ns, dtype=torch.float64, device=dev)
+    n_per = dd.numel() // max(ns, 1)
+    sp = 0 if stream is None else stream.cuda_stream
+    _check(lib().ehi_misfit(ctypes.c_void_p(dd.data_ptr()), ctypes.c_void_p(pred.data_ptr()),
+                            ctypes.c_void_p(obs.data_ptr()), ns, n_per, ctypes.c_void_p(err.data_ptr()),
+                            ctypes.c_void_p(rel.data_ptr()), ctypes.c_void_p(sp)))
+    return err, rel
 
 
 def factor_batch(surveys: Sequence["Survey"], mu: Sequence[float],

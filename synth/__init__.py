@@ -180,6 +180,46 @@ def residuals_device(nf: int, ns: int, nr: int, seed: int, device) -> "torch.Ten
     return torch.complex(z[0], z[1])
 
 
+def time_residuals(ns: int, nr: int, nt: int, seed: int) -> np.ndarray:
+    """Time-domain data residuals ``[ns][nr][nt]`` float32, i.i.d. N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((ns, nr, nt), dtype=np.float32)
+
+
+def subgrid_sources(ns: int, nt: int, nzs: int, nxs: int, seed: int) -> np.ndarray:
+    """Source fields on the subgrid ``[ns][nt][nzs][nxs]`` float32, i.i.d. N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((ns, nt, nzs, nxs), dtype=np.float32)
+
+
+def ricker(nt: int, dt: float, f0: float, t0: float | None = None) -> np.ndarray:
+    """Ricker wavelet of peak frequency f0 at samples n = 0..nt-1 (time n dt),
+    centred at t0 (default 1.5 / f0), float32."""
+    t0 = 1.5 / f0 if t0 is None else t0
+    a = (math.pi * f0 * (np.arange(nt) * dt - t0)) ** 2
+    return ((1.0 - 2.0 * a) * np.exp(-a)).astype(np.float32)
+
+
+def smoothed(vel: np.ndarray, radius: int) -> np.ndarray:
+    """Box-filtered copy of a velocity model (edges replicated): a starting
+    model for the accuracy test."""
+    from scipy.ndimage import uniform_filter
+    return uniform_filter(np.asarray(vel, dtype=np.float64), size=2 * radius + 1,
+                          mode="nearest").astype(np.float32)
+
+
+def nearest_bins(nt: int, dt: float, freqs_hz) -> tuple:
+    """The bins of the 2nt-point transform nearest to the given frequencies
+    (distinct, ascending)."""
+    k = sorted({int(round(f * 2.0 * nt * dt)) for f in freqs_hz})
+    return transform_bins(nt, dt, k)
+
+
+def transform_bins(nt: int, dt: float, k) -> tuple:
+    """Frequencies (Hz) of bins k of the 2nt-point transform: k / (2 nt dt)."""
+    return tuple(float(kk) / (2.0 * nt * dt) for kk in k)
+
+
 # ---------------------------------------------------------------------------
 # the workloads
 # ---------------------------------------------------------------------------
@@ -274,6 +314,22 @@ def ragged(nz: int = 45, nx: int = 77, nb: int = 9, nt: int = 157, nr: int = 5,
         rec_ix=tuple(3 + 13 * k for k in range(nr)), ns=5, stride=stride,
         model_seed=seed, resid_seed=seed + 1, model_kind="layered", n_interfaces=4,
         v_min=1500.0, v_max=3000.0)
+
+
+def accuracy_micro(nt: int = 60) -> Survey:
+    """A survey whose frequencies are every bin 0..nt of the 2nt-point
+    transform (24 x 30 grid, 6-cell sponge, 4 surface receivers, stride 1), for
+    the accuracy test at full band."""
+    s = micro(nz=24, nx=30, nb=6, nt=nt, nr=4, seed=21)
+    return s.with_(name=f"accuracy-micro-nt{nt}", freqs_hz=transform_bins(nt, s.dt, range(nt + 1)))
+
+
+def accuracy_tiny() -> Survey:
+    """The tiny survey with the 21 bins of the 2nt-point transform in 2-12 Hz
+    (0.5 Hz apart), for the accuracy-test workload."""
+    t = tiny()
+    return t.with_(name="accuracy-tiny-101x101-nr16-nt1000-nf21",
+                   freqs_hz=transform_bins(t.nt, t.dt, range(4, 25)))
 
 
 WORKLOADS = {

@@ -52,6 +52,8 @@ def test_workspace_bytes_valid(ehi):
     dict(precision=7), dict(max_ns=0), dict(nr_batch=-3), dict(weighting=2),
     dict(weighting="finite_record", precision="plain_fp32"),
     dict(weighting="finite_record", nr_batch=1), dict(chunk=128), dict(chunk=300),
+    dict(keep=(3, 0)), dict(keep=(21, 5)), dict(keep=(5, 31)), dict(keep=(-1, 4)),
+    dict(keep=(4, 4), weighting="finite_record"),
 ])
 def test_workspace_bytes_rejects(ehi, bad):
     with pytest.raises(ehi.EhiError) as ei:
@@ -65,6 +67,13 @@ def test_finite_record_weighting_accepted_with_all_receivers(ehi):
     b = ehi.workspace_bytes(**_desc_kw(weighting="finite_record"))
     c = ehi.workspace_bytes(**_desc_kw(weighting="finite_record", nr_batch=2))
     assert b > a and c == b   # FP64 partial sums of the finite-record contraction
+
+
+def test_compression_buffers(ehi):
+    a = ehi.workspace_bytes(**_desc_kw())
+    b = ehi.workspace_bytes(**_desc_kw(keep=(5, 6)))
+    c = ehi.workspace_bytes(**_desc_kw(keep=(20, 30)))
+    assert a < b < c
 
 
 def test_longer_staging_window(ehi):
@@ -100,3 +109,17 @@ def test_null_handle_calls_fail_cleanly(ehi):
     assert L.ehi_build_hessian(None) == ehi.EHI_EINVAL
     assert L.ehi_factor(None, ctypes.c_double(1.0), None) == ehi.EHI_EINVAL
     assert L.ehi_destroy(None) == ehi.EHI_OK
+
+
+def test_modelling_calls_validate_on_the_host(ehi):
+    L = ehi.lib()
+    assert L.ehi_set_medium(None, None) == ehi.EHI_EINVAL
+    assert L.ehi_forward_subgrid(None, None, 0, None) == ehi.EHI_EINVAL
+    assert L.ehi_backpropagate(None, None, 0, None) == ehi.EHI_EINVAL
+    assert L.ehi_residual_spectra(None, None, 0, None, None) == ehi.EHI_EINVAL
+    assert L.ehi_multipliers_to_time(None, None, 0, None, None) == ehi.EHI_EINVAL
+    # the misfit needs no survey: empty batches succeed, bad sizes and NULLs fail
+    assert L.ehi_misfit(None, None, None, 0, 1, None, None, None) == ehi.EHI_OK
+    assert L.ehi_misfit(None, None, None, -1, 1, None, None, None) == ehi.EHI_EINVAL
+    assert L.ehi_misfit(None, None, None, 1, 0, None, None, None) == ehi.EHI_EINVAL
+    assert L.ehi_misfit(None, None, None, 2, 10, None, None, None) == ehi.EHI_EINVAL
