@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # precision, time levels, segment rows, band width, receivers per launch); recorded in
 # profiles/survey_layered-1000x300_pmc.md.  Any other shape reports null.
 MEASURED_TRAFFIC = {
-    ("layered-1000x300-nr200-nt4000-nf30-ns200", "split_bf16", 8, 128, 256, 200): (461812.5 * 2 + 1152341.5) * 1024,
+    ("layered-1000x300-nr200-nt4000-nf30-ns200", "split_bf16", 8, 128, 256, 200): (461956.5 * 2 + 1152470.3) * 1024,
 }
 
 
@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--acc-ns", type=int, default=16, help="accuracy: sources per step")
     ap.add_argument("--chunk", type=int, default=512, choices=[256, 512],
                     help="time samples per DFT staging window")
+    ap.add_argument("--windows", type=int, default=1, choices=[1, 2],
+                    help="staging windows (2: the DFT of one overlaps the stepping of the next)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=300, help="FD steps in the CPU sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -367,7 +369,7 @@ def main():
     R = torch.from_numpy(s.residuals()).to(dev)
     X = torch.empty_like(R)
     sv = ehi.survey_from(s, precision=args.precision, max_ns=s.ns, nr_batch=args.nr_batch,
-                         weighting=args.weighting, chunk=args.chunk)
+                         weighting=args.weighting, chunk=args.chunk, windows=args.windows)
     print(f"# workload {s.name} precision {args.precision} workspace {sv.workspace_bytes / 1e9:.2f} GB",
           file=sys.stderr, flush=True)
 
@@ -459,7 +461,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": s.name, "precision": args.precision, "weighting": args.weighting,
-                   "chunk": args.chunk,
+                   "chunk": args.chunk, "windows": args.windows,
                    "nz": s.nz, "nx": s.nx,
                    "nb": s.nb, "nr": s.nr, "nt": s.nt, "nf": s.nf, "ns": s.ns, "stride": s.stride,
                    "nr_batch": nrb},

@@ -111,6 +111,10 @@ typedef enum {
  *             orthonormal 2D DCT-II and only the leading keep_z x keep_x
  *             coefficients enter Hhat (exact when all are kept).  Long-record
  *             weighting only.
+ *   windows   staging windows (0 = 1; 1 or 2).  With 2, the DFT of a full
+ *             window runs on a second, library-owned stream while the time
+ *             steps fill the other window, at twice the staging memory.
+ *             Results do not depend on it.
  */
 typedef struct {
   int32_t nz, nx, nb;
@@ -128,6 +132,7 @@ typedef struct {
   int32_t weighting;
   int32_t chunk;
   int32_t keep_z, keep_x;
+  int32_t windows;
 } ehi_survey_desc;
 
 typedef struct ehi_survey ehi_survey;

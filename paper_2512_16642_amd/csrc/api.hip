@@ -80,6 +80,7 @@ bool validate(const ehi_survey_desc* d, std::string* why) {
     if (d->keep_z > 0 && d->weighting == EHI_WEIGHT_FINITE_RECORD)
       return bad("spatial compression applies to the final-spectrum contraction only");
   }
+  if (d->windows < 0 || d->windows > 2) return bad("windows must be 0, 1 or 2");
   const long long chunk = d->chunk ? d->chunk : 256;
   if ((nsub + 256) * chunk * 4 >= (1LL << 31)) return bad("subgrid too large for the staging buffer");
   return true;
@@ -101,6 +102,7 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   g.nsub = g.nzs * g.nxs;
   g.nsub_p = (int)ehi::align_up((size_t)g.nsub, 256);  // the DFT reads whole 256-point blocks
   g.chunk = d->chunk ? d->chunk : 256;
+  g.windows = d->windows == 2 ? 2 : 1;
   g.nt = d->nt;
   g.nr = d->nr;
   g.nf = d->nf;
@@ -161,7 +163,7 @@ ehi::Layout make_layout(const ehi::Geometry& g) {
   L.u1 = take(sizeof(float) * g.plane() * g.nrb);
   L.w0 = take(sizeof(float) * g.plane() * g.nrb);
   L.w1 = take(sizeof(float) * g.plane() * g.nrb);
-  L.stage = take(sizeof(float) * (size_t)g.nrb * g.chunk * g.nsub_p);
+  L.stage = take(sizeof(float) * (size_t)g.windows * g.nrb * g.chunk * g.nsub_p);
   L.ghat = take(sizeof(float2) * (size_t)g.nf * g.nr * g.nsub);
   L.hpart = take(sizeof(float2) * (size_t)g.herk_split * g.nf * nn);
   L.hpart64 = take(g.weighting == EHI_WEIGHT_FINITE_RECORD ? sizeof(double2) * (size_t)g.herk_split * g.nf * nn : 0);
@@ -216,6 +218,22 @@ hipError_t Profiler::end() {
 }
 
 }  // namespace ehi
+
+namespace {
+
+// The second stream and its events (two staging windows); safe on a partly
+// created survey.
+void release_side(ehi_survey* s) {
+  for (int b = 0; b < 2; ++b) {
+    if (s->ev_marched[b]) (void)hipEventDestroy(s->ev_marched[b]);
+    if (s->ev_dft[b]) (void)hipEventDestroy(s->ev_dft[b]);
+    s->ev_marched[b] = s->ev_dft[b] = nullptr;
+  }
+  if (s->side) (void)hipStreamDestroy(s->side);
+  s->side = nullptr;
+}
+
+}  // namespace
 
 #define PROF(kind, st) EHI_TRY(s->prof.begin((kind), (st)), "profiler event")
 #define PROF_N(n) s->prof.count(n)
@@ -284,7 +302,15 @@ ehi_status ehi_create(const ehi_survey_desc* desc, void* workspace_dev, size_t w
     if (e == hipSuccess) e = ehi::launch_dct_matrix(g.nxs, g.keep_x, s->ptr<float2>(L.dctx), s->stream);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e == hipSuccess && g.windows == 2) {
+    e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+      e = hipEventCreateWithFlags(&s->ev_marched[b], hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_dft[b], hipEventDisableTiming);
+    }
+  }
   if (e != hipSuccess) {
+    release_side(s);
     delete s;
     return hip_fail(e, "ehi_create set-up");
   }
@@ -299,6 +325,7 @@ ehi_status ehi_destroy(ehi_survey* s) {
     (void)hipEventDestroy(r.start);
     (void)hipEventDestroy(r.stop);
   }
+  release_side(s);
   delete s;
   return EHI_OK;
 }
@@ -356,14 +383,28 @@ ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev) {
   PROF_N(4);
   const float2* tw = s->ptr<float2>(L.tw);
   float2* ghat = s->ptr<float2>(L.ghat);
-  float* stage = s->ptr<float>(L.stage);
+  const size_t wfloats = (size_t)g.nrb * g.chunk * g.nsub_p;
+  float* stage[2] = {s->ptr<float>(L.stage), s->ptr<float>(L.stage) + (g.windows == 2 ? wfloats : 0)};
+  // with two windows the DFT of window buffer b runs on the side stream once
+  // the steps filling it are done (ev_marched[b]); steps into b wait until
+  // that DFT has read it (ev_dft[b])
+  const bool two = g.windows == 2;
+  hipStream_t dst = two ? s->side : st;
+  bool pending[2] = {false, false};
+  auto free_window = [&](int b) -> hipError_t {
+    if (!two || !pending[b]) return hipSuccess;
+    pending[b] = false;
+    return hipStreamWaitEvent(st, s->ev_dft[b], 0);
+  };
   for (int r0 = 0; r0 < g.nr; r0 += g.nrb) {
     const int nb_now = std::min(g.nrb, g.nr - r0);
     float* ub[2] = {s->ptr<float>(L.u0), s->ptr<float>(L.u1)};
     float* wb[2] = {s->ptr<float>(L.w0), s->ptr<float>(L.w1)};
+    int b = 0;  // window buffer being filled
+    EHI_TRY(free_window(0), "window wait");
     PROF(EHI_PROF_SETUP, st);
     EHI_TRY(ehi::launch_wave_init(g, vel_dev, s->ptr<int32_t>(L.rec), r0, nb_now, ub[0], wb[0],
-                                  stage, st),
+                                  stage[0], st),
             "wave init");
     // the marching kernel relies on zero ghost rings in both ping-pong buffers
     const size_t nplane = (size_t)nb_now * g.plane();
@@ -376,24 +417,34 @@ ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev) {
     for (;;) {
       if (n_cur % g.chunk == 0 || n_cur == g.nt) {
         const int n0 = (n_cur - 1) / g.chunk * g.chunk + 1;
+        if (two) {
+          EHI_TRY(hipEventRecord(s->ev_marched[b], st), "window event");
+          EHI_TRY(hipStreamWaitEvent(dst, s->ev_marched[b], 0), "window wait");
+        }
         if (g.weighting == EHI_WEIGHT_FINITE_RECORD) {
           // the running spectra of this window, before the DFT advances them
-          PROF(EHI_PROF_HERK, st);
-          EHI_TRY(ehi::launch_herk_r2_chunk(g, stage, tw, ghat, n0, n_cur - n0 + 1, n0 == 1,
-                                            s->ptr<double2>(L.hpart64), st),
+          PROF(EHI_PROF_HERK, dst);
+          EHI_TRY(ehi::launch_herk_r2_chunk(g, stage[b], tw, ghat, n0, n_cur - n0 + 1, n0 == 1,
+                                            s->ptr<double2>(L.hpart64), dst),
                   "finite-record contraction");
           PROF_N(1);
         }
-        PROF(EHI_PROF_DFT, st);
-        EHI_TRY(ehi::launch_dft_chunk(g, stage, tw, n0, n_cur - n0 + 1, n0 == 1, r0, nb_now, ghat, st),
+        PROF(EHI_PROF_DFT, dst);
+        EHI_TRY(ehi::launch_dft_chunk(g, stage[b], tw, n0, n_cur - n0 + 1, n0 == 1, r0, nb_now, ghat, dst),
                 "dft chunk");
         PROF_N(1);
+        if (two) {
+          EHI_TRY(hipEventRecord(s->ev_dft[b], dst), "window event");
+          pending[b] = true;
+          b ^= 1;
+          if (n_cur != g.nt) EHI_TRY(free_window(b), "window wait");
+        }
       }
       if (n_cur == g.nt) break;
       // advance to the next multiple of tblock (never past the chunk end: tblock | chunk)
       const int target = std::min(g.nt, (n_cur / g.tblock + 1) * g.tblock);
       PROF(EHI_PROF_STEP, st);
-      EHI_TRY(ehi::launch_march(g, ca, bd, rowtab, ub[cur], wb[cur], ub[1 - cur], wb[1 - cur], stage,
+      EHI_TRY(ehi::launch_march(g, ca, bd, rowtab, ub[cur], wb[cur], ub[1 - cur], wb[1 - cur], stage[b],
                                 n_cur % g.chunk, target - n_cur, nb_now, st),
               "time steps");
       PROF_N(1);
@@ -401,6 +452,9 @@ ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev) {
       n_cur = target;
     }
   }
+  // the survey's stream resumes after the last DFT
+  EHI_TRY(free_window(0), "window wait");
+  EHI_TRY(free_window(1), "window wait");
   PROF_END();
   s->state = ehi::State::Green;
   return EHI_OK;

@@ -31,6 +31,7 @@ struct Geometry {
   int stride, sshift, nzs, nxs, nsub;  // stride = 1 << sshift
   int nsub_p;      // staging row pitch (nsub rounded up to 256)
   int chunk;       // time samples per DFT chunk (staging depth; multiple of 4 and tblock)
+  int windows;     // staging windows: 1, or 2 (the DFT of one overlaps the stepping of the next)
   int nt, nr, nf, nrb, max_ns;
   int herk_split;  // split-K partitions
   int split_bf16;  // 1: split-BF16 contraction, 0: plain FP32
@@ -55,7 +56,7 @@ struct Layout {
   size_t tw;        // float2 [nt][nf] exp(-i w n dt), n = 1..nt
   size_t u0, u1;    // float [nrb][Zp][Xp]  (ping-pong)
   size_t w0, w1;    // float [nrb][Zp][Xp]  (ping-pong)
-  size_t stage;     // float [nrb][chunk][nsub_p]
+  size_t stage;     // float [windows][nrb][chunk][nsub_p]
   size_t ghat;      // float2 [nf][nr][nsub]
   size_t hpart;     // float2 [split][nf][nr][nr]
   size_t hpart64;   // double2 [split][nf][nr][nr]  finite-record partial sums (else empty)
@@ -124,6 +125,10 @@ struct ehi_survey {
   char* ws;
   size_t ws_bytes;
   hipStream_t stream;
+  // two staging windows: the DFT (and finite-record contraction) of a window
+  // runs on `side` while `stream` steps into the other window
+  hipStream_t side;
+  hipEvent_t ev_marched[2], ev_dft[2];
   int device;
   ehi::State state;
   bool medium;      // ca, bd hold a velocity model (build_green or set_medium)

@@ -57,7 +57,7 @@ class SurveyDesc(ctypes.Structure):
         ("nf", ctypes.c_int32), ("freq_hz", ctypes.POINTER(ctypes.c_double)),
         ("precision", ctypes.c_int32), ("max_ns", ctypes.c_int32), ("nr_batch", ctypes.c_int32),
         ("weighting", ctypes.c_int32), ("chunk", ctypes.c_int32),
-        ("keep_z", ctypes.c_int32), ("keep_x", ctypes.c_int32),
+        ("keep_z", ctypes.c_int32), ("keep_x", ctypes.c_int32), ("windows", ctypes.c_int32),
     ]
 
 
@@ -150,7 +150,7 @@ def _require(t: torch.Tensor, dtype, shape, name: str, device: torch.device):
 
 
 def make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision, max_ns,
-              nr_batch, weighting="long_record", chunk=0, keep=(0, 0)):
+              nr_batch, weighting="long_record", chunk=0, keep=(0, 0), windows=1):
     riz = np.ascontiguousarray(rec_iz, dtype=np.int32)
     rix = np.ascontiguousarray(rec_ix, dtype=np.int32)
     fr = np.ascontiguousarray(freqs_hz, dtype=np.float64)
@@ -163,7 +163,7 @@ def make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision
                    nf=len(fr), freq_hz=fr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                    precision=prec, max_ns=max_ns, nr_batch=nr_batch,
                    weighting=_WEIGHT[weighting] if isinstance(weighting, str) else int(weighting),
-                   chunk=int(chunk), keep_z=int(keep[0]), keep_x=int(keep[1]))
+                   chunk=int(chunk), keep_z=int(keep[0]), keep_x=int(keep[1]), windows=int(windows))
     return d, (riz, rix, fr)   # keep the arrays alive with the descriptor
 
 
@@ -181,7 +181,7 @@ class Survey:
     def __init__(self, *, nz: int, nx: int, nb: int, h: float, dt: float, nt: int, stride: int,
                  rec_iz: Sequence[int], rec_ix: Sequence[int], freqs_hz: Sequence[float],
                  precision="split_bf16", max_ns: int = 256, nr_batch: int = 0,
-                 weighting="long_record", chunk: int = 0, keep=(0, 0), device=None,
+                 weighting="long_record", chunk: int = 0, keep=(0, 0), windows: int = 1, device=None,
                  stream: Optional[torch.cuda.Stream] = None):
         self._h = None
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
@@ -193,7 +193,7 @@ class Survey:
         self.max_ns = max_ns
         self.nr_batch = nr_batch
         d, keep = make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision,
-                            max_ns, nr_batch, weighting, chunk, keep)
+                            max_ns, nr_batch, weighting, chunk, keep, windows)
         self.weighting = weighting
         L = lib()
         nbytes = L.ehi_workspace_bytes(ctypes.byref(d))

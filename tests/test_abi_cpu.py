@@ -123,3 +123,11 @@ def test_modelling_calls_validate_on_the_host(ehi):
     assert L.ehi_misfit(None, None, None, -1, 1, None, None, None) == ehi.EHI_EINVAL
     assert L.ehi_misfit(None, None, None, 1, 0, None, None, None) == ehi.EHI_EINVAL
     assert L.ehi_misfit(None, None, None, 2, 10, None, None, None) == ehi.EHI_EINVAL
+
+
+def test_two_staging_windows_double_the_staging(ehi):
+    one = ehi.workspace_bytes(**_desc_kw(windows=1))
+    two = ehi.workspace_bytes(**_desc_kw(windows=2))
+    assert two > one
+    with pytest.raises(ehi.EhiError):
+        ehi.workspace_bytes(**_desc_kw(windows=3))

@@ -129,6 +129,37 @@ def test_green_dft_512_sample_window(ehi, tiny_ref):
     assert max(errs) < 5e-6
 
 
+@pytest.mark.parametrize("chunk,nr_batch", [(256, 0), (256, 2), (512, 3)])
+def test_two_staging_windows_bitwise_identical(ehi, chunk, nr_batch):
+    # the DFT of each window on the second stream, overlapped with the steps of
+    # the next: same kernels, same order of accumulation, so the same bits;
+    # nt = 1157 leaves a partial last window, receiver batches restart the
+    # windows
+    s = synth.ragged(nt=1157)
+    v = s.velocity()
+    out = []
+    for windows in (1, 2):
+        sv = ehi.survey_from(s, chunk=chunk, nr_batch=nr_batch, windows=windows)
+        sv.build_green(dev(v))
+        sv.build_green(dev(v))       # a second build on the same handle
+        out.append(sv.copy_green_dft().cpu().numpy())
+        sv.close()
+    np.testing.assert_array_equal(out[1], out[0])
+
+
+def test_two_staging_windows_finite_record_identical(ehi):
+    s = synth.ragged(nt=700)
+    v = s.velocity()
+    out = []
+    for windows in (1, 2):
+        sv = ehi.survey_from(s, chunk=256, weighting="finite_record", windows=windows)
+        sv.build_green(dev(v))
+        sv.build_hessian()
+        out.append(sv.copy_hessian().cpu().numpy())
+        sv.close()
+    np.testing.assert_array_equal(out[1], out[0])
+
+
 def test_green_single_step_and_chunk_edges(ehi):
     # nt = 1 (only the impulse sample), nt = 64 and 65 (DFT chunk edge)
     base = synth.ragged(nt=1)
