@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--build-slots", type=int, default=2, help="serve: concurrent builds")
     ap.add_argument("--nr-batch", type=int, default=0)
     ap.add_argument("--acc-ns", type=int, default=16, help="accuracy: sources per step")
+    ap.add_argument("--cg-iters", type=int, default=60, help="accuracy: cap on the CG baseline's iterations")
     ap.add_argument("--chunk", type=int, default=512, choices=[256, 512],
                     help="time samples per DFT staging window")
     ap.add_argument("--windows", type=int, default=1, choices=[1, 2],
@@ -268,9 +269,22 @@ def run_accuracy(args):
     v0 = synth.smoothed(v_true, 10)
     sv = ehi.survey_from(s, precision=args.precision, max_ns=ns)
     t0 = time.perf_counter()
-    sv.build_green(torch.from_numpy(v0).to(dev))
+    vel0 = torch.from_numpy(v0).to(dev)
+    sv.build_green(vel0)
     sv.build_hessian()
-    sv.factor(1e-3 * sv.lambda_max())
+    mu = 1e-3 * sv.lambda_max()
+    sv.factor(mu)
+    torch.cuda.synchronize()
+    # the direct method's set-up as timed (Nr PDE solves + contraction + factor)
+    e_direct = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    stream0 = torch.cuda.current_stream()
+    e_direct[0].record(stream0)
+    sv.build_green(vel0)
+    sv.build_hessian()
+    sv.factor(mu)
+    e_direct[1].record(stream0)
+    e_direct[1].synchronize()
+    direct_setup_ms = e_direct[0].elapsed_time(e_direct[1])
     # observed data from the true model, predicted data from the starting model:
     # Ricker sources (8 Hz) at depth 20 m, spread across x, on the subgrid
     src = torch.zeros((ns, s.nt, s.nzs, s.nxs), dtype=torch.float32, device=dev)
@@ -310,6 +324,20 @@ def run_accuracy(args):
     K = args.steps
     tot = sum(acc) / K
     relerr = rel.cpu().tolist()
+    # the Krylov baseline: CG on the time-domain system with two PDE solves per
+    # iteration, stopped once every source's fit reaches the direct method's
+    # (the paper's rule) or after args.cg_iters iterations
+    from paper_2512_16642_amd import krylov
+    obs2 = (d_obs.double() ** 2).sum(dim=(1, 2)).cpu()
+    e_cg = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e_cg[0].record(stream)
+    cgr = krylov.cg(sv, dd, mu, args.cg_iters, target=torch.tensor(relerr, dtype=torch.float64),
+                    obs_norm2=obs2)
+    e_cg[1].record(stream)
+    e_cg[1].synchronize()
+    cg_ms = e_cg[0].elapsed_time(e_cg[1])
+    cg_rel = cgr["relerr_history"][-1].tolist() if cgr["relerr_history"] else []
+    print(f"# accuracy: CG {cgr['iterations']} iterations in {cg_ms / 1e3:.1f} s", file=sys.stderr, flush=True)
     cells = 2.0 * ns * s.nt * (s.nz + 2 * s.nb) * (s.nx + 2 * s.nb)
     pde_ms = (acc[1] + acc[2]) / K
     out = {
@@ -332,6 +360,15 @@ def run_accuracy(args):
         "gcell_updates_per_s": round(cells / (pde_ms / 1e3) / 1e9, 1),
         "relerr": {"min": round(min(relerr), 5), "max": round(max(relerr), 5),
                    "mean": round(sum(relerr) / len(relerr), 5)},
+        "direct_vs_cg": {
+            "direct": {"pde_solves": s.nr, "setup_s": round(direct_setup_ms / 1e3, 3),
+                       "deblur_ms": round(acc[0] / K, 3),
+                       "s_for_these_sources": round((direct_setup_ms + acc[0] / K) / 1e3, 3)},
+            "cg": {"iterations": cgr["iterations"], "pde_solves": cgr["pde_solves"],
+                   "s_for_these_sources": round(cg_ms / 1e3, 3),
+                   "reached_direct_fit": bool(cg_rel) and all(c <= d for c, d in zip(cg_rel, relerr)),
+                   "relerr_max": round(max(cg_rel), 5) if cg_rel else None},
+        },
     }
     sv.close()
     print(json.dumps(out), flush=True)

@@ -302,6 +302,39 @@ ehi_status ehi_multipliers_to_time(ehi_survey* s, const void* mult_dev, int32_t 
 ehi_status ehi_misfit(const float* dd_dev, const float* pred_dev, const float* obs_dev, int32_t ns,
                       int64_t len, float* err_dev, double* relerr_dev, void* stream);
 
+/* ---- The Krylov baseline: conjugate gradients on Q x = dd ------------------
+ *
+ * The paper's comparison method (Introduction; Hessian accuracy test; Table of
+ * PDE solves and CPU times): CG on the time-domain system Q x = dd with
+ * Q = S S^T + mu I applied through one ehi_backpropagate and one
+ * ehi_forward_subgrid per iteration (two PDE solves per source).  These four
+ * calls are the vector arithmetic of one batched CG, ns independent records of
+ * len float32 values each (device arrays [ns][len]); the per-record scalars
+ * rr, pAp, rr_new, fit are device double [ns].  Each call is one launch, one
+ * workgroup per record, FP64 sums in a fixed order; enqueued on stream (NULL =
+ * the default stream).  EHI_EINVAL for ns < 0, len < 1 or a NULL pointer.
+ * An iteration:  Ap = S (S^T p);  ehi_cg_shift_dot;  ehi_cg_update;
+ *                ehi_cg_direction;  rr <- rr_new.  */
+
+/* x = 0, r = p = dd, rr = r.r */
+ehi_status ehi_cg_init(const float* dd_dev, int32_t ns, int64_t len, float* x_dev, float* r_dev,
+                       float* p_dev, double* rr_dev, void* stream);
+
+/* Ap += mu p (Ap holds S S^T p on entry), pAp = p.Ap */
+ehi_status ehi_cg_shift_dot(float* ap_dev, const float* p_dev, double mu, int32_t ns, int64_t len,
+                            double* pap_dev, void* stream);
+
+/* alpha = rr / pAp (0 if pAp <= 0); x += alpha p; r -= alpha Ap;
+ * rr_new = r.r; fit = |r + mu x|^2, which equals |dd - S S^T x|^2, the
+ * accuracy test's misfit of the current iterate. */
+ehi_status ehi_cg_update(float* x_dev, float* r_dev, const float* p_dev, const float* ap_dev,
+                         const double* rr_dev, const double* pap_dev, double mu, int32_t ns, int64_t len,
+                         double* rr_new_dev, double* fit_dev, void* stream);
+
+/* p = r + (rr_new / rr) p (beta 0 if rr <= 0) */
+ehi_status ehi_cg_direction(float* p_dev, const float* r_dev, const double* rr_new_dev, const double* rr_dev,
+                            int32_t ns, int64_t len, void* stream);
+
 /* Event-based timing of the kernels a survey launches.  Kinds: */
 enum {
   EHI_PROF_SETUP = 0,   /* medium, twiddle and wavefield set-up */

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <new>
 #include <string>
 #include <vector>
@@ -915,6 +916,63 @@ ehi_status ehi_misfit(const float* dd_dev, const float* pred_dev, const float* o
   EHI_TRY(ehi::launch_misfit(dd_dev, pred_dev, obs_dev, ns, (size_t)len, err_dev, relerr_dev,
                              static_cast<hipStream_t>(stream)),
           "misfit");
+  return EHI_OK;
+}
+
+namespace {
+
+ehi_status cg_check(int32_t ns, int64_t len, std::initializer_list<const void*> ptrs) {
+  if (ns < 0 || len < 1) return fail(EHI_EINVAL, "need ns >= 0 and len >= 1");
+  if (ns > 0)
+    for (const void* q : ptrs)
+      if (!q) return fail(EHI_EINVAL, "NULL argument");
+  return EHI_OK;
+}
+
+}  // namespace
+
+ehi_status ehi_cg_init(const float* dd_dev, int32_t ns, int64_t len, float* x_dev, float* r_dev,
+                       float* p_dev, double* rr_dev, void* stream) {
+  g_err.clear();
+  ehi_status c = cg_check(ns, len, {dd_dev, x_dev, r_dev, p_dev, rr_dev});
+  if (c != EHI_OK || ns == 0) return c;
+  EHI_TRY(ehi::launch_cg_init(dd_dev, x_dev, r_dev, p_dev, ns, (size_t)len, rr_dev,
+                              static_cast<hipStream_t>(stream)),
+          "cg init");
+  return EHI_OK;
+}
+
+ehi_status ehi_cg_shift_dot(float* ap_dev, const float* p_dev, double mu, int32_t ns, int64_t len,
+                            double* pap_dev, void* stream) {
+  g_err.clear();
+  ehi_status c = cg_check(ns, len, {ap_dev, p_dev, pap_dev});
+  if (c != EHI_OK || ns == 0) return c;
+  EHI_TRY(ehi::launch_cg_shift_dot(ap_dev, p_dev, (float)mu, ns, (size_t)len, pap_dev,
+                                   static_cast<hipStream_t>(stream)),
+          "cg shift");
+  return EHI_OK;
+}
+
+ehi_status ehi_cg_update(float* x_dev, float* r_dev, const float* p_dev, const float* ap_dev,
+                         const double* rr_dev, const double* pap_dev, double mu, int32_t ns, int64_t len,
+                         double* rr_new_dev, double* fit_dev, void* stream) {
+  g_err.clear();
+  ehi_status c = cg_check(ns, len, {x_dev, r_dev, p_dev, ap_dev, rr_dev, pap_dev, rr_new_dev, fit_dev});
+  if (c != EHI_OK || ns == 0) return c;
+  EHI_TRY(ehi::launch_cg_update(x_dev, r_dev, p_dev, ap_dev, rr_dev, pap_dev, (float)mu, ns, (size_t)len,
+                                rr_new_dev, fit_dev, static_cast<hipStream_t>(stream)),
+          "cg update");
+  return EHI_OK;
+}
+
+ehi_status ehi_cg_direction(float* p_dev, const float* r_dev, const double* rr_new_dev, const double* rr_dev,
+                            int32_t ns, int64_t len, void* stream) {
+  g_err.clear();
+  ehi_status c = cg_check(ns, len, {p_dev, r_dev, rr_new_dev, rr_dev});
+  if (c != EHI_OK || ns == 0) return c;
+  EHI_TRY(ehi::launch_cg_direction(p_dev, r_dev, rr_new_dev, rr_dev, ns, (size_t)len,
+                                   static_cast<hipStream_t>(stream)),
+          "cg direction");
   return EHI_OK;
 }
 

@@ -214,6 +214,15 @@ hipError_t launch_to_time(const Geometry& g, const float2* X, int nq, const floa
                           unsigned long long edge_bins, float* x, hipStream_t st);
 hipError_t launch_misfit(const float* dd, const float* pred, const float* obs, int ns, size_t len,
                          float* err, double* relerr, hipStream_t st);
+hipError_t launch_cg_init(const float* dd, float* x, float* r, float* p, int ns, size_t len, double* rr,
+                          hipStream_t st);
+hipError_t launch_cg_shift_dot(float* Ap, const float* p, float mu, int ns, size_t len, double* pAp,
+                               hipStream_t st);
+hipError_t launch_cg_update(float* x, float* r, const float* p, const float* Ap, const double* rr,
+                            const double* pAp, float mu, int ns, size_t len, double* rr_new, double* fit,
+                            hipStream_t st);
+hipError_t launch_cg_direction(float* p, const float* r, const double* rr_new, const double* rr, int ns,
+                               size_t len, hipStream_t st);
 hipError_t launch_c64_from_c128(const double2* in, float2* out, size_t n, hipStream_t st);
 
 }  // namespace ehi

@@ -220,7 +220,123 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0) relerr[blockIdx.x] = se[0] / so[0];
 }
 
+// ---- conjugate gradients on Q x = dd, Q = S S^T + mu I (the Krylov baseline) --
+// Vectors are float32 records [ns][len]; scalars per record are FP64 device
+// arrays.  One workgroup per record, a fixed reduction order (deterministic).
+constexpr int kCgThreads = 1024;
+
+__device__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = kCgThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double out = red[0];
+  __syncthreads();
+  return out;
+}
+
+// x = 0, r = p = dd, rr = r.r
+__global__ void __launch_bounds__(kCgThreads)
+    k_cg_init(const float* __restrict__ dd, float* __restrict__ x, float* __restrict__ r,
+              float* __restrict__ p, size_t len, double* __restrict__ rr) {
+  __shared__ double red[kCgThreads];
+  const size_t base = (size_t)blockIdx.x * len;
+  double acc = 0.0;
+  for (size_t i = threadIdx.x; i < len; i += kCgThreads) {
+    const float v = dd[base + i];
+    x[base + i] = 0.f;
+    r[base + i] = v;
+    p[base + i] = v;
+    acc += (double)v * (double)v;
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) rr[blockIdx.x] = t;
+}
+
+// Ap += mu p (Ap holds S S^T p on entry), pAp = p.Ap
+__global__ void __launch_bounds__(kCgThreads)
+    k_cg_shift_dot(float* __restrict__ Ap, const float* __restrict__ p, float mu, size_t len,
+                   double* __restrict__ pAp) {
+  __shared__ double red[kCgThreads];
+  const size_t base = (size_t)blockIdx.x * len;
+  double acc = 0.0;
+  for (size_t i = threadIdx.x; i < len; i += kCgThreads) {
+    const float pv = p[base + i];
+    const float a = fmaf(mu, pv, Ap[base + i]);
+    Ap[base + i] = a;
+    acc += (double)pv * (double)a;
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) pAp[blockIdx.x] = t;
+}
+
+// alpha = rr / pAp; x += alpha p; r -= alpha Ap; rr_new = r.r; fit = |r + mu x|^2
+// (dd - S S^T x = r + mu x: the accuracy test's misfit of the current iterate)
+__global__ void __launch_bounds__(kCgThreads)
+    k_cg_update(float* __restrict__ x, float* __restrict__ r, const float* __restrict__ p,
+                const float* __restrict__ Ap, const double* __restrict__ rr, const double* __restrict__ pAp,
+                float mu, size_t len, double* __restrict__ rr_new, double* __restrict__ fit) {
+  __shared__ double red[kCgThreads];
+  const size_t base = (size_t)blockIdx.x * len;
+  const double den = pAp[blockIdx.x];
+  const float alpha = den > 0.0 ? (float)(rr[blockIdx.x] / den) : 0.f;
+  double a2 = 0.0, f2 = 0.0;
+  for (size_t i = threadIdx.x; i < len; i += kCgThreads) {
+    const float xv = fmaf(alpha, p[base + i], x[base + i]);
+    const float rv = fmaf(-alpha, Ap[base + i], r[base + i]);
+    x[base + i] = xv;
+    r[base + i] = rv;
+    a2 += (double)rv * (double)rv;
+    const double e = (double)rv + (double)mu * (double)xv;
+    f2 += e * e;
+  }
+  const double t1 = block_sum(a2, red);
+  const double t2 = block_sum(f2, red);
+  if (threadIdx.x == 0) {
+    rr_new[blockIdx.x] = t1;
+    fit[blockIdx.x] = t2;
+  }
+}
+
+// p = r + (rr_new / rr) p
+__global__ void __launch_bounds__(kCgThreads)
+    k_cg_direction(float* __restrict__ p, const float* __restrict__ r, const double* __restrict__ rr_new,
+                   const double* __restrict__ rr, size_t len) {
+  const size_t base = (size_t)blockIdx.x * len;
+  const double den = rr[blockIdx.x];
+  const float beta = den > 0.0 ? (float)(rr_new[blockIdx.x] / den) : 0.f;
+  for (size_t i = threadIdx.x; i < len; i += kCgThreads) p[base + i] = fmaf(beta, p[base + i], r[base + i]);
+}
+
 }  // namespace
+
+hipError_t launch_cg_init(const float* dd, float* x, float* r, float* p, int ns, size_t len, double* rr,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_init, dim3(ns), dim3(kCgThreads), 0, st, dd, x, r, p, len, rr);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_shift_dot(float* Ap, const float* p, float mu, int ns, size_t len, double* pAp,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_shift_dot, dim3(ns), dim3(kCgThreads), 0, st, Ap, p, mu, len, pAp);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(float* x, float* r, const float* p, const float* Ap, const double* rr,
+                            const double* pAp, float mu, int ns, size_t len, double* rr_new, double* fit,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_update, dim3(ns), dim3(kCgThreads), 0, st, x, r, p, Ap, rr, pAp, mu, len, rr_new,
+                     fit);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_direction(float* p, const float* r, const double* rr_new, const double* rr, int ns,
+                               size_t len, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_direction, dim3(ns), dim3(kCgThreads), 0, st, p, r, rr_new, rr, len);
+  return hipGetLastError();
+}
 
 hipError_t launch_fd_step(const Geometry& g, const float* ca, const float* bd, const float* uin,
                           float* uout, float* w, int nb_now, const float* src, size_t src_field,

@@ -35,7 +35,8 @@ SYMBOLS = (
     "ehi_version", "ehi_profile_enable", "ehi_profile_read", "ehi_batch_workspace_bytes",
     "ehi_factor_batch", "ehi_set_stream", "ehi_set_launch", "ehi_get_launch",
     "ehi_set_medium", "ehi_forward_subgrid", "ehi_backpropagate", "ehi_residual_spectra",
-    "ehi_multipliers_to_time", "ehi_misfit",
+    "ehi_multipliers_to_time", "ehi_misfit", "ehi_cg_init", "ehi_cg_shift_dot", "ehi_cg_update",
+    "ehi_cg_direction",
 )
 PROF_KINDS = ("setup", "step", "dft", "herk", "factor", "solve", "model")
 _PROF_N = 8
@@ -116,6 +117,13 @@ def lib() -> ctypes.CDLL:
         getattr(L, name).restype = st
     L.ehi_misfit.argtypes = [vp, vp, vp, i32, ctypes.c_int64, vp, vp, vp]
     L.ehi_misfit.restype = st
+    i64, dbl = ctypes.c_int64, ctypes.c_double
+    L.ehi_cg_init.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp]
+    L.ehi_cg_shift_dot.argtypes = [vp, vp, dbl, i32, i64, vp, vp]
+    L.ehi_cg_update.argtypes = [vp, vp, vp, vp, vp, vp, dbl, i32, i64, vp, vp, vp]
+    L.ehi_cg_direction.argtypes = [vp, vp, vp, vp, i32, i64, vp]
+    for name in ("ehi_cg_init", "ehi_cg_shift_dot", "ehi_cg_update", "ehi_cg_direction"):
+        getattr(L, name).restype = st
     L.ehi_destroy.argtypes = [vp]
     L.ehi_destroy.restype = st
     L.ehi_last_error.argtypes = []

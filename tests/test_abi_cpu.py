@@ -131,3 +131,13 @@ def test_two_staging_windows_double_the_staging(ehi):
     assert two > one
     with pytest.raises(ehi.EhiError):
         ehi.workspace_bytes(**_desc_kw(windows=3))
+
+
+def test_cg_calls_validate_on_the_host(ehi):
+    L = ehi.lib()
+    d = ctypes.c_double(1.0)
+    assert L.ehi_cg_init(None, 0, 1, None, None, None, None, None) == ehi.EHI_OK
+    assert L.ehi_cg_init(None, 1, 1, None, None, None, None, None) == ehi.EHI_EINVAL
+    assert L.ehi_cg_shift_dot(None, None, d, -1, 1, None, None) == ehi.EHI_EINVAL
+    assert L.ehi_cg_update(None, None, None, None, None, None, d, 1, 0, None, None, None) == ehi.EHI_EINVAL
+    assert L.ehi_cg_direction(None, None, None, None, 2, 5, None) == ehi.EHI_EINVAL
