@@ -198,8 +198,10 @@ template <typename T, int MODE, int EPI, int BT = 0, typename TA = T>
 __global__ void __launch_bounds__(256) k_cgemm(GemmArgs a) {
   typedef typename Cx<T>::t C2;
   typedef typename Cx<TA>::t A2;
-  __shared__ C2 As[kGk][kGm];
-  __shared__ C2 Bs[kGk][kGn];
+  // two LDS stages: stage k + 1 is loaded into registers while stage k is
+  // multiplied, then stored into the other buffer (one barrier per stage)
+  __shared__ C2 As[2][kGk][kGm];
+  __shared__ C2 Bs[2][kGk][kGn];
   const int f = blockIdx.z;
   const int i0 = blockIdx.y * kGm, j0 = blockIdx.x * kGn;
   const int tid = threadIdx.x;
@@ -214,49 +216,69 @@ __global__ void __launch_bounds__(256) k_cgemm(GemmArgs a) {
   int kbeg = 0, kend = a.kdim;
   if (MODE == 1) kend = min(kend, i0 + kGm);             // M(i, k) = 0 for k > i
   if (MODE == 2) kbeg = i0 / kGk * kGk;                  // conj(M(k, i)) = 0 for k < i
-  for (int k0 = kbeg; k0 < kend; k0 += kGk) {
-    __syncthreads();
+  // element q of this thread's share of a stage: (stage row kk, LDS column)
+  // of A and of B; the LDS column keeps the register-tile index outermost
+  auto a_slot = [&](int q, int& kk, int& ii) {
+    const int e = tid + 256 * q;
+    if (MODE == 2) { kk = e / kGm; ii = e % kGm; }      // contiguous along i
+    else { ii = e / kGk; kk = e % kGk; }                // contiguous along k
+  };
+  auto b_slot = [&](int q, int& kk, int& jj) {
+    const int e = tid + 256 * q;
+    if (BT) { kk = e / kGn; jj = e % kGn; }             // contiguous along j
+    else { jj = e / kGk; kk = e % kGk; }                // contiguous along k
+  };
+  C2 ra[4], rb[4];
+  auto gload = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      if (MODE == 2) {
-        const int kk = e / kGm, ii = e % kGm;          // contiguous along i
-        const int gk = k0 + kk, gi = i0 + ii;
-        C2 v = C2{0, 0};
-        if (gk < kend && gi < a.arows) {
+      int kk, ii, jj, kb;
+      a_slot(q, kk, ii);
+      const int gk = k0 + kk, gi = i0 + ii;
+      C2 v = C2{0, 0};
+      if (gk < kend && gi < a.arows) {
+        if (MODE == 2) {
           const C2 m = A[(size_t)gk * a.lda + gi];
           v = C2{m.x, -m.y};
+        } else {
+          v = A[(size_t)gi * a.lda + gk];
+          if (MODE == 3) v.y = -v.y;                     // A(i, k) = conj(Am[i * lda + k])
         }
-        As[kk][(ii & 3) * 16 + (ii >> 2)] = v;
-      } else {
-        const int ii = e / kGk, kk = e % kGk;          // contiguous along k
-        const int gk = k0 + kk, gi = i0 + ii;
-        C2 v = (gk < kend && gi < a.arows) ? A[(size_t)gi * a.lda + gk] : C2{0, 0};
-        if (MODE == 3) v.y = -v.y;                     // A(i, k) = conj(Am[i * lda + k])
-        As[kk][(ii & 3) * 16 + (ii >> 2)] = v;
       }
-      if (BT) {
-        const int kk = e / kGn, jj = e % kGn;          // contiguous along j
-        const int gk = k0 + kk, gj = j0 + jj;
-        Bs[kk][(jj & 3) * 16 + (jj >> 2)] = (gk < kend && gj < a.ns) ? B[(size_t)gk * a.ldb + gj] : C2{0, 0};
-      } else {
-        const int jj = e / kGk, kk = e % kGk;          // contiguous along k
-        const int gk = k0 + kk, gj = j0 + jj;
-        Bs[kk][(jj & 3) * 16 + (jj >> 2)] = (gk < kend && gj < a.ns) ? B[(size_t)gj * a.ldb + gk] : C2{0, 0};
-      }
+      ra[q] = v;
+      b_slot(q, kb, jj);
+      const int hk = k0 + kb, gj = j0 + jj;
+      rb[q] = (hk < kend && gj < a.ns) ? (BT ? B[(size_t)hk * a.ldb + gj] : B[(size_t)gj * a.ldb + hk])
+                                       : C2{0, 0};
     }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int kk, ii, jj, kb;
+      a_slot(q, kk, ii);
+      As[buf][kk][(ii & 3) * 16 + (ii >> 2)] = ra[q];
+      b_slot(q, kb, jj);
+      Bs[buf][kb][(jj & 3) * 16 + (jj >> 2)] = rb[q];
+    }
+  };
+  if (kbeg < kend) gload(kbeg);
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += kGk, buf ^= 1) {
+    sstore(buf);
     __syncthreads();
+    if (k0 + kGk < kend) gload(k0 + kGk);
 #pragma unroll 4
     for (int kk = 0; kk < kGk; ++kk) {
       A2 av[4], bv[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const C2 v = As[kk][r * 16 + ty];
+        const C2 v = As[buf][kk][r * 16 + ty];
         av[r] = A2{(TA)v.x, (TA)v.y};
       }
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const C2 v = Bs[kk][c * 16 + tx];
+        const C2 v = Bs[buf][kk][c * 16 + tx];
         bv[c] = A2{(TA)v.x, (TA)v.y};
       }
 #pragma unroll
