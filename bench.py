@@ -484,6 +484,11 @@ def main():
     rep = s.nt if args.weighting == "finite_record" else 1
     herk_flops = costs.herk_flops_per_survey(s.nz, s.nx, s.stride, s.nr, s.nf) * rep
     herk_ms = prof["herk"][0] / K
+    # 32 x 32 block pairs in the whole-matrix contraction (up to 224 receivers,
+    # final-spectrum form), 64 x 64 tile pairs otherwise
+    whole = (args.precision == "split_bf16" and args.weighting == "long_record" and s.nr <= 224
+             and os.environ.get("EHI_HERK_WHOLE", "1") != "0")
+    herk_tile = 32 if whole else 64
     out = {
         "metric": METRIC,
         "value": round(survey_s, 6),
@@ -508,7 +513,7 @@ def main():
         "kernel_ms": {k: round(v[0] / K, 3) for k, v in prof.items()},
         "gcell_updates_per_s": round(cell_updates / (prof["step"][0] / K / 1e3) / 1e9, 2),
         "herk_tflops": round(herk_flops / (herk_ms / 1e3) / 1e12, 2) if herk_ms > 0 else None,
-        "herk_mfma_bf16_tflops": (round(costs.herk_bf16_mfma_flops_per_survey(s.nr, s.nsub, s.nf) * rep
+        "herk_mfma_bf16_tflops": (round(costs.herk_bf16_mfma_flops_per_survey(s.nr, s.nsub, s.nf, herk_tile) * rep
                                         / (herk_ms / 1e3) / 1e12, 1)
                                   if herk_ms > 0 and args.precision == "split_bf16" else None),
         "dft_gbs": round(dft_bytes / (dft_ms / 1e3) / 1e9, 1) if dft_ms > 0 else None,

@@ -57,8 +57,9 @@ def herk_flops_per_survey(nz, nx, stride, nr, nf):
 
 def herk_bf16_mfma_flops_per_survey(nr, nsub, nf, tile=64):
     """BF16 MFMA flops the split contraction executes: 16 real products of
-    K = nsub (hi/lo x hi/lo for Re and Im) on every 64 x 64 tile on or above the
-    block diagonal."""
+    K = nsub (hi/lo x hi/lo for Re and Im) on every tile x tile block on or
+    above the block diagonal (64 x 64 tile pairs, or the 32 x 32 block pairs of
+    the whole-matrix form)."""
     nb = -(-nr // tile)
     pairs = nb * (nb + 1) // 2
     return 2.0 * 16 * pairs * tile * tile * nsub * nf

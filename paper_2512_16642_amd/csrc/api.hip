@@ -118,6 +118,11 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   int ntile = ehi::cdiv(g.nr, g.split_bf16 ? 64 : ehi::kHerkTile);
   int pairs = ntile * (ntile + 1) / 2;
   int want = ehi::cdiv(2048, pairs * g.nf);
+  // the final-spectrum split-BF16 contraction of up to 224 receivers runs one
+  // workgroup per CU per (frequency, partition, pair group): partitions for
+  // about four full rounds of workgroups (a partial last round costs a round)
+  g.herk_whole = (g.split_bf16 && g.weighting == EHI_WEIGHT_LONG_RECORD && g.nr <= 224) ? 1 : 0;
+  if (g.herk_whole) want = std::max(1, 1024 / (g.nf * ehi::herk_whole_groups(g.nr)));
   int kmax = std::max(1, g.nsub / 1024);
   g.herk_split = std::max(1, std::min(want, std::min(ehi::kHerkSplitMax, kmax)));
   g.tblock = 8;
@@ -126,6 +131,12 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   if (const char* e = std::getenv("EHI_TBLOCK")) {
     int v = std::atoi(e);
     if (v == 4 || v == 8) g.tblock = v;
+  }
+  if (const char* e = std::getenv("EHI_HERK_WHOLE")) {
+    if (std::atoi(e) == 0 && g.herk_whole) {
+      g.herk_whole = 0;
+      g.herk_split = std::max(1, std::min(ehi::cdiv(2048, pairs * g.nf), std::min(ehi::kHerkSplitMax, kmax)));
+    }
   }
   if (const char* e = std::getenv("EHI_HERK_SPLIT")) {
     int v = std::atoi(e);

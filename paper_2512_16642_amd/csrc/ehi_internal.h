@@ -34,6 +34,7 @@ struct Geometry {
   int windows;     // staging windows: 1, or 2 (the DFT of one overlaps the stepping of the next)
   int nt, nr, nf, nrb, max_ns;
   int herk_split;  // split-K partitions
+  int herk_whole;  // 1: one workgroup per (frequency, partition) forms all of Hhat (nr <= 224)
   int split_bf16;  // 1: split-BF16 contraction, 0: plain FP32
   int weighting;   // EHI_WEIGHT_LONG_RECORD or EHI_WEIGHT_FINITE_RECORD
   int keep_z, keep_x;  // leading DCT-II coefficients kept along z and x of the subgrid (0 = no transform)
@@ -186,6 +187,7 @@ hipError_t launch_dct_compress(const Geometry& g, const float2* ghat, const floa
                                float2* tmp, float2* gcomp, hipStream_t st);
 hipError_t launch_herk_reduce(const Geometry& g, const float2* hpart, double2* hhat,
                               hipStream_t st);
+int herk_whole_groups(int nr);  // workgroups per (frequency, partition) of the whole-matrix contraction
 hipError_t launch_herk_compressed(const Geometry& g, const float2* gcomp, int K, double2* hhat,
                                   hipStream_t st);
 hipError_t launch_factor_jobs(const FactorJob* jobs, int njobs, hipStream_t st);

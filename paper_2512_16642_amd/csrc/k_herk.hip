@@ -273,6 +273,182 @@ __global__ void __launch_bounds__(256)
       }
 }
 
+// The same contraction for surveys of at most 224 receivers, without tile
+// pairs: the 32 x 32 block pairs (bi <= bj) of the 32-row blocks, in row-major
+// order of the upper triangle, form groups of 16, and one workgroup per
+// (frequency, grid-point partition, group) stages every row once per 32-point
+// stage (loaded from HBM, split into hi/lo planes, stored in LDS) and computes
+// its group's pairs, pair 16 group + w + 8 m on wave w (m < 2: waves w and
+// w + 4 share a SIMD, so a partial group still spreads evenly).  Per pair the
+// same 2 x 2 MFMA tiles and 16 products per tile as above, 32-point chains from
+// zero; stages are double-buffered.  At 200 receivers (28 pairs, 2 groups) the
+// spectra are read twice instead of about three times, and split once per
+// group instead of once per tile pair.  Output: the upper-triangle blocks of
+// hpart (the reduction reads j >= i only).
+constexpr int kWholeRows = 224;   // rows held in LDS
+constexpr int kWholeWaves = 8;
+constexpr int kWholePairs = 2;    // block pairs per wave
+constexpr int kWholeGroup = kWholeWaves * kWholePairs;
+
+template <bool VEC>
+__global__ void __launch_bounds__(512)
+    k_herk_bf16_whole(Geometry g, const float2* __restrict__ ghat, float2* __restrict__ hpart, int split) {
+  __shared__ u32x4 pl[2][4][kBk / 8][kWholeRows];  // [buffer][plane][group of 8 points][row]
+  const int nb = cdiv(g.nr, 32);
+  const int rows = nb * 32;  // rows staged (>= nr, zero beyond)
+  const int npair = nb * (nb + 1) / 2;
+  const int ngroup = cdiv(npair, kWholeGroup);
+  const int grp_id = blockIdx.x % ngroup;
+  const int ks = (blockIdx.x / ngroup) % split;
+  const int f = blockIdx.x / (ngroup * split);
+  const int kchunk = cdiv(cdiv(g.nsub, split), kBk) * kBk;
+  const int k0 = ks * kchunk;
+  const int k1 = min(g.nsub, k0 + kchunk);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const float2* G = ghat + (size_t)f * g.nr * g.nsub;
+
+  // this wave's block pairs: p = 16 group + wave + 8 m, row-major in the upper triangle
+  int pbi[kWholePairs], pbj[kWholePairs];
+  const int pfirst = grp_id * kWholeGroup + wave;
+  const int mine = npair > pfirst ? min(kWholePairs, (npair - pfirst + kWholeWaves - 1) / kWholeWaves) : 0;
+#pragma unroll
+  for (int m = 0; m < kWholePairs; ++m) {
+    int p = pfirst + kWholeWaves * m, i = 0;
+    if (p >= npair) p = 0;
+    while (p >= nb - i) {
+      p -= nb - i;
+      ++i;
+    }
+    pbi[m] = i;
+    pbj[m] = i + p;
+  }
+  floatx4 re[kWholePairs][2][2], im[kWholePairs][2][2];
+#pragma unroll
+  for (int m = 0; m < kWholePairs; ++m)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) re[m][a][b] = im[m][a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  // load tasks: (row, point group) = (task % rows, task / rows), task = tid, tid + 512
+  float2 v[2][8];
+  auto gload = [&](int kb) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int task = tid + 512 * p;
+      const int row = task % rows, grp = task / rows;
+      const bool ok = task < 4 * rows && row < g.nr;
+      const int k = kb + 8 * grp;
+      const float2* src = G + (size_t)(ok ? row : 0) * g.nsub;
+      if (VEC && ok && k + 8 <= k1) {
+        const floatx4* q4 = reinterpret_cast<const floatx4*>(src + k);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const floatx4 q = q4[e];
+          v[p][2 * e] = make_float2(q[0], q[1]);
+          v[p][2 * e + 1] = make_float2(q[2], q[3]);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[p][e] = (ok && k + e < k1) ? src[k + e] : make_float2(0.f, 0.f);
+      }
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int task = tid + 512 * p;
+      if (task >= 4 * rows) continue;
+      const int row = task % rows, grp = task / rows;
+      unsigned w[4][4];
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        const float2 z0 = v[p][e], z1 = v[p][e + 1];
+        const bf16x2 rh = {(__bf16)z0.x, (__bf16)z1.x};
+        const bf16x2 ih = {(__bf16)z0.y, (__bf16)z1.y};
+        const bf16x2 rl = {(__bf16)(z0.x - (float)rh[0]), (__bf16)(z1.x - (float)rh[1])};
+        const bf16x2 il = {(__bf16)(z0.y - (float)ih[0]), (__bf16)(z1.y - (float)ih[1])};
+        w[0][e >> 1] = __builtin_bit_cast(unsigned, rh);
+        w[1][e >> 1] = __builtin_bit_cast(unsigned, rl);
+        w[2][e >> 1] = __builtin_bit_cast(unsigned, ih);
+        w[3][e >> 1] = __builtin_bit_cast(unsigned, il);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) pl[buf][q][grp][row] = u32x4{w[q][0], w[q][1], w[q][2], w[q][3]};
+    }
+  };
+
+  const int nst = cdiv(k1 - k0, kBk);
+  if (nst > 0) {
+    gload(k0);
+    lstore(0);
+  }
+  __syncthreads();
+  const int fr = lane & 15, fg = lane >> 4;
+  const u32x4 sgn = u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nst) gload(k0 + (st + 1) * kBk);
+    bf16x8 ai[2][4], aj[2][4];
+#pragma unroll
+    for (int m = 0; m < kWholePairs; ++m) {
+      if (m >= mine) break;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          ai[a][q] = __builtin_bit_cast(bf16x8, pl[buf][q][fg][pbi[m] * 32 + a * 16 + fr]);
+          aj[a][q] = __builtin_bit_cast(bf16x8, pl[buf][q][fg][pbj[m] * 32 + a * 16 + fr]);
+        }
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const bf16x8 nrh = __builtin_bit_cast(bf16x8, __builtin_bit_cast(u32x4, ai[a][0]) ^ sgn);
+        const bf16x8 nrl = __builtin_bit_cast(bf16x8, __builtin_bit_cast(u32x4, ai[a][1]) ^ sgn);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          floatx4 r = floatx4{0.f, 0.f, 0.f, 0.f}, mm = floatx4{0.f, 0.f, 0.f, 0.f};
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][0], aj[b][0], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][0], aj[b][1], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][1], aj[b][0], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][1], aj[b][1], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][2], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][3], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][2], r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][3], r, 0, 0, 0);
+          mm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][0], mm, 0, 0, 0);
+          mm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][2], aj[b][1], mm, 0, 0, 0);
+          mm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][0], mm, 0, 0, 0);
+          mm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a][3], aj[b][1], mm, 0, 0, 0);
+          mm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrh, aj[b][2], mm, 0, 0, 0);
+          mm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrh, aj[b][3], mm, 0, 0, 0);
+          mm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrl, aj[b][2], mm, 0, 0, 0);
+          mm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nrl, aj[b][3], mm, 0, 0, 0);
+          re[m][a][b] += r;
+          im[m][a][b] += mm;
+        }
+      }
+    }
+    if (st + 1 < nst) lstore(buf ^ 1);
+    __syncthreads();
+  }
+  float2* out = hpart + ((size_t)ks * g.nf + f) * g.nr * g.nr;
+#pragma unroll
+  for (int m = 0; m < kWholePairs; ++m) {
+    if (m >= mine) break;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v4 = 0; v4 < 4; ++v4) {
+          const int i = pbi[m] * 32 + a * 16 + 4 * (lane >> 4) + v4;
+          const int j = pbj[m] * 32 + b * 16 + (lane & 15);
+          if (i < g.nr && j < g.nr) out[(size_t)i * g.nr + j] = make_float2(re[m][a][b][v4], im[m][a][b][v4]);
+        }
+  }
+}
+
 // Finite-record weighting (the paper's weighting function W(m, n) =
 // min(Nt - m, Nt - n) in the algorithm for the Fourier block-diagonal Hessian):
 // Hhat_W(w) = (1/Nt) sum_{p=1}^{Nt} Ghat_p(w) Ghat_p(w)^H, Ghat_p the DFT
@@ -518,6 +694,11 @@ hipError_t launch_herk_fp32(const Geometry& g, const float2* ghat, float2* hpart
   return hipGetLastError();
 }
 
+int herk_whole_groups(int nr) {
+  const int nb = cdiv(nr, 32);
+  return cdiv(nb * (nb + 1) / 2, kWholeGroup);
+}
+
 int herk_bf16_blocks(const Geometry& g) {
   const int nb = cdiv(g.nr, kBt);
   return nb * (nb + 1) / 2;
@@ -525,6 +706,15 @@ int herk_bf16_blocks(const Geometry& g) {
 
 hipError_t launch_herk_split_bf16(const Geometry& g, const float2* ghat, float2* hpart,
                                   hipStream_t st) {
+  if (g.herk_whole) {
+    if (g.nr > kWholeRows) return hipErrorInvalidValue;
+    dim3 grid((unsigned)(g.nf * g.herk_split * herk_whole_groups(g.nr)));
+    if (g.nsub % 2 == 0)
+      hipLaunchKernelGGL(k_herk_bf16_whole<true>, grid, dim3(512), 0, st, g, ghat, hpart, g.herk_split);
+    else
+      hipLaunchKernelGGL(k_herk_bf16_whole<false>, grid, dim3(512), 0, st, g, ghat, hpart, g.herk_split);
+    return hipGetLastError();
+  }
   const long long items = (long long)herk_bf16_blocks(g) * g.herk_split * g.nf;
   if (items > 0x7fffffffLL) return hipErrorInvalidValue;
   dim3 grid((unsigned)items);
