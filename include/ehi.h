@@ -191,7 +191,7 @@ ehi_status ehi_factor_batch(ehi_survey* const* surveys, int32_t n, const double*
 ehi_status ehi_set_stream(ehi_survey* s, void* stream);
 
 /* Launch shape of the Green-function stepping: time levels per launch
- * (4 or 8; 0 keeps the current value), rows per marching segment (16..256;
+ * (4 or 8; 0 keeps the current value), rows per marching segment (16..512;
  * 0 keeps), and columns per marching workgroup (256, 384, 448 or 512; 0 picks
  * the width that covers the padded grid with the fewest lanes for the chosen
  * time levels; -1 keeps the current request).  Results do not depend on them

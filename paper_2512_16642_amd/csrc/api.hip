@@ -635,7 +635,7 @@ ehi_status ehi_set_launch(ehi_survey* s, int32_t tblock, int32_t seg_rows, int32
   if (!s) return fail(EHI_EINVAL, "survey is NULL");
   if (tblock != 0 && tblock != 4 && tblock != 8) return fail(EHI_EINVAL, "tblock must be 0, 4 or 8");
   if (seg_rows != 0 && (seg_rows < ehi::kMinSegRows || seg_rows > ehi::kMaxSegRows))
-    return fail(EHI_EINVAL, "seg_rows must be 0 or 16..256");
+    return fail(EHI_EINVAL, "seg_rows must be 0 or 16..512");
   if (band != -1 && band != 0 && band != 256 && band != 384 && band != 448 && band != 512)
     return fail(EHI_EINVAL, "band must be -1, 0, 256, 384, 448 or 512");
   if (tblock) s->g.tblock = tblock;

@@ -145,7 +145,7 @@ namespace ehi {
 // per segment, kRowTabStride row-table entries: entry ti describes padded row
 // z0 - 4T + ti (z0 = first owned row, T = time levels per launch).
 constexpr int kMinSegRows = 16;
-constexpr int kMaxSegRows = 256;
+constexpr int kMaxSegRows = 512;
 constexpr int kRowTabStride = kMaxSegRows + 6 * 8 + 8;
 
 // bz = b / a of the row's distance into the top/bottom layer (1 outside the
