@@ -81,3 +81,36 @@ def test_cg_converges_to_dense_solve(micro_system):
     ref = np.linalg.solve(Q0 + mu * np.eye(Q0.shape[0]), d.reshape(-1)).reshape(d.shape)
     assert solves == 2 * it
     np.testing.assert_allclose(x, ref, rtol=1e-7, atol=1e-8 * np.abs(ref).max())
+
+
+def test_gmres_converges_to_dense_solve(micro_system):
+    s, op, Q0, mu, d = micro_system
+    ref = np.linalg.solve(Q0 + mu * np.eye(Q0.shape[0]), d.reshape(-1)).reshape(d.shape)
+    x, it, solves, hist = krylov.gmres(op, d, mu, m=30, tol=1e-11, maxiter=300)
+    assert solves == 2 * it
+    np.testing.assert_allclose(x, ref, rtol=1e-7, atol=1e-8 * np.abs(ref).max())
+
+
+def test_gmres_minimal_residual_and_exact_in_n_steps(micro_system):
+    # without restarts GMRES minimises |d - Q x| over the Krylov space, so after
+    # k iterations its residual is never above CG's; in n iterations it is exact
+    s, op, Q0, mu, d = micro_system
+    Q = Q0 + mu * np.eye(Q0.shape[0])
+    b = d.reshape(-1)
+    for k in (3, 8, 15):
+        xg, _, _, _ = krylov.gmres(op, d, mu, m=k, tol=0.0, maxiter=k)
+        xc, _, _ = krylov.cg(op, d, mu, tol=0.0, maxiter=k)
+        rg = np.linalg.norm(b - Q @ xg.reshape(-1))
+        rc = np.linalg.norm(b - Q @ xc.reshape(-1))
+        assert rg <= rc * (1 + 1e-9), (k, rg, rc)
+    # the Krylov space of a small system fills up: residual at rounding level
+    small = synth.micro(nz=8, nx=9, nb=2, nt=6, nr=2)
+    v = small.velocity()
+    op2 = fd.ForwardOperator(v, small.nb, small.h, small.dt, small.nt, small.rec_iz, small.rec_ix, 1)
+    gt = fd.green_samples(v, small.nb, small.h, small.dt, small.nt, small.rec_iz, small.rec_ix, 1)
+    Q2 = hessian.time_domain_matrix(gt.reshape(small.nr, small.nt, -1), 0.1)
+    d2 = np.random.default_rng(9).standard_normal((small.nr, small.nt))
+    n = Q2.shape[0]
+    x2, _, _, _ = krylov.gmres(op2, d2, 0.1, m=n, tol=0.0, maxiter=n)
+    np.testing.assert_allclose(Q2 @ x2.reshape(-1), d2.reshape(-1), rtol=1e-8, atol=1e-9 * np.abs(d2).max())
+
