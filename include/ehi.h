@@ -335,6 +335,22 @@ ehi_status ehi_cg_update(float* x_dev, float* r_dev, const float* p_dev, const f
 ehi_status ehi_cg_direction(float* p_dev, const float* r_dev, const double* rr_new_dev, const double* rr_dev,
                             int32_t ns, int64_t len, void* stream);
 
+/* Block operations of a Krylov basis (GMRES, the paper's second iterative
+ * baseline): nvec float32 vectors of ns records of len values, vector j of
+ * record s at v_dev + j * vstride + s * len (vstride >= len elements).  One
+ * launch each, FP64 sums, enqueued on stream (NULL = the default stream).
+ * EHI_EINVAL for negative or oversized counts or a NULL pointer. */
+
+/* out[s][j] = V_j[s] . w[s] for j < nvec (out double [ns][nvec], device);
+ * nvec, ns <= 65535. */
+ehi_status ehi_mdot(const float* v_dev, int64_t vstride, int32_t nvec, const float* w_dev, int32_t ns,
+                    int64_t len, double* out_dev, void* stream);
+
+/* dst[s] = beta dst[s] + sum_j coef[s][j] V_j[s] (coef double [ns][nvec],
+ * device; nvec <= 1024; dst [ns][len] must not overlap the V_j). */
+ehi_status ehi_combine(const float* v_dev, int64_t vstride, int32_t nvec, const double* coef_dev, int32_t ns,
+                       int64_t len, double beta, float* dst_dev, void* stream);
+
 /* Event-based timing of the kernels a survey launches.  Kinds: */
 enum {
   EHI_PROF_SETUP = 0,   /* medium, twiddle and wavefield set-up */

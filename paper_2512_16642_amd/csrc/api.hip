@@ -987,4 +987,30 @@ ehi_status ehi_cg_direction(float* p_dev, const float* r_dev, const double* rr_n
   return EHI_OK;
 }
 
+ehi_status ehi_mdot(const float* v_dev, int64_t vstride, int32_t nvec, const float* w_dev, int32_t ns,
+                    int64_t len, double* out_dev, void* stream) {
+  g_err.clear();
+  if (nvec < 0 || nvec > 65535 || ns > 65535) return fail(EHI_EINVAL, "nvec and ns must be in [0, 65535]");
+  ehi_status c = cg_check(ns, len, {v_dev, w_dev, out_dev});
+  if (c != EHI_OK || ns == 0 || nvec == 0) return c;
+  if (vstride < len) return fail(EHI_EINVAL, "vstride must be >= len");
+  EHI_TRY(ehi::launch_mdot(v_dev, (size_t)vstride, nvec, w_dev, ns, (size_t)len, out_dev,
+                           static_cast<hipStream_t>(stream)),
+          "mdot");
+  return EHI_OK;
+}
+
+ehi_status ehi_combine(const float* v_dev, int64_t vstride, int32_t nvec, const double* coef_dev, int32_t ns,
+                       int64_t len, double beta, float* dst_dev, void* stream) {
+  g_err.clear();
+  if (nvec < 0 || nvec > 1024 || ns > 65535) return fail(EHI_EINVAL, "nvec must be in [0, 1024], ns <= 65535");
+  ehi_status c = cg_check(ns, len, {v_dev, coef_dev, dst_dev});
+  if (c != EHI_OK || ns == 0) return c;
+  if (nvec > 0 && vstride < len) return fail(EHI_EINVAL, "vstride must be >= len");
+  EHI_TRY(ehi::launch_combine(v_dev, (size_t)vstride, nvec, coef_dev, ns, (size_t)len, beta, dst_dev,
+                              static_cast<hipStream_t>(stream)),
+          "combine");
+  return EHI_OK;
+}
+
 }  // extern "C"

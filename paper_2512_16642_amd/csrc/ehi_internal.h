@@ -216,6 +216,10 @@ hipError_t launch_to_time(const Geometry& g, const float2* X, int nq, const floa
                           unsigned long long edge_bins, float* x, hipStream_t st);
 hipError_t launch_misfit(const float* dd, const float* pred, const float* obs, int ns, size_t len,
                          float* err, double* relerr, hipStream_t st);
+hipError_t launch_mdot(const float* v, size_t vstride, int nvec, const float* w, int ns, size_t len,
+                       double* out, hipStream_t st);
+hipError_t launch_combine(const float* v, size_t vstride, int nvec, const double* coef, int ns, size_t len,
+                          double beta, float* dst, hipStream_t st);
 hipError_t launch_cg_init(const float* dd, float* x, float* r, float* p, int ns, size_t len, double* rr,
                           hipStream_t st);
 hipError_t launch_cg_shift_dot(float* Ap, const float* p, float mu, int ns, size_t len, double* pAp,

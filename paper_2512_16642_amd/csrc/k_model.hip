@@ -310,7 +310,59 @@ __global__ void __launch_bounds__(kCgThreads)
   for (size_t i = threadIdx.x; i < len; i += kCgThreads) p[base + i] = fmaf(beta, p[base + i], r[base + i]);
 }
 
+// ---- block dot products and linear combinations (the GMRES basis) ---------
+// Vector j of record s at v + j * vstride + s * len.
+
+// out[s][j] = V_j[s] . w[s] (FP64), one workgroup per (j, s)
+__global__ void __launch_bounds__(256)
+    k_mdot(const float* __restrict__ v, size_t vstride, int nvec, const float* __restrict__ w, size_t len,
+           double* __restrict__ out) {
+  __shared__ double red[256];
+  const int j = blockIdx.x, sidx = blockIdx.y;
+  const float* a = v + (size_t)j * vstride + (size_t)sidx * len;
+  const float* b = w + (size_t)sidx * len;
+  double acc = 0.0;
+  for (size_t i = threadIdx.x; i < len; i += 256) acc += (double)a[i] * (double)b[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[(size_t)sidx * nvec + j] = red[0];
+}
+
+// dst[s][i] = beta dst[s][i] + sum_j coef[s][j] V_j[s][i] (FP64 sum)
+__global__ void __launch_bounds__(256)
+    k_combine(const float* __restrict__ v, size_t vstride, int nvec, const double* __restrict__ coef,
+              size_t len, double beta, float* __restrict__ dst) {
+  __shared__ double c[1024];
+  const int sidx = blockIdx.y;
+  for (int j = threadIdx.x; j < nvec; j += 256) c[j] = coef[(size_t)sidx * nvec + j];
+  __syncthreads();
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= len) return;
+  float* d = dst + (size_t)sidx * len;
+  double acc = beta != 0.0 ? beta * (double)d[i] : 0.0;
+  const float* a = v + (size_t)sidx * len + i;
+  for (int j = 0; j < nvec; ++j) acc += c[j] * (double)a[(size_t)j * vstride];
+  d[i] = (float)acc;
+}
+
 }  // namespace
+
+hipError_t launch_mdot(const float* v, size_t vstride, int nvec, const float* w, int ns, size_t len,
+                       double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_mdot, dim3(nvec, ns), dim3(256), 0, st, v, vstride, nvec, w, len, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const float* v, size_t vstride, int nvec, const double* coef, int ns, size_t len,
+                          double beta, float* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_combine, dim3((unsigned)((len + 255) / 256), ns), dim3(256), 0, st, v, vstride, nvec,
+                     coef, len, beta, dst);
+  return hipGetLastError();
+}
 
 hipError_t launch_cg_init(const float* dd, float* x, float* r, float* p, int ns, size_t len, double* rr,
                           hipStream_t st) {

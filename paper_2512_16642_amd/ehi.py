@@ -36,7 +36,7 @@ SYMBOLS = (
     "ehi_factor_batch", "ehi_set_stream", "ehi_set_launch", "ehi_get_launch",
     "ehi_set_medium", "ehi_forward_subgrid", "ehi_backpropagate", "ehi_residual_spectra",
     "ehi_multipliers_to_time", "ehi_misfit", "ehi_cg_init", "ehi_cg_shift_dot", "ehi_cg_update",
-    "ehi_cg_direction",
+    "ehi_cg_direction", "ehi_mdot", "ehi_combine",
 )
 PROF_KINDS = ("setup", "step", "dft", "herk", "factor", "solve", "model")
 _PROF_N = 8
@@ -122,7 +122,10 @@ def lib() -> ctypes.CDLL:
     L.ehi_cg_shift_dot.argtypes = [vp, vp, dbl, i32, i64, vp, vp]
     L.ehi_cg_update.argtypes = [vp, vp, vp, vp, vp, vp, dbl, i32, i64, vp, vp, vp]
     L.ehi_cg_direction.argtypes = [vp, vp, vp, vp, i32, i64, vp]
-    for name in ("ehi_cg_init", "ehi_cg_shift_dot", "ehi_cg_update", "ehi_cg_direction"):
+    L.ehi_mdot.argtypes = [vp, i64, i32, vp, i32, i64, vp, vp]
+    L.ehi_combine.argtypes = [vp, i64, i32, vp, i32, i64, dbl, vp, vp]
+    for name in ("ehi_cg_init", "ehi_cg_shift_dot", "ehi_cg_update", "ehi_cg_direction", "ehi_mdot",
+                 "ehi_combine"):
         getattr(L, name).restype = st
     L.ehi_destroy.argtypes = [vp]
     L.ehi_destroy.restype = st

@@ -141,3 +141,13 @@ def test_cg_calls_validate_on_the_host(ehi):
     assert L.ehi_cg_shift_dot(None, None, d, -1, 1, None, None) == ehi.EHI_EINVAL
     assert L.ehi_cg_update(None, None, None, None, None, None, d, 1, 0, None, None, None) == ehi.EHI_EINVAL
     assert L.ehi_cg_direction(None, None, None, None, 2, 5, None) == ehi.EHI_EINVAL
+
+
+def test_block_calls_validate_on_the_host(ehi):
+    L = ehi.lib()
+    d = ctypes.c_double(1.0)
+    assert L.ehi_mdot(None, 10, 0, None, 0, 10, None, None) == ehi.EHI_OK
+    assert L.ehi_mdot(None, 10, -1, None, 1, 10, None, None) == ehi.EHI_EINVAL
+    assert L.ehi_mdot(None, 10, 2, None, 1, 10, None, None) == ehi.EHI_EINVAL
+    assert L.ehi_combine(None, 10, 2000, None, 1, 10, d, None, None) == ehi.EHI_EINVAL
+    assert L.ehi_combine(None, 10, 1, None, 1, 0, d, None, None) == ehi.EHI_EINVAL
