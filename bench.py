@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # precision, time levels, segment rows, band width, receivers per launch); recorded in
 # profiles/survey_layered-1000x300_pmc.md.  Any other shape reports null.
 MEASURED_TRAFFIC = {
-    ("layered-1000x300-nr200-nt4000-nf30-ns200", "split_bf16", 8, 128, 256, 200): (461956.5 * 2 + 1152470.3) * 1024,
+    ("layered-1000x300-nr200-nt4000-nf30-ns200", "split_bf16", 8, 128, 256, 200): (461511.5 * 2 + 1152355.5) * 1024,
 }
 
 
@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--nr-batch", type=int, default=0)
     ap.add_argument("--acc-ns", type=int, default=16, help="accuracy: sources per step")
     ap.add_argument("--cg-iters", type=int, default=60, help="accuracy: cap on the CG baseline's iterations")
-    ap.add_argument("--chunk", type=int, default=512, choices=[256, 512],
+    ap.add_argument("--chunk", type=int, default=1024, choices=[256, 512, 1024],
                     help="time samples per DFT staging window")
     ap.add_argument("--windows", type=int, default=1, choices=[1, 2],
                     help="staging windows (2: the DFT of one overlaps the stepping of the next)")

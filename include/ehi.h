@@ -100,8 +100,8 @@ typedef enum {
  *   nr_batch  receivers time-stepped together (0 = all).  Sizes the
  *             wavefield buffers.
  *   weighting an ehi_weighting value.
- *   chunk     time samples per staging window of the DFT (0 = 256; 256 or
- *             512).  A longer window halves the accumulator traffic of the
+ *   chunk     time samples per staging window of the DFT (0 = 256; 256, 512
+ *             or 1024).  Each doubling halves the accumulator traffic of the
  *             DFT and doubles the staging buffer (nr_batch x chunk x subgrid
  *             floats).
  *   keep_z, keep_x  spatial compression of the contraction (the orthonormal

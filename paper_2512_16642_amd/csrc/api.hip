@@ -72,7 +72,8 @@ bool validate(const ehi_survey_desc* d, std::string* why) {
   // buffer resources address one plane / one staging block with 31-bit byte offsets
   if ((Z + 4) * (X + 4 + ehi::kRowAlign) > (1LL << 28)) return bad("grid too large");
   long long nsub = (long long)((d->nz + d->stride - 1) / d->stride) * ((d->nx + d->stride - 1) / d->stride);
-  if (d->chunk != 0 && d->chunk != 256 && d->chunk != 512) return bad("chunk must be 0, 256 or 512");
+  if (d->chunk != 0 && d->chunk != 256 && d->chunk != 512 && d->chunk != 1024)
+    return bad("chunk must be 0, 256, 512 or 1024");
   {
     const int nzs = (d->nz + d->stride - 1) / d->stride, nxs = (d->nx + d->stride - 1) / d->stride;
     if ((d->keep_z == 0) != (d->keep_x == 0)) return bad("keep_z and keep_x must both be 0 or both positive");

@@ -80,6 +80,7 @@ def test_longer_staging_window(ehi):
     a = ehi.workspace_bytes(**_desc_kw())
     assert ehi.workspace_bytes(**_desc_kw(chunk=256)) == a
     assert ehi.workspace_bytes(**_desc_kw(chunk=512)) > a
+    assert ehi.workspace_bytes(**_desc_kw(chunk=1024)) > ehi.workspace_bytes(**_desc_kw(chunk=512))
 
 
 def test_workspace_grows_with_sizes(ehi):

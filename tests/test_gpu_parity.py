@@ -117,19 +117,21 @@ def test_launch_shapes_bitwise_identical(ehi):
     assert max(errs) < 5e-6
 
 
-def test_green_dft_512_sample_window(ehi, tiny_ref):
-    # the longer staging window changes only the grouping of the DFT sums
+@pytest.mark.parametrize("chunk", [512, 1024])
+def test_green_dft_longer_sample_windows(ehi, tiny_ref, chunk):
+    # a longer staging window changes only the grouping of the DFT sums (1024 >
+    # nt = 1000: one partial window)
     s = tiny_ref["s"]
-    sv = ehi.survey_from(s, chunk=512)
+    sv = ehi.survey_from(s, chunk=chunk)
     sv.build_green(dev(tiny_ref["v"]))
     G = sv.copy_green_dft().reshape(s.nf, s.nr, -1).cpu().numpy()
     sv.close()
     errs = per_freq_rel(G, tiny_ref["G"])
-    print("512-sample window ghat rel err per freq", errs)
+    print(chunk, "sample window ghat rel err per freq", errs)
     assert max(errs) < 5e-6
 
 
-@pytest.mark.parametrize("chunk,nr_batch", [(256, 0), (256, 2), (512, 3)])
+@pytest.mark.parametrize("chunk,nr_batch", [(256, 0), (256, 2), (512, 3), (1024, 0)])
 def test_two_staging_windows_bitwise_identical(ehi, chunk, nr_batch):
     # the DFT of each window on the second stream, overlapped with the steps of
     # the next: same kernels, same order of accumulation, so the same bits;
