@@ -2,7 +2,8 @@
 
 Workload: layered 1000 x 300 grid (h = 10 m, 40-cell sponge), 200 receivers,
 nt = 4000 at 0.8 ms, 30 frequencies over 3-15 Hz, 200 sources, stride 2,
-split-BF16 form, default launch shapes.
+split-BF16 form, default launch shapes, 1024-sample staging window and the
+whole-matrix contraction (as bench.py times them).
 
 The FP64 oracle cannot build all 200 Green functions in a test, so:
   * sampled outputs: the spectra of receivers 0 and 137 are computed by the
@@ -42,7 +43,7 @@ def ehi():
 def full(ehi):
     s = synth.layered_1000x300()
     v = s.velocity()
-    sv = ehi.survey_from(s, precision="split_bf16")
+    sv = ehi.survey_from(s, precision="split_bf16", chunk=1024)   # the benchmark's window
     vel = torch.from_numpy(v).cuda()
     sv.build_green(vel)
     sv.build_hessian()
@@ -70,6 +71,19 @@ def test_full_green_sampled_receivers(full, oracle_sample):
     errs = [rel(Gs[f], oracle_sample[f]) for f in range(s.nf)]
     print("full-size ghat rel err: max", max(errs), "min", min(errs))
     assert max(errs) < 5e-6
+
+
+def test_full_hessian_sampled_entries(full, oracle_sample):
+    # the 2 x 2 block of Hhat between the sampled receivers, from the oracle's
+    # own spectra of those two rows (the contraction at full size)
+    H = full["H"].cpu().numpy()
+    ref = hessian.hessian_r1(oracle_sample)                  # [nf][2][2]
+    errs = []
+    for f in range(ref.shape[0]):
+        blk = H[f][np.ix_(SAMPLE, SAMPLE)]
+        errs.append(float(np.abs(blk - ref[f]).max() / np.abs(ref[f]).max()))
+    print("full-size Hhat sampled 2x2 block rel err, max over frequencies", max(errs))
+    assert max(errs) < 1e-5
 
 
 def test_full_reciprocity(full):
@@ -132,7 +146,7 @@ def test_full_grid_two_receiver_survey_end_to_end(ehi, full, oracle_sample):
     mu = 1e-3 * solve.lambda_max(Hr)
     R = s.residuals()
     Xr = solve.multipliers(Hr, mu, R.astype(np.complex128))
-    sv = ehi.survey_from(s, precision="split_bf16")
+    sv = ehi.survey_from(s, precision="split_bf16", chunk=1024)
     sv.build_green(torch.from_numpy(full["v"]).cuda())
     sv.build_hessian()
     sv.factor(mu)
