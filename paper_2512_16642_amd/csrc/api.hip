@@ -170,6 +170,8 @@ ehi::Layout make_layout(const ehi::Geometry& g) {
   L.ca = take(sizeof(float) * g.plane());
   L.bd = take(sizeof(float) * (ehi::kMaxSponge + 1));
   L.rowtab = take(sizeof(ehi::RowEntry) * (size_t)ehi::cdiv(g.Z, ehi::kMinSegRows) * ehi::kRowTabStride);
+  L.rowrec = take(sizeof(int32_t) * (size_t)g.Z);
+  L.recmap = take(sizeof(int32_t) * g.plane());
   L.vmax = take(sizeof(uint32_t) * 4);
   L.tw = take(sizeof(float2) * (size_t)g.nt * g.nf);
   L.u0 = take(sizeof(float) * g.plane() * g.nrb);
@@ -309,6 +311,23 @@ ehi_status ehi_create(const ehi_survey_desc* desc, void* workspace_dev, size_t w
   if (e == hipSuccess)
     e = hipMemcpyAsync(s->ptr<int32_t>(L.rec), rec.data(), sizeof(int32_t) * 2 * g.nr,
                        hipMemcpyHostToDevice, s->stream);
+  // receiver map of the padded plane (index, -1 elsewhere) and the rows holding
+  // receivers, for the modelling runs on the marching kernel
+  std::vector<int32_t> recmap(g.plane(), -1), rowrec(g.Z, 0);
+  s->rec_distinct = true;
+  for (int r = 0; r < g.nr; ++r) {
+    const int q = s->rec_iz[r] + g.nb;
+    const size_t o = (size_t)(q + ehi::kGhost) * g.Xp + (s->rec_ix[r] + g.nb + ehi::kGhost);
+    if (recmap[o] >= 0) s->rec_distinct = false;
+    recmap[o] = r;
+    rowrec[q] = 1;
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->ptr<int32_t>(L.recmap), recmap.data(), sizeof(int32_t) * recmap.size(),
+                       hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->ptr<int32_t>(L.rowrec), rowrec.data(), sizeof(int32_t) * rowrec.size(),
+                       hipMemcpyHostToDevice, s->stream);
   if (e == hipSuccess) e = ehi::launch_twiddles(g, s->ptr<double>(L.freq), s->ptr<float2>(L.tw), s->stream);
   if (e == hipSuccess && g.keep_z > 0) {
     e = ehi::launch_dct_matrix(g.nzs, g.keep_z, s->ptr<float2>(L.dctz), s->stream);
@@ -392,7 +411,7 @@ ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev) {
   EHI_TRY(ehi::launch_coefficients(g, vel_dev, vmax, ca, bd, st), "coefficients");
   s->medium = true;
   ehi::RowEntry* rowtab = s->ptr<ehi::RowEntry>(L.rowtab);
-  EHI_TRY(ehi::launch_row_table(g, bd, rowtab, st), "row table");
+  EHI_TRY(ehi::launch_row_table(g, bd, s->ptr<int32_t>(L.rowrec), rowtab, st), "row table");
   PROF_N(4);
   const float2* tw = s->ptr<float2>(L.tw);
   float2* ghat = s->ptr<float2>(L.ghat);
@@ -790,10 +809,87 @@ ehi_status model_check(ehi_survey* s, const void* in, const void* out, int32_t n
 
 }  // namespace
 
+namespace {
+
+// S (mode 1) or S^T (mode 2) on the marching kernel, 8 time levels per launch:
+// needs distinct receiver cells and buffers the 32-bit buffer offsets reach.
+bool march_model_ok(const ehi_survey* s) {
+  const ehi::Geometry& g = s->g;
+  return s->rec_distinct && g.tblock == 8 && (long long)g.nt * g.nsub * 4 < (1LL << 31) &&
+         (long long)g.nr * g.nt * 4 < (1LL << 31);
+}
+
+ehi_status march_model(ehi_survey* s, int mode, const float* in, int32_t ns, float* out) {
+  // segment height for about 1024 workgroups per launch (a modelling batch holds
+  // fewer fields than a Green-function batch has receivers), 32 rows at least;
+  // the Green-function build rebuilds its own row table
+  ehi::Geometry g = s->g;
+  {
+    const int fields = std::min(g.nrb, ns);
+    const int want_seg = ehi::cdiv(1024, std::max(1, fields * ehi::march_bands(g)));
+    int seg = std::max(32, ehi::cdiv(ehi::cdiv(g.Z, want_seg), 16) * 16);
+    if (const char* e = std::getenv("EHI_MODEL_SEG")) {
+      const int v = std::atoi(e);
+      if (v >= ehi::kMinSegRows && v <= ehi::kMaxSegRows) seg = v;
+    }
+    g.seg_rows = std::min(seg, ehi::kMaxSegRows);
+  }
+  const ehi::Layout& L = s->L;
+  hipStream_t st = s->stream;
+  const float* ca = s->ptr<float>(L.ca);
+  const float* bd = s->ptr<float>(L.bd);
+  ehi::RowEntry* rowtab = s->ptr<ehi::RowEntry>(L.rowtab);
+  float* ub[2] = {s->ptr<float>(L.u0), s->ptr<float>(L.u1)};
+  float* wb[2] = {s->ptr<float>(L.w0), s->ptr<float>(L.w1)};
+  const size_t src_field = (size_t)g.nt * g.nsub, d_field = (size_t)g.nr * g.nt;
+  PROF(EHI_PROF_MODEL, st);
+  // the row table of the current launch shape (set_launch may have changed it)
+  EHI_TRY(ehi::launch_row_table(g, bd, s->ptr<int32_t>(L.rowrec), rowtab, st), "row table");
+  PROF_N(1);
+  for (int s0 = 0; s0 < ns; s0 += g.nrb) {
+    const int nb = std::min(g.nrb, ns - s0);
+    const size_t nplane = (size_t)nb * g.plane();
+    for (int b = 0; b < 2; ++b) {
+      EHI_TRY(ehi::launch_fill_u32(reinterpret_cast<uint32_t*>(ub[b]), 0u, nplane, st), "fill");
+      EHI_TRY(ehi::launch_fill_u32(reinterpret_cast<uint32_t*>(wb[b]), 0u, nplane, st), "fill");
+    }
+    PROF_N(4);
+    ehi::ModelArgs m{};
+    m.recmap = s->ptr<int32_t>(L.recmap);
+    m.src_field = src_field;
+    m.dat_field = d_field;
+    m.sub_field = src_field;
+    m.nt = g.nt;
+    m.scale = (float)(12.0 * g.h * g.h);
+    if (mode == 1) {
+      m.src = in + (size_t)s0 * src_field;
+      m.dat_out = out + (size_t)s0 * d_field;
+    } else {
+      m.dat_in = in + (size_t)s0 * d_field;
+      m.sub_out = out + (size_t)s0 * src_field;
+    }
+    int cur = 0;
+    for (int n = 0; n < g.nt; n += 8) {
+      const int nlev = std::min(8, g.nt - n);
+      m.n_in = n;
+      EHI_TRY(ehi::launch_march_model(g, mode, ca, bd, rowtab, ub[cur], wb[cur], ub[1 - cur], wb[1 - cur], m,
+                                      nlev, nb, st),
+              mode == 1 ? "forward steps" : "adjoint steps");
+      PROF_N(1);
+      cur = 1 - cur;
+    }
+  }
+  PROF_END();
+  return EHI_OK;
+}
+
+}  // namespace
+
 ehi_status ehi_forward_subgrid(ehi_survey* s, const float* src_dev, int32_t ns, float* data_dev) {
   g_err.clear();
   ehi_status chk = model_check(s, src_dev, data_dev, ns);
   if (chk != EHI_OK || ns == 0) return chk;
+  if (march_model_ok(s)) return march_model(s, 1, src_dev, ns, data_dev);
   const ehi::Geometry& g = s->g;
   const ehi::Layout& L = s->L;
   hipStream_t st = s->stream;
@@ -832,6 +928,7 @@ ehi_status ehi_backpropagate(ehi_survey* s, const float* data_dev, int32_t ns, f
   g_err.clear();
   ehi_status chk = model_check(s, data_dev, src_dev, ns);
   if (chk != EHI_OK || ns == 0) return chk;
+  if (march_model_ok(s)) return march_model(s, 2, data_dev, ns, src_dev);
   const ehi::Geometry& g = s->g;
   const ehi::Layout& L = s->L;
   hipStream_t st = s->stream;

@@ -53,6 +53,8 @@ struct Layout {
   size_t ca;        // float [Zp][Xp]  kappa / (12 h^2 a)
   size_t bd;        // float [kMaxSponge + 1]  b / a by distance into the layer
   size_t rowtab;    // RowEntry [cdiv(Z, kMinSegRows)][kRowTabStride]  marching row table
+  size_t rowrec;    // int32 [Z]  1 if the padded row holds a receiver
+  size_t recmap;    // int32 [Zp][Xp]  receiver index per cell (-1: none), for the modelling runs
   size_t vmax;      // uint32 [4]  max velocity bits
   size_t tw;        // float2 [nt][nf] exp(-i w n dt), n = 1..nt
   size_t u0, u1;    // float [nrb][Zp][Xp]  (ping-pong)
@@ -133,6 +135,7 @@ struct ehi_survey {
   int device;
   ehi::State state;
   bool medium;      // ca, bd hold a velocity model (build_green or set_medium)
+  bool rec_distinct; // no two receivers share a cell (the marching modelling path applies)
   double mu;
   ehi::Profiler prof;
   template <class T>
@@ -151,10 +154,30 @@ constexpr int kRowTabStride = kMaxSegRows + 6 * 8 + 8;
 // bz = b / a of the row's distance into the top/bottom layer (1 outside the
 // grid); own = byte offset of the row in a plane if the segment owns it, else
 // -1; sub = byte offset of the row's subgrid line inside a staging slot if the
-// segment owns it and it lies on the subgrid, else -1.
+// segment owns it and it lies on the subgrid, else -1.  For the modelling
+// runs: suball = the subgrid line offset for any row on the subgrid (owned or
+// halo), recall = the row's byte offset in the receiver map for any row
+// holding a receiver, recown = the same for owned rows only (else -1).
 struct alignas(16) RowEntry {
   float bz;
-  int32_t own, sub, pad;
+  int32_t own, sub, recown;
+  int32_t suball, recall, pad0, pad1;
+};
+
+// Arguments of the modelling modes of the marching kernel (forward S with a
+// subgrid source and traces recorded at the receivers; S^T with the traces
+// injected at the receivers and the field recorded on the subgrid).  Pointers
+// are the batch's first field; field k adds k * the *_field strides (floats).
+struct ModelArgs {
+  const float* src;       // S: source [field][nt][nsub]
+  const float* dat_in;    // S^T: traces [field][nr][nt]
+  float* dat_out;         // S: traces [field][nr][nt]
+  float* sub_out;         // S^T: subgrid field [field][nt][nsub]
+  const int32_t* recmap;  // receiver index of every plane cell, -1 elsewhere
+  size_t src_field, dat_field, sub_field;
+  int n_in;               // sample index of the launch's input level
+  int nt;
+  float scale;            // 12 h^2: kappa f / a = ca 12 h^2 f
 };
 
 // ---- launchers (each returns hipGetLastError() of its launch) ----------------
@@ -167,7 +190,12 @@ hipError_t launch_wave_init(const Geometry& g, const float* vel, const int32_t* 
                             int nrb_now, float* u0, float* w0, float* stage, hipStream_t st);
 int march_bands(const Geometry& g);
 int march_band_for(int X, int tblock);  // band width covering X columns with the fewest lanes
-hipError_t launch_row_table(const Geometry& g, const float* bd, RowEntry* rt, hipStream_t st);
+hipError_t launch_row_table(const Geometry& g, const float* bd, const int32_t* rowrec, RowEntry* rt,
+                            hipStream_t st);
+// modelling runs on the marching kernel: mode 1 = S, mode 2 = S^T (tblock 8 only)
+hipError_t launch_march_model(const Geometry& g, int mode, const float* ca, const float* bd, const RowEntry* rt,
+                              const float* uin, const float* win, float* uout, float* wout,
+                              const ModelArgs& m, int nlev, int nrb_now, hipStream_t st);
 hipError_t launch_march(const Geometry& g, const float* ca, const float* bd, const RowEntry* rt,
                         const float* uin, const float* win, float* uout, float* wout, float* stage,
                         int slot0, int nlev, int nrb_now, hipStream_t st);

@@ -80,7 +80,10 @@ __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, int vo
 constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
 constexpr int lcm_c(int a, int b) { return a / gcd_c(a, b) * b; }
 
-template <int T, bool FULL, int PD, int KB>
+// MODE 0: Green functions (staged subgrid samples); 1: S (subgrid source in,
+// traces at the receivers out); 2: S^T (traces injected at the receivers,
+// subgrid field out in reversed time, through the staging store).
+template <int T, bool FULL, int PD, int KB, int MODE = 0>
 struct March3 {
   static constexpr int CRR = T == 4 ? 12 : 24;          // ca ring rows (>= 2T + 2, even)
   // iterations per unrolled body: a multiple of the u/w ring (3 iterations), the
@@ -102,6 +105,7 @@ struct March3 {
   float Wr[T][6];   // level-t w
   float C[CRR];     // ca rows, slot = rho mod CRR
   float pu[SETS][2], pw[SETS][2], pc[SETS][2];  // prefetch sets [set][row of pair]
+  float fs[MODE == 1 ? T : 1][2];  // S: this iteration's source samples [level][row of pair]
 
   struct Ctx {
     __amdgpu_buffer_rsrc_t ru, rw, rc, rou, row_, rst;
@@ -116,6 +120,12 @@ struct March3 {
     int slot_off;        // byte offset of staging slot slot0
     const CRowEntry* rt; // this segment's row table (entry rho + 2T = row kb + rho)
     float bx;   // bd[distance of the column into the left/right layer]
+    // modelling modes: source / trace / receiver-map resources of this field,
+    // the lane's subgrid column for any subgrid lane (halo included) or kDrop
+    __amdgpu_buffer_rsrc_t rsrc, rdat, rmap;
+    unsigned vsuba;
+    int src_off, src_pitch, n_in, nt;
+    float scale;
   };
 
   // rows outside the grid read the zero ghost row next to the edge
@@ -149,6 +159,19 @@ struct March3 {
     C[C0] = pc[SET][0];
     C[C0 + 1] = pc[SET][1];
     load_pair(x, 2 * (i + PD), (PH + PD) % SETS);
+    if constexpr (MODE == 1) {
+      // the sources of this iteration's levels, issued before the barrier so
+      // the loads are in flight while the rows are published
+#pragma unroll
+      for (int t = 1; t <= T; ++t)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int sa = rrow[2 * T - 2 * t + h].suball;
+          fs[t - 1][h] = ((FULL || t <= x.nlev) && sa >= 0)
+                             ? bload(x.rsrc, (int)x.vsuba, x.src_off + (t - 1) * x.src_pitch + sa)
+                             : 0.f;
+        }
+    }
     float* col = sh.lu + x.tid * LS;  // column c - 2 of this lane; own column at + 2 LS
 #pragma unroll
     for (int t = 0; t < T; ++t)
@@ -162,22 +185,46 @@ struct March3 {
         const int sl = mod(2 * PH - 2 * t + h, 6);  // slot of row rho = 2i - 2t + h
         const int sm2 = (sl + 4) % 6, sm1 = (sl + 5) % 6, sp1 = (sl + 1) % 6, sp2 = (sl + 2) % 6;
         const int cs = mod(2 * PH - 2 * t + h, CRR);
-        const float re_bz = rrow[2 * T - 2 * t + h].bz;
-        const int re_sub = rrow[2 * T - 2 * t + h].sub;
-        const int re_own = rrow[2 * T - 2 * t + h].own;
+        const CRowEntry& re = rrow[2 * T - 2 * t + h];
+        const float re_bz = re.bz;
+        const int re_sub = re.sub;
+        const int re_own = re.own;
         const float cen = U[t - 1][sl];
         float un, wn;
         if (FULL || t <= x.nlev) {
           const int e = (BUF * T + t - 1) * 2 + h;
           const float n1 = (col[LS + e] + col[3 * LS + e]) + (U[t - 1][sm1] + U[t - 1][sp1]);
           const float n2 = (col[e] + col[4 * LS + e]) + (U[t - 1][sm2] + U[t - 1][sp2]);
-          const float lap = 16.f * n1 - n2 - 60.f * cen;
+          float lap = 16.f * n1 - n2 - 60.f * cen;
+          if constexpr (MODE == 1) {
+            // the source of the step that produces sample n_in + t
+            lap += x.scale * fs[t - 1][h];
+          } else if constexpr (MODE == 2) {
+            // trace sample nt - (n_in + t) injected at the receivers of this row
+            const int ra = re.recall;
+            if (ra >= 0) {
+              const int ridx = __float_as_int(bload(x.rmap, x.voff, ra));
+              const unsigned vo = ridx >= 0 ? (unsigned)((ridx * x.nt + x.nt - x.n_in - t) * 4) : kDrop;
+              lap += x.scale * bload(x.rdat, (int)vo, 0);
+            }
+          }
           // bd is non-increasing in the distance, so bd[max(dz, dx)] = min(bd[dz], bd[dx]);
           // both are positive floats, whose bit patterns order like the integers
           const float bq = __int_as_float(min(__float_as_int(re_bz), __float_as_int(x.bx)));
           wn = bq * Wr[t - 1][sl] + C[cs] * lap;
           un = cen + wn;
-          if (re_sub >= 0) bstore(un, x.rst, (int)x.vsub, x.slot_off + (t - 1) * x.slot_bytes + re_sub);
+          if constexpr (MODE != 1) {
+            if (re_sub >= 0) bstore(un, x.rst, (int)x.vsub, x.slot_off + (t - 1) * x.slot_bytes + re_sub);
+          } else {
+            // sample n_in + t at the receivers of an owned row
+            const int ro = re.recown;
+            if (ro >= 0) {
+              const int ridx = __float_as_int(bload(x.rmap, x.voff, ro));
+              const unsigned vo =
+                  (ridx >= 0 && x.vown != kDrop) ? (unsigned)((ridx * x.nt + x.n_in + t - 1) * 4) : kDrop;
+              bstore(un, x.rdat, (int)vo, 0);
+            }
+          }
         } else {
           un = cen;
           wn = Wr[t - 1][sl];
@@ -206,13 +253,13 @@ struct March3 {
   }
 };
 
-template <int T, bool FULL, int PD, int KB>
+template <int T, bool FULL, int PD, int KB, int MODE = 0>
 __global__ void __launch_bounds__(KB)
     k_march(Geometry g, const float* __restrict__ ca, const float* __restrict__ bd,
             const RowEntry* __restrict__ rowtab, const float* __restrict__ uin,
             const float* __restrict__ win, float* __restrict__ uout, float* __restrict__ wout,
-            float* __restrict__ stage, int slot0, int nlev) {
-  using M = March3<T, FULL, PD, KB>;
+            float* __restrict__ stage, int slot0, int nlev, ModelArgs ma) {
+  using M = March3<T, FULL, PD, KB, MODE>;
   __shared__ typename M::Shared sh;
   typename M::Ctx x;
   x.tid = threadIdx.x;
@@ -236,10 +283,31 @@ __global__ void __launch_bounds__(KB)
   x.rc = make_rsrc(ca, pbytes);
   x.rou = make_rsrc(uout + (size_t)r * plane, pbytes);
   x.row_ = make_rsrc(wout + (size_t)r * plane, pbytes);
-  const size_t sbytes = (size_t)g.chunk * g.nsub_p * sizeof(float);
-  x.rst = make_rsrc(stage + (size_t)r * g.chunk * g.nsub_p, sbytes);
-  x.slot_bytes = g.nsub_p * 4;
-  x.slot_off = slot0 * x.slot_bytes;
+  if constexpr (MODE == 0) {
+    const size_t sbytes = (size_t)g.chunk * g.nsub_p * sizeof(float);
+    x.rst = make_rsrc(stage + (size_t)r * g.chunk * g.nsub_p, sbytes);
+    x.slot_bytes = g.nsub_p * 4;
+    x.slot_off = slot0 * x.slot_bytes;
+  } else {
+    const size_t fbytes = (size_t)ma.nt * g.nsub * sizeof(float);
+    const size_t tbytes = (size_t)g.nr * ma.nt * sizeof(float);
+    x.rmap = make_rsrc(ma.recmap, plane * sizeof(int32_t));
+    x.n_in = ma.n_in;
+    x.nt = ma.nt;
+    x.scale = ma.scale;
+    if constexpr (MODE == 1) {
+      x.rsrc = make_rsrc(ma.src + (size_t)r * ma.src_field, fbytes);
+      x.rdat = make_rsrc(ma.dat_out + (size_t)r * ma.dat_field, tbytes);
+      x.src_pitch = g.nsub * 4;
+      x.src_off = ma.n_in * x.src_pitch;
+    } else {
+      x.rdat = make_rsrc(ma.dat_in + (size_t)r * ma.dat_field, tbytes);
+      // sample m = n_in + t goes to slot nt - m: a descending slot pitch
+      x.rst = make_rsrc(ma.sub_out + (size_t)r * ma.sub_field, fbytes);
+      x.slot_bytes = -g.nsub * 4;
+      x.slot_off = (ma.nt - ma.n_in - 1) * g.nsub * 4;
+    }
+  }
   // the table is read-only during the launch: constant address space, so the
   // uniform entries are fetched with scalar loads
   x.rt = (const CRowEntry*)rowtab + (size_t)blockIdx.z * kRowTabStride;
@@ -249,6 +317,7 @@ __global__ void __launch_bounds__(KB)
   const bool subx = jx >= 0 && jx < g.nx && (jx & (g.stride - 1)) == 0;
   x.vown = own ? (unsigned)x.voff : kDrop;
   x.vsub = (own && subx) ? (unsigned)((jx >> g.sshift) * 4) : kDrop;
+  if constexpr (MODE == 1) x.vsuba = (colv && subx) ? (unsigned)((jx >> g.sshift) * 4) : kDrop;
   x.bx = bd[colv ? max(max(g.nb - c, c - (g.nb + g.nx - 1)), 0) : 0];
 
   // the two zero columns on each side of the band
@@ -382,8 +451,8 @@ __global__ void __launch_bounds__(256)
 
 // Row table for the current launch shape: entry ti of segment sg describes
 // padded row q = sg * seg_rows - 4T + ti.
-__global__ void k_row_table(Geometry g, const float* __restrict__ bd, RowEntry* __restrict__ rt,
-                            int nseg) {
+__global__ void k_row_table(Geometry g, const float* __restrict__ bd, const int32_t* __restrict__ rowrec,
+                            RowEntry* __restrict__ rt, int nseg) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nseg * kRowTabStride) return;
   const int sg = e / kRowTabStride, ti = e % kRowTabStride;
@@ -396,19 +465,25 @@ __global__ void k_row_table(Geometry g, const float* __restrict__ bd, RowEntry* 
   const bool owned = q >= z0 && q < z1;
   r.own = owned ? (q + kGhost) * g.Xp * 4 : -1;
   const int jz = q - g.nb;
-  const bool subz = owned && jz >= 0 && jz < g.nz && (jz & (g.stride - 1)) == 0;
-  r.sub = subz ? (jz >> g.sshift) * g.nxs * 4 : -1;
-  r.pad = 0;
+  const bool onsub = jz >= 0 && jz < g.nz && (jz & (g.stride - 1)) == 0;
+  r.sub = (owned && onsub) ? (jz >> g.sshift) * g.nxs * 4 : -1;
+  r.suball = onsub ? (jz >> g.sshift) * g.nxs * 4 : -1;
+  const bool hasrec = inside && rowrec[q] != 0;
+  const int rowoff = (q + kGhost) * g.Xp * 4;
+  r.recall = hasrec ? rowoff : -1;
+  r.recown = (hasrec && owned) ? rowoff : -1;
+  r.pad0 = r.pad1 = 0;
   rt[e] = r;
 }
 
 int march_bands(const Geometry& g) { return cdiv(g.X, g.band - 4 * g.tblock); }
 
-hipError_t launch_row_table(const Geometry& g, const float* bd, RowEntry* rt, hipStream_t st) {
+hipError_t launch_row_table(const Geometry& g, const float* bd, const int32_t* rowrec, RowEntry* rt,
+                            hipStream_t st) {
   if (g.seg_rows < kMinSegRows || g.seg_rows > kMaxSegRows) return hipErrorInvalidValue;
   const int nseg = cdiv(g.Z, g.seg_rows);
   const int n = nseg * kRowTabStride;
-  hipLaunchKernelGGL(k_row_table, dim3(cdiv(n, 256)), dim3(256), 0, st, g, bd, rt, nseg);
+  hipLaunchKernelGGL(k_row_table, dim3(cdiv(n, 256)), dim3(256), 0, st, g, bd, rowrec, rt, nseg);
   return hipGetLastError();
 }
 
@@ -433,7 +508,7 @@ hipError_t launch_march(const Geometry& g, const float* ca, const float* bd, con
   dim3 grid(nrb_now, march_bands(g), cdiv(g.Z, g.seg_rows));
 #define EHI_MARCH(TT, FF, KK)                                                                     \
   hipLaunchKernelGGL((k_march<TT, FF, 2, KK>), grid, dim3(KK), 0, st, g, ca, bd, rt, uin, win,   \
-                     uout, wout, stage, slot0, nlev)
+                     uout, wout, stage, slot0, nlev, ModelArgs{})
 #define EHI_MARCH_T(TT, KK)                \
   if (nlev == TT) EHI_MARCH(TT, true, KK); \
   else EHI_MARCH(TT, false, KK);
@@ -455,6 +530,38 @@ hipError_t launch_march(const Geometry& g, const float* ca, const float* bd, con
 #undef EHI_MARCH_B
 #undef EHI_MARCH_T
 #undef EHI_MARCH
+  return hipGetLastError();
+}
+
+hipError_t launch_march_model(const Geometry& g, int mode, const float* ca, const float* bd, const RowEntry* rt,
+                              const float* uin, const float* win, float* uout, float* wout,
+                              const ModelArgs& m, int nlev, int nrb_now, hipStream_t st) {
+  if (g.nb > kMaxSponge || g.seg_rows < kMinSegRows || g.seg_rows > kMaxSegRows || nlev < 1 ||
+      nlev > 8 || g.tblock != 8 || (mode != 1 && mode != 2) || m.n_in < 0 || m.n_in + nlev > m.nt)
+    return hipErrorInvalidValue;
+  dim3 grid(nrb_now, march_bands(g), cdiv(g.Z, g.seg_rows));
+#define EHI_MODEL(MM, FF, KK)                                                                        \
+  hipLaunchKernelGGL((k_march<8, FF, 2, KK, MM>), grid, dim3(KK), 0, st, g, ca, bd, rt, uin, win,     \
+                     uout, wout, nullptr, 0, nlev, m)
+#define EHI_MODEL_F(MM, KK)                 \
+  if (nlev == 8) EHI_MODEL(MM, true, KK);   \
+  else EHI_MODEL(MM, false, KK);
+#define EHI_MODEL_B(MM)                                 \
+  switch (g.band) {                                     \
+    case 256: EHI_MODEL_F(MM, 256) break;               \
+    case 384: EHI_MODEL_F(MM, 384) break;               \
+    case 448: EHI_MODEL_F(MM, 448) break;               \
+    case 512: EHI_MODEL_F(MM, 512) break;               \
+    default: return hipErrorInvalidValue;               \
+  }
+  if (mode == 1) {
+    EHI_MODEL_B(1)
+  } else {
+    EHI_MODEL_B(2)
+  }
+#undef EHI_MODEL_B
+#undef EHI_MODEL_F
+#undef EHI_MODEL
   return hipGetLastError();
 }
 
