@@ -171,3 +171,44 @@ def test_accuracy_test_matches_oracle(ehi):
     print("accuracy test vs oracle:", e, "| RelErr", out[4], "oracle", relerr_r)
     assert e["dde"] < 1e-6 and e["db"] < 5e-6 and e["pred"] < 5e-6
     assert e["err"] < 5e-6 and e["relerr"] < 1e-6
+
+
+@pytest.mark.parametrize("case", ["shared_cell", "four_levels"])
+def test_single_level_fallback_matches_oracle(ehi, case):
+    # receivers sharing a cell (the receiver map holds one index per cell) or a
+    # 4-level launch shape: S and S^T step one level per launch instead
+    s = _ragged()
+    if case == "shared_cell":
+        s = s.with_(rec_iz=s.rec_iz[:4] + (s.rec_iz[1],), rec_ix=s.rec_ix[:4] + (s.rec_ix[1],))
+    f = synth.subgrid_sources(2, s.nt, s.nzs, s.nxs, seed=51)
+    x = synth.time_residuals(2, s.nr, s.nt, seed=52)
+    sv = _medium_survey(ehi, s)
+    if case == "four_levels":
+        sv.set_launch(4, 0, 0)
+    d = sv.forward_subgrid(torch.from_numpy(f).cuda()).cpu().numpy()
+    db = sv.backpropagate(torch.from_numpy(x).cuda()).cpu().numpy()
+    sv.close()
+    op = _op(s)
+    ef = [rel(d[k], op.apply(f[k].astype(np.float64))) for k in range(2)]
+    eb = [rel(db[k].reshape(s.nt, -1), op.adjoint(x[k].astype(np.float64))) for k in range(2)]
+    print(case, "fallback S", ef, "S^T", eb)
+    assert max(ef) < 2e-6 and max(eb) < 2e-6
+
+
+def test_march_modelling_independent_of_launch_shape(ehi):
+    # the modelling march gives the same bits for every band width and segment
+    # height (the segment height of a modelling run is its own choice)
+    s = _ragged().with_(nx=700)
+    f = torch.from_numpy(synth.subgrid_sources(2, s.nt, s.nzs, s.nxs, seed=53)).cuda()
+    x = torch.from_numpy(synth.time_residuals(2, s.nr, s.nt, seed=54)).cuda()
+    ref = None
+    for band in (256, 384, 448, 512):
+        sv = _medium_survey(ehi, s)
+        sv.set_launch(8, 0, band)
+        out = (sv.forward_subgrid(f).cpu().numpy(), sv.backpropagate(x).cpu().numpy())
+        sv.close()
+        if ref is None:
+            ref = out
+        else:
+            np.testing.assert_array_equal(out[0], ref[0], err_msg=f"S band {band}")
+            np.testing.assert_array_equal(out[1], ref[1], err_msg=f"S^T band {band}")
