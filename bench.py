@@ -500,10 +500,11 @@ def main():
     herk_flops = costs.herk_flops_per_survey(s.nz, s.nx, s.stride, s.nr, s.nf) * rep
     herk_ms = prof["herk"][0] / K
     # 32 x 32 block pairs in the whole-matrix contraction (up to 224 receivers,
-    # final-spectrum form), 64 x 64 tile pairs otherwise
+    # final-spectrum form) and in the finite-record contraction, 64 x 64 tile
+    # pairs otherwise
     whole = (args.precision == "split_bf16" and args.weighting == "long_record" and s.nr <= 224
              and os.environ.get("EHI_HERK_WHOLE", "1") != "0")
-    herk_tile = 32 if whole else 64
+    herk_tile = 32 if (whole or args.weighting == "finite_record") else 64
     out = {
         "metric": METRIC,
         "value": round(survey_s, 6),

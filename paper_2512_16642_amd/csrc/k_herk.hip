@@ -453,8 +453,10 @@ __global__ void __launch_bounds__(512)
 // min(Nt - m, Nt - n) in the algorithm for the Fourier block-diagonal Hessian):
 // Hhat_W(w) = (1/Nt) sum_{p=1}^{Nt} Ghat_p(w) Ghat_p(w)^H, Ghat_p the DFT
 // truncated after sample p.  One launch per staging window (samples
-// n0 .. n0 + cnt - 1), before the DFT advances the spectra: a workgroup owns one
-// (frequency, 64 x 64 tile pair, grid partition), each wave a 32 x 32 quarter.
+// n0 .. n0 + cnt - 1), before the DFT advances the spectra: each wave owns one
+// 32 x 32 block pair (bi <= bj) of one frequency and grid partition, four
+// block pairs to a workgroup (no block below the diagonal or beyond nr is
+// computed).
 // For every 32-point block of the partition a wave starts from the running
 // spectra Ghat_{n0-1} of its 32 i-rows and 32 j-rows (zero for the first
 // window), adds one staged sample times its twiddle per step and contracts
@@ -464,15 +466,18 @@ __global__ void __launch_bounds__(512)
 // 8 (lane / 16) ..), so the step loop needs no data exchange between waves;
 // rows shared by two waves are updated by both.  Sums: 16 steps in FP32, then
 // FP64 (per-lane LDS slots) over steps and blocks, then FP64 over windows
-// (hpart64, read-modify-written by the one workgroup that owns the entry).
+// (hpart64, read-modify-written by the one wave that owns the entry).
 // All receivers must be stepped together.
 __global__ void __launch_bounds__(256)
     k_herk_r2(Geometry g, const float* __restrict__ stage, const float2* __restrict__ tw,
               const float2* __restrict__ ghat, int n0, int cnt, int first,
               double2* __restrict__ hpart64) {
   __shared__ double acc_s[32][256];  // per lane: [a][b][re/im][v] FP64 sums
-  const int nblk = cdiv(g.nr, kBt);
+  // work: the 32 x 32 block pairs (bi <= bj) of the upper triangle, four to a
+  // workgroup (one per wave; the waves are independent)
+  const int nblk = cdiv(g.nr, 32);
   const int npair = nblk * (nblk + 1) / 2;
+  const int ngrp = cdiv(npair, 4);
   const int split = g.herk_split;
   // XCD-aware work item; the frequency varies fastest, so the workgroups that
   // read the same staged rows share an XCD's L2
@@ -481,9 +486,13 @@ __global__ void __launch_bounds__(256)
   const int item = n < n8 ? (n % kXcd) * (n8 / kXcd) + n / kXcd : n;
   const int f = item % g.nf;
   const int rest = item / g.nf;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int pidx = 4 * (rest % ngrp) + wave;
+  if (pidx >= npair) return;
   int bi, bj;
   {
-    int p = rest % npair, i = 0;
+    int p = pidx, i = 0;
     while (p >= nblk - i) {
       p -= nblk - i;
       ++i;
@@ -491,13 +500,10 @@ __global__ void __launch_bounds__(256)
     bi = i;
     bj = i + p;
   }
-  const int ks = rest / npair;
+  const int ks = rest / ngrp;
   const int kchunk = cdiv(cdiv(g.nsub, split), kBk) * kBk;
   const int k0 = ks * kchunk;
   const int k1 = min(g.nsub, k0 + kchunk);
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wi = wave >> 1, wj = wave & 1;
   const int fr = lane & 15, fg = lane >> 4;
   // this lane's four rows: i-rows (a = 0, 1), then j-rows (b = 0, 1)
   int row[4];
@@ -506,7 +512,7 @@ __global__ void __launch_bounds__(256)
   const float2* Grow[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    row[u] = u < 2 ? bi * kBt + wi * 32 + u * 16 + fr : bj * kBt + wj * 32 + (u - 2) * 16 + fr;
+    row[u] = u < 2 ? bi * 32 + u * 16 + fr : bj * 32 + (u - 2) * 16 + fr;
     rv[u] = row[u] < g.nr;
     Srow[u] = stage + (size_t)(rv[u] ? row[u] : 0) * g.chunk * g.nsub_p;
     Grow[u] = ghat + ((size_t)f * g.nr + (rv[u] ? row[u] : 0)) * g.nsub;
@@ -624,8 +630,8 @@ __global__ void __launch_bounds__(256)
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v4 = 0; v4 < 4; ++v4) {
-        const int i = bi * kBt + wi * 32 + a * 16 + 4 * (lane >> 4) + v4;
-        const int j = bj * kBt + wj * 32 + b * 16 + (lane & 15);
+        const int i = bi * 32 + a * 16 + 4 * (lane >> 4) + v4;
+        const int j = bj * 32 + b * 16 + (lane & 15);
         if (i < g.nr && j < g.nr) {
           double2* o = out + (size_t)i * g.nr + j;
           double2 v = first ? make_double2(0.0, 0.0) : *o;
@@ -728,7 +734,8 @@ hipError_t launch_herk_split_bf16(const Geometry& g, const float2* ghat, float2*
 hipError_t launch_herk_r2_chunk(const Geometry& g, const float* stage, const float2* tw,
                                 const float2* ghat, int n0, int cnt, bool first, double2* hpart64,
                                 hipStream_t st) {
-  const long long items = (long long)herk_bf16_blocks(g) * g.herk_split * g.nf;
+  const int nb32 = cdiv(g.nr, 32);
+  const long long items = (long long)cdiv(nb32 * (nb32 + 1) / 2, 4) * g.herk_split * g.nf;
   if (items > 0x7fffffffLL || cnt < 1 || cnt > g.chunk || g.nrb < g.nr) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_herk_r2, dim3((unsigned)items), dim3(256), 0, st, g, stage, tw, ghat, n0, cnt,
                      first ? 1 : 0, hpart64);
