@@ -355,7 +355,7 @@ constexpr int kDftKs = 64;  // time samples per LDS twiddle stage
 // Samples at tau >= cnt and frequencies >= nf are zero; points >= nsub are
 // computed (the row pitch is padded) but not stored.
 template <int MT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     k_dft_mfma(Geometry g, const float* __restrict__ stage, const float2* __restrict__ tw, int n0,
                int cnt, int first, int r0, float2* __restrict__ ghat) {
   constexpr int MP = 16 * MT;
@@ -368,7 +368,12 @@ __global__ void __launch_bounds__(256)
   const int r = blockIdx.y;
   const int col = blockIdx.x * 256 + wave * 64 + 4 * (lane & 15);  // this lane's 4 grid points
   const int krow = lane >> 4;
-  const float* S = stage + (size_t)r * g.chunk * g.nsub_p;
+  // staged samples through a buffer resource that covers the cnt valid rows:
+  // rows at or past cnt read as zero, and the row offset is a scalar
+  const __amdgpu_buffer_rsrc_t rs =
+      make_rsrc(stage + (size_t)r * g.chunk * g.nsub_p, (size_t)cnt * g.nsub_p * sizeof(float));
+  const int pitch = g.nsub_p * 4;
+  const int voff = krow * pitch + col * 4;
   floatx4 acc[MT][4];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
@@ -379,11 +384,8 @@ __global__ void __launch_bounds__(256)
   // current one is loaded before the current group's MFMAs are issued
   auto load_b = [&](floatx4* b, int k16) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int tau = k16 + 4 * u + krow;
-      b[u] = floatx4{0.f, 0.f, 0.f, 0.f};
-      if (tau < cnt) b[u] = *reinterpret_cast<const floatx4*>(S + (size_t)tau * g.nsub_p + col);
-    }
+    for (int u = 0; u < 4; ++u)
+      b[u] = __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, (k16 + 4 * u) * pitch, 0));
   };
   const int ngrp = (cnt + 15) / 16;
   floatx4 b[2][4];
