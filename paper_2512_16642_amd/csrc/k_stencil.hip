@@ -354,8 +354,10 @@ constexpr int kDftKs = 64;  // time samples per LDS twiddle stage
 // <-> grid point 4i + j) so each lane loads its four B values with one float4.
 // Samples at tau >= cnt and frequencies >= nf are zero; points >= nsub are
 // computed (the row pitch is padded) but not stored.
+// occupancy target: the most waves per SIMD whose registers hold the MT x 4
+// accumulator tiles without spilling
 template <int MT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT <= 4 ? 4 : MT <= 6 ? 3 : 2)))
     k_dft_mfma(Geometry g, const float* __restrict__ stage, const float2* __restrict__ tw, int n0,
                int cnt, int first, int r0, float2* __restrict__ ghat) {
   constexpr int MP = 16 * MT;
