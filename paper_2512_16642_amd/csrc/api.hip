@@ -423,6 +423,10 @@ ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev) {
   const bool two = g.windows == 2;
   hipStream_t dst = two ? s->side : st;
   bool pending[2] = {false, false};
+  // the finite-record contraction reads whole 32-point blocks of staged samples;
+  // the tail of the last block lies in the row padding, which must hold zeros
+  if (g.weighting == EHI_WEIGHT_FINITE_RECORD)
+    EHI_TRY(ehi::launch_zero_stage_tails(g, s->ptr<float>(L.stage), st), "staging padding");
   auto free_window = [&](int b) -> hipError_t {
     if (!two || !pending[b]) return hipSuccess;
     pending[b] = false;

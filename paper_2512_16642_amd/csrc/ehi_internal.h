@@ -186,6 +186,8 @@ hipError_t launch_vmax(const float* vel, int n, uint32_t* out_bits, hipStream_t 
 hipError_t launch_coefficients(const Geometry& g, const float* vel, const uint32_t* vmax_bits,
                                float* ca, float* bd, hipStream_t st);
 hipError_t launch_twiddles(const Geometry& g, const double* freq, float2* tw, hipStream_t st);
+// zero the row padding [nsub, nsub_p) of every staging slot of every window
+hipError_t launch_zero_stage_tails(const Geometry& g, float* stage, hipStream_t st);
 hipError_t launch_wave_init(const Geometry& g, const float* vel, const int32_t* rec, int r0,
                             int nrb_now, float* u0, float* w0, float* stage, hipStream_t st);
 int march_bands(const Geometry& g);

@@ -117,6 +117,22 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
+// hi/lo split of two FP32 values into packed BF16 pairs (element 0 in the low
+// half): hi = bf16(x) (round to nearest even), lo = bf16(x - hi).  The hi pair
+// is converted once and its two halves widened back to FP32 by a byte permute
+// and a mask, so every value costs one half of each conversion (used where the
+// split sits on the per-step path of the finite-record contraction; the
+// once-per-stage splits of the final-spectrum forms keep the plain expression,
+// which holds fewer registers there).
+__device__ __forceinline__ void split_pair(float x0, float x1, unsigned& hi, unsigned& lo) {
+  hi = __builtin_bit_cast(unsigned, bf16x2{(__bf16)x0, (__bf16)x1});
+  // low half moved up by a byte permute (the compiler would otherwise convert
+  // x0 a second time to widen it)
+  const float h0 = __uint_as_float(__builtin_amdgcn_perm(0u, hi, 0x01000c0cu));
+  const float h1 = __uint_as_float(hi & 0xffff0000u);
+  lo = __builtin_bit_cast(unsigned, bf16x2{(__bf16)(x0 - h0), (__bf16)(x1 - h1)});
+}
+
 constexpr int kBt = 64;  // H tile (rows = cols)
 constexpr int kBk = 32;  // grid points per stage (four groups of 8)
 constexpr int kXcd = 8;  // XCDs per device
@@ -544,6 +560,10 @@ __global__ void __launch_bounds__(256)
         q[u][1] = *reinterpret_cast<const floatx4*>(src + 4);
       }
     };
+    // No sample is masked: partitions end on 32-point block boundaries except
+    // the last, whose tail lies in the row padding of the staging buffer, which
+    // holds zeros; rows at or beyond nr run on row 0's samples and their entries
+    // are not stored.
     auto step = [&](int t, const floatx4 (&q)[4][2]) {
       const float2 w = tw[(size_t)(n0 - 1 + t) * g.nf + f];
       bf16x8 fr4[4][4];  // [row][plane]
@@ -554,21 +574,15 @@ __global__ void __launch_bounds__(256)
         unsigned wd[4][4];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const float x = (rv[u] && kx + e < k1) ? gv[e] : 0.f;
+          const float x = gv[e];
           S[u][e].x = fmaf(w.x, x, S[u][e].x);
           S[u][e].y = fmaf(w.y, x, S[u][e].y);
         }
 #pragma unroll
         for (int e = 0; e < 8; e += 2) {
           const float2 z0 = S[u][e], z1 = S[u][e + 1];
-          const bf16x2 rh = {(__bf16)z0.x, (__bf16)z1.x};
-          const bf16x2 ih = {(__bf16)z0.y, (__bf16)z1.y};
-          const bf16x2 rl = {(__bf16)(z0.x - (float)rh[0]), (__bf16)(z1.x - (float)rh[1])};
-          const bf16x2 il = {(__bf16)(z0.y - (float)ih[0]), (__bf16)(z1.y - (float)ih[1])};
-          wd[0][e >> 1] = __builtin_bit_cast(unsigned, rh);
-          wd[1][e >> 1] = __builtin_bit_cast(unsigned, rl);
-          wd[2][e >> 1] = __builtin_bit_cast(unsigned, ih);
-          wd[3][e >> 1] = __builtin_bit_cast(unsigned, il);
+          split_pair(z0.x, z1.x, wd[0][e >> 1], wd[1][e >> 1]);
+          split_pair(z0.y, z1.y, wd[2][e >> 1], wd[3][e >> 1]);
         }
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq)

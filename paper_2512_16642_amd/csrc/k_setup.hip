@@ -127,6 +127,14 @@ __global__ void k_zero_slot0(float* __restrict__ stage, size_t nsub, size_t pitc
   if (i < nsub && r < nrb) stage[(size_t)r * pitch + i] = 0.f;
 }
 
+// Zero the padding [used, pitch) of rows of a pitched buffer.
+__global__ void k_zero_row_tails(float* __restrict__ p, size_t rows, int used, int pitch) {
+  const size_t tail = (size_t)(pitch - used);
+  const size_t n = rows * tail;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[(i / tail) * pitch + used + i % tail] = 0.f;
+}
+
 __global__ void k_c128_from_c64(const float2* __restrict__ in, double2* __restrict__ out, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = make_double2((double)in[i].x, (double)in[i].y);
@@ -184,6 +192,16 @@ hipError_t launch_twiddles(const Geometry& g, const double* freq, float2* tw, hi
   size_t n = (size_t)g.nt * g.nf;
   hipLaunchKernelGGL(k_twiddles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g.nt, g.nf,
                      g.dt, freq, tw);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_stage_tails(const Geometry& g, float* stage, hipStream_t st) {
+  const int tail = g.nsub_p - g.nsub;
+  if (tail == 0) return hipSuccess;
+  const size_t rows = (size_t)g.windows * g.nrb * g.chunk;
+  const size_t n = rows * (size_t)tail;
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_zero_row_tails, dim3(blocks), dim3(256), 0, st, stage, rows, g.nsub, g.nsub_p);
   return hipGetLastError();
 }
 
