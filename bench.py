@@ -43,8 +43,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="layered_1000x300",
                     help="layered_1000x300 (default), tiny, batch8 (the eight uneven surveys), serve "
-                         "(Poisson request mix over the eight surveys) or accuracy (the Hessian "
-                         "accuracy test on the 1000 x 300 survey)")
+                         "(Poisson request mix over the eight surveys), accuracy (the Hessian "
+                         "accuracy test on the 1000 x 300 survey) or randomized (one receiver per "
+                         "subset, factors reused over iterations, on the 1000 x 300 survey)")
     ap.add_argument("--batch-nt", type=int, default=4000, help="time steps of the batch8 surveys")
     ap.add_argument("--precision", default="split_bf16", choices=["split_bf16", "plain_fp32"])
     ap.add_argument("--weighting", default="long_record", choices=["long_record", "finite_record"],
@@ -61,6 +62,12 @@ def parse():
                     help="time samples per DFT staging window")
     ap.add_argument("--windows", type=int, default=1, choices=[1, 2],
                     help="staging windows (2: the DFT of one overlaps the stepping of the next)")
+    ap.add_argument("--keep", type=int, nargs=2, default=[0, 0], metavar=("KZ", "KX"),
+                    help="contract the leading KZ x KX 2D DCT-II coefficients of the subgrid "
+                         "instead of the grid points (0 0: no transform)")
+    ap.add_argument("--subsets", type=int, default=100, help="randomized: receiver subsets (receivers kept)")
+    ap.add_argument("--reuse", type=int, default=5, help="randomized: iterations per selection")
+    ap.add_argument("--iters", type=int, default=20, help="randomized: timed iterations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=300, help="FD steps in the CPU sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -249,6 +256,69 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def run_randomized(args):
+    """Randomized receivers with Hessian reuse on the 1000 x 300 survey: every
+    selection keeps one receiver drawn from each of ``--subsets`` contiguous
+    subsets, is built (Green functions, contraction, lambda_max, factor) once
+    and serves ``--reuse`` consecutive iterations; each iteration deblurs all
+    sources at all frequencies against the resident factors.  Reports seconds
+    per iteration (builds amortised), next to the build and reused-deblur times."""
+    import torch
+
+    import synth
+    from paper_2512_16642_amd import randomized
+
+    s = synth.layered_1000x300()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    vel = torch.from_numpy(s.velocity()).to(dev)
+    R = torch.from_numpy(s.residuals()).to(dev)
+    rh = randomized.RandomizedHessian(s, args.subsets, reuse=args.reuse, seed=2024, max_ns=s.ns)
+    for it in range(args.reuse):  # warm-up: one selection and its reuses
+        rh.deblur(it, vel, R)
+    torch.cuda.synchronize()
+    print("# warmup done", file=sys.stderr, flush=True)
+    t_build, t_reuse, n_build, n_reuse = 0.0, 0.0, 0, 0
+    t0 = time.perf_counter()
+    base = args.reuse  # start on a fresh selection
+    for it in range(base, base + args.iters):
+        b0 = rh.builds
+        ta = time.perf_counter()
+        _, X = rh.deblur(it, vel, R)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - ta
+        if rh.builds > b0:
+            t_build += dt
+            n_build += 1
+        else:
+            t_reuse += dt
+            n_reuse += 1
+    wall = time.perf_counter() - t0
+    rh.close()
+    out = {
+        "metric": "randomized receivers with Hessian reuse: s per iteration (selection builds amortised)",
+        "value": round(wall / args.iters, 6),
+        "unit": "s/iteration",
+        "n_gpus": 1,
+        "steps": args.iters,
+        "warmup": args.reuse,
+        "ms_per_step": round(wall / args.iters * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{s.name}-randomized-{args.subsets}of{s.nr}", "subsets": args.subsets,
+                   "reuse": args.reuse, "nt": s.nt, "nf": s.nf, "ns": s.ns, "precision": "split_bf16"},
+        "build_s": round(t_build / max(n_build, 1), 4),
+        "builds": n_build,
+        "reused_deblur_ms": round(t_reuse / max(n_reuse, 1) * 1e3, 3),
+        "reused_iterations": n_reuse,
+        "solves_per_s_reused": round(s.nf * s.ns / (t_reuse / max(n_reuse, 1)), 1) if n_reuse else None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_accuracy(args):
     """The Hessian accuracy test on the 1000 x 300 layered survey: frequencies
     moved to the nearest bins of the 2nt-point transform, factors of the
@@ -391,11 +461,12 @@ def run_accuracy(args):
 
 def main():
     args = parse()
-    if args.workload in ("batch8", "serve", "accuracy"):
+    if args.workload in ("batch8", "serve", "accuracy", "randomized"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        {"batch8": run_batch, "serve": run_serve, "accuracy": run_accuracy}[args.workload](args)
+        {"batch8": run_batch, "serve": run_serve, "accuracy": run_accuracy,
+         "randomized": run_randomized}[args.workload](args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
@@ -420,8 +491,9 @@ def main():
     vel = torch.from_numpy(s.velocity()).to(dev)
     R = torch.from_numpy(s.residuals()).to(dev)
     X = torch.empty_like(R)
+    keep = tuple(args.keep)
     sv = ehi.survey_from(s, precision=args.precision, max_ns=s.ns, nr_batch=args.nr_batch,
-                         weighting=args.weighting, chunk=args.chunk, windows=args.windows)
+                         weighting=args.weighting, chunk=args.chunk, windows=args.windows, keep=keep)
     print(f"# workload {s.name} precision {args.precision} workspace {sv.workspace_bytes / 1e9:.2f} GB",
           file=sys.stderr, flush=True)
 
@@ -498,6 +570,10 @@ def main():
     # times the final-spectrum contraction
     rep = s.nt if args.weighting == "finite_record" else 1
     herk_flops = costs.herk_flops_per_survey(s.nz, s.nx, s.stride, s.nr, s.nf) * rep
+    compressed = keep[0] > 0 and keep[1] > 0
+    if compressed:
+        # the contraction runs over the kept coefficients instead of the grid points
+        herk_flops *= keep[0] * keep[1] / s.nsub
     herk_ms = prof["herk"][0] / K
     # 32 x 32 block pairs in the whole-matrix contraction (up to 224 receivers,
     # final-spectrum form) and in the finite-record contraction, 64 x 64 tile
@@ -519,7 +595,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": s.name, "precision": args.precision, "weighting": args.weighting,
-                   "chunk": args.chunk, "windows": args.windows,
+                   "chunk": args.chunk, "windows": args.windows, "keep": list(keep),
                    "nz": s.nz, "nx": s.nx,
                    "nb": s.nb, "nr": s.nr, "nt": s.nt, "nf": s.nf, "ns": s.ns, "stride": s.stride,
                    "nr_batch": nrb},
@@ -531,7 +607,8 @@ def main():
         "herk_tflops": round(herk_flops / (herk_ms / 1e3) / 1e12, 2) if herk_ms > 0 else None,
         "herk_mfma_bf16_tflops": (round(costs.herk_bf16_mfma_flops_per_survey(s.nr, s.nsub, s.nf, herk_tile) * rep
                                         / (herk_ms / 1e3) / 1e12, 1)
-                                  if herk_ms > 0 and args.precision == "split_bf16" else None),
+                                  if herk_ms > 0 and args.precision == "split_bf16" and not compressed
+                                  else None),
         "dft_gbs": round(dft_bytes / (dft_ms / 1e3) / 1e9, 1) if dft_ms > 0 else None,
         "dft_tflops": round(dft_flops / (dft_ms / 1e3) / 1e12, 2) if dft_ms > 0 else None,
         "roofline": roof,
