@@ -396,16 +396,27 @@ __global__ void __launch_bounds__(512)
   };
 
   const int nst = cdiv(k1 - k0, kBk);
+  // waves w and w + 4 share a SIMD: the first four split the next stage before
+  // their products and the other four after theirs, so one wave's conversions
+  // run beside the other's matrix products.  The early waves load two stages
+  // ahead (their split comes first, so its data must already be in flight).
+  const bool early = wave < 4;
   if (nst > 0) {
     gload(k0);
     lstore(0);
+    if (early && nst > 1) gload(k0 + kBk);
   }
   __syncthreads();
   const int fr = lane & 15, fg = lane >> 4;
   const u32x4 sgn = u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
   for (int st = 0; st < nst; ++st) {
     const int buf = st & 1;
-    if (st + 1 < nst) gload(k0 + (st + 1) * kBk);
+    if (early) {
+      if (st + 1 < nst) lstore(buf ^ 1);
+      if (st + 2 < nst) gload(k0 + (st + 2) * kBk);
+    } else if (st + 1 < nst) {
+      gload(k0 + (st + 1) * kBk);
+    }
     bf16x8 ai[2][4], aj[2][4];
 #pragma unroll
     for (int m = 0; m < kWholePairs; ++m) {
@@ -445,7 +456,7 @@ __global__ void __launch_bounds__(512)
         }
       }
     }
-    if (st + 1 < nst) lstore(buf ^ 1);
+    if (!early && st + 1 < nst) lstore(buf ^ 1);
     __syncthreads();
   }
   float2* out = hpart + ((size_t)ks * g.nf + f) * g.nr * g.nr;
