@@ -11,7 +11,10 @@
 // every solve is a dense batched product over (row tile, source tile,
 // frequency) with no sequential dependency between rows.  In the split-BF16
 // precision mode two refinement steps follow: r = R - Qhat X in FP64 (X kept in
-// FP64), X += M^H (M r) in FP32.
+// FP64), X += M^H (M r) in FP32.  These products run on the matrix cores
+// (k_cgemm_mfma); k_cgemm, the same tiling on FMAs with a choice of B layout
+// and of the summation type, serves the DCT passes and the compressed
+// contraction.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -153,7 +156,7 @@ __global__ void __launch_bounds__(256) k_tri_inv_cols(const FactorJob* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Batched complex products, one batch entry (frequency) per blockIdx.z:
+// Batched complex products on FMAs, one batch entry (frequency) per blockIdx.z:
 //   C(i, j) = sum_{k < kdim} op(A)(i, k) B(k, j),  i < n, j < ns
 // A (arows rows, row-major): MODE 0: A itself (Qhat, or a transform matrix);
 // MODE 1: M (lower, np x np); MODE 2: M^H, i.e. A(i, k) = conj(M(k, i)); MODE 3:
