@@ -616,6 +616,18 @@ def main():
         "dft_tflops": round(dft_flops / (dft_ms / 1e3) / 1e12, 2) if dft_ms > 0 else None,
         "roofline": roof,
     }
+    # the two other hot kernels against their own peaks (the contraction on the
+    # BF16 matrix cores; the DFT on the FP32 matrix cores, its bytes beside)
+    herk_exec = out["herk_mfma_bf16_tflops"]
+    if herk_exec is not None:
+        out["roofline_herk"] = {"kernel": "k_herk_bf16_whole" if whole else "k_herk_bf16", "bound": "mfma",
+                                "achieved": herk_exec, "peak": 2500.0, "unit": "TFLOP/s",
+                                "frac": round(herk_exec / 2500.0, 4)}
+    if dft_ms > 0:
+        dft_tf = dft_flops / (dft_ms / 1e3) / 1e12
+        out["roofline_dft"] = {"kernel": "k_dft_mfma", "bound": "mfma", "achieved": round(dft_tf, 2),
+                               "peak": 157.3, "unit": "TFLOP/s", "frac": round(dft_tf / 157.3, 4),
+                               "hbm_frac": round(dft_bytes / (dft_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
     if not args.no_cpu_baseline:
         print("# timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_steps, args.cpu_hessians)
