@@ -5,8 +5,8 @@
 // block-diagonal frequency system is inverted and stored (frequency-domain
 // inversion; last step of the Fourier block-diagonal Hessian algorithm).  The
 // inverse is applied through a Cholesky factor Qhat = L L^H computed once and
-// kept resident.  One workgroup factors one frequency (right-looking, column by
-// column, trailing update spread over the workgroup).
+// kept resident.  One workgroup factors one frequency (left-looking, column by
+// column, each row's new entry one dot product).
 #include <hip/hip_runtime.h>
 
 #include "ehi_internal.h"
@@ -30,48 +30,76 @@ struct cplx<float> {
 // In-place lower Cholesky of A (n x n, row-major, complex).  Reads the lower
 // triangle, leaves L there and zeros above.  status[f] = 0 on success, 1 if a
 // pivot is not positive and finite.
+// Left-looking, one column at a time: row j's finished part L[j][0..j) is
+// staged in LDS, the pivot is d = A[j][j] - sum_k |L[j][k]|^2 (a workgroup
+// reduction), and every row i > j forms L[i][j] = (A[i][j] - sum_k L[i][k]
+// conj(L[j][k])) / L[j][j] as one dot product over its own finished entries
+// (one to eight lanes per row), so each column costs two barriers and no
+// element is rewritten by later columns.
 template <class R>
 __device__ void chol_inplace(typename cplx<R>::T* A, int n, int32_t* status_f) {
   using C = typename cplx<R>::T;
+  constexpr int kMaxN = 1024;  // the largest nr the descriptor accepts
+  __shared__ C lj[kMaxN];
+  __shared__ R red[256 / 64];
   __shared__ int bad;
   __shared__ R piv;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
+  for (int j = 0; j < n && n <= kMaxN; ++j) {
+    R part = R(0);
+    for (int k = threadIdx.x; k < j; k += blockDim.x) {
+      const C v = A[(size_t)j * n + k];
+      lj[k] = v;
+      part += v.x * v.x + v.y * v.y;
+    }
+    // workgroup sum of |L[j][k]|^2
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+    __syncthreads();
     if (threadIdx.x == 0) {
-      R d = A[(size_t)k * n + k].x;
+      R sum = R(0);
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += red[w];
+      const R d = A[(size_t)j * n + j].x - sum;
       if (!(d > R(0)) || !isfinite(d)) {
         bad = 1;
       } else {
         piv = sqrt(d);
-        A[(size_t)k * n + k] = cplx<R>::make(piv, R(0));
+        A[(size_t)j * n + j] = cplx<R>::make(piv, R(0));
       }
     }
     __syncthreads();
     if (bad) break;
-    R inv = R(1) / piv;
-    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) {
-      C a = A[(size_t)i * n + k];
-      A[(size_t)i * n + k] = cplx<R>::make(a.x * inv, a.y * inv);
-    }
-    __syncthreads();
-    // trailing update of the lower triangle: A[i][j] -= A[i][k] conj(A[j][k]), k < j <= i
-    const int m = n - k - 1;
-    const int mm = m * m;
-    for (int p = threadIdx.x; p < mm; p += blockDim.x) {
-      int ii = p / m, jj = p % m;
-      if (jj > ii) continue;
-      int i = k + 1 + ii, j = k + 1 + jj;
-      C lik = A[(size_t)i * n + k], ljk = A[(size_t)j * n + k];
-      C a = A[(size_t)i * n + j];
-      // lik * conj(ljk)
-      R pr = lik.x * ljk.x + lik.y * ljk.y;
-      R pim = lik.y * ljk.x - lik.x * ljk.y;
-      A[(size_t)i * n + j] = cplx<R>::make(a.x - pr, a.y - pim);
+    const R inv = R(1) / piv;
+    // g lanes per row (more lanes as fewer rows remain, so the workgroup stays
+    // busy through the long dot products of the last columns), each summing
+    // every g-th k, then a butterfly over the g lanes
+    const int rows = n - j - 1;
+    const int g = rows <= 32 ? 8 : rows <= 64 ? 4 : rows <= 128 ? 2 : 1;
+    const int rg = (int)threadIdx.x & (g - 1);
+    for (int i0 = j + 1; i0 < n; i0 += (int)blockDim.x / g) {
+      const int i = i0 + (int)threadIdx.x / g;
+      const bool live = i < n;
+      const C* Ai = A + (size_t)(live ? i : j) * n;
+      R sr = R(0), si = R(0);
+      for (int k = rg; k < j; k += g) {
+        const C a = Ai[k], b = lj[k];
+        // a * conj(b)
+        sr += a.x * b.x + a.y * b.y;
+        si += a.y * b.x - a.x * b.y;
+      }
+      for (int o = 1; o < g; o <<= 1) {
+        sr += __shfl_xor(sr, o);
+        si += __shfl_xor(si, o);
+      }
+      if (live && rg == 0) {
+        const C a = Ai[j];
+        A[(size_t)i * n + j] = cplx<R>::make((a.x - sr) * inv, (a.y - si) * inv);
+      }
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) *status_f = bad;
+  if (threadIdx.x == 0) *status_f = (bad || n > kMaxN) ? 1 : 0;
   __syncthreads();
   // zero the strict upper triangle
   for (long long e = threadIdx.x; e < (long long)n * n; e += blockDim.x) {
