@@ -75,7 +75,7 @@ __device__ void chol_inplace(typename cplx<R>::T* A, int n, int32_t* status_f) {
     // busy through the long dot products of the last columns), each summing
     // every g-th k, then a butterfly over the g lanes
     const int rows = n - j - 1;
-    const int g = rows <= 32 ? 8 : rows <= 64 ? 4 : rows <= 128 ? 2 : 1;
+    const int g = rows <= 8 ? 32 : rows <= 16 ? 16 : rows <= 32 ? 8 : rows <= 64 ? 4 : rows <= 128 ? 2 : 1;
     const int rg = (int)threadIdx.x & (g - 1);
     for (int i0 = j + 1; i0 < n; i0 += (int)blockDim.x / g) {
       const int i = i0 + (int)threadIdx.x / g;
