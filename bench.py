@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # precision, time levels, segment rows, band width, receivers per launch); recorded in
 # profiles/survey_layered-1000x300_pmc.md.  Any other shape reports null.
 MEASURED_TRAFFIC = {
-    ("layered-1000x300-nr200-nt4000-nf30-ns200", "split_bf16", 8, 128, 256, 200): (455088.0 * 2 + 1152008.0) * 1024,
+    ("layered-1000x300-nr200-nt4000-nf30-ns200", "split_bf16", 8, 256, 256, 200): (417499.0 * 2 + 1150910.0) * 1024,
 }
 
 

@@ -127,7 +127,7 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   int kmax = std::max(1, g.nsub / 1024);
   g.herk_split = std::max(1, std::min(want, std::min(ehi::kHerkSplitMax, kmax)));
   g.tblock = 8;
-  g.seg_rows = 128;
+  g.seg_rows = 256;  // measured best for the 1000 x 300 benchmark grid (1-2 % over 128)
   // tuning overrides (launch shapes only; results do not depend on them)
   if (const char* e = std::getenv("EHI_TBLOCK")) {
     int v = std::atoi(e);
