@@ -490,59 +490,67 @@ hipError_t run_gemm_mfma(const GemmArgs& a, int nf, hipStream_t st) {
 }
 
 // Largest eigenvalue of each Hhat(w) by power iteration in FP64 (one workgroup
-// per frequency), Rayleigh quotient of the final vector.
+// per frequency), Rayleigh quotient of the final vector.  Eight lanes per row
+// (coalesced 128-byte reads of Hhat), and per iteration one workgroup
+// reduction of |y|^2, Re(v^H y) and |v|^2 together (wave butterflies, one
+// LDS slot per wave).
 __global__ void __launch_bounds__(256)
     k_power(Geometry g, const double2* __restrict__ hhat, double* __restrict__ eig, int iters) {
   extern __shared__ double2 sv[];  // v[n], y[n]
-  __shared__ double red[256];
+  __shared__ double red[3][256 / 64];
   const int f = blockIdx.x;
   const int n = g.nr;
   const double2* H = hhat + (size_t)f * n * n;
   double2* v = sv;
   double2* y = sv + n;
+  const int r8 = threadIdx.x & 7;
+  const int nw = (int)(blockDim.x >> 6);
   for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = make_double2(1.0 + 0.25 * sin(1.0 + i), 0.0);
   __syncthreads();
   double lam = 0.0;
   for (int it = 0; it <= iters; ++it) {
-    double part = 0.0, rq = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double part = 0.0, rq = 0.0, vn = 0.0;
+    for (int i0 = 0; i0 < n; i0 += (int)(blockDim.x >> 3)) {
+      const int i = i0 + (int)(threadIdx.x >> 3);
+      const bool live = i < n;
+      const double2* Hi = H + (size_t)(live ? i : 0) * n;
       double tr = 0.0, ti = 0.0;
-      for (int j = 0; j < n; ++j) {
-        double2 h = H[(size_t)i * n + j], x = v[j];
+      for (int j = r8; j < n; j += 8) {
+        const double2 h = Hi[j], x = v[j];
         tr += h.x * x.x - h.y * x.y;
         ti += h.x * x.y + h.y * x.x;
       }
-      y[i] = make_double2(tr, ti);
-      part += tr * tr + ti * ti;
-      rq += v[i].x * tr + v[i].y * ti;  // Re(conj(v_i) y_i)
+      for (int o = 1; o < 8; o <<= 1) {
+        tr += __shfl_xor(tr, o);
+        ti += __shfl_xor(ti, o);
+      }
+      if (live && r8 == 0) {
+        y[i] = make_double2(tr, ti);
+        part += tr * tr + ti * ti;
+        rq += v[i].x * tr + v[i].y * ti;  // Re(conj(v_i) y_i)
+        vn += v[i].x * v[i].x + v[i].y * v[i].y;
+      }
     }
-    red[threadIdx.x] = part;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) {
+      part += __shfl_xor(part, o);
+      rq += __shfl_xor(rq, o);
+      vn += __shfl_xor(vn, o);
     }
-    double ny = sqrt(red[0]);
-    __syncthreads();
-    red[threadIdx.x] = rq;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+      red[0][threadIdx.x >> 6] = part;
+      red[1][threadIdx.x >> 6] = rq;
+      red[2][threadIdx.x >> 6] = vn;
     }
-    double vv_rq = red[0];
     __syncthreads();
+    double ys = 0.0, q = 0.0, vs = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      ys += red[0][w];
+      q += red[1][w];
+      vs += red[2][w];
+    }
+    const double ny = sqrt(ys);
     // normalise v's norm into the quotient
-    double vn = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) vn += v[i].x * v[i].x + v[i].y * v[i].y;
-    red[threadIdx.x] = vn;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    lam = vv_rq / red[0];
-    __syncthreads();
+    lam = q / vs;
     if (ny == 0.0) break;
     for (int i = threadIdx.x; i < n; i += blockDim.x) v[i] = make_double2(y[i].x / ny, y[i].y / ny);
     __syncthreads();
