@@ -473,7 +473,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
-              "described in DESIGN.md and not benchmarked", file=sys.stderr)
+              "a design note and is not benchmarked", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

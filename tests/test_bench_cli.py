@@ -1,5 +1,5 @@
 """bench.py's command line on the CPU: the options parse, and more than one GPU
-is refused with a message (this build runs on one GPU)."""
+is refused with a message (the benchmark runs on one GPU)."""
 import os
 import subprocess
 import sys
