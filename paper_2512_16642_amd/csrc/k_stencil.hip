@@ -343,7 +343,7 @@ __global__ void __launch_bounds__(KB)
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kDftKs = 64;  // time samples per LDS twiddle stage
+constexpr int kDftKs = 128;  // time samples per LDS twiddle stage (40 KB at 64 rows: four workgroups per CU)
 
 // DFT of one staged chunk as a real matrix product on FP32 MFMA:
 //   C[m][x] = sum_tau A[m][tau] S[tau][x],  A[2f][tau] = Re tw, A[2f+1][tau] = Im tw,
