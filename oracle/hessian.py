@@ -113,7 +113,7 @@ def hessian_r1(ghat: np.ndarray) -> np.ndarray:
     """Hhat(w)[i][j] = sum_x ghat_i(w, x) conj(ghat_j(w, x)); ``ghat`` is
     ``[nf][nr][nsub]`` complex.  Returns ``[nf][nr][nr]`` complex128."""
     g = np.asarray(ghat, dtype=np.complex128)
-    return np.einsum("fix,fjx->fij", g, np.conj(g), optimize=True)
+    return np.stack([g[f] @ g[f].conj().T for f in range(g.shape[0])])
 
 
 def dct_matrix(n: int, keep: int) -> np.ndarray:

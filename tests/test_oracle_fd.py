@@ -145,3 +145,97 @@ def test_c_recurrence_matches_numpy():
         a = fd.green_samples(v, s.nb, s.h, s.dt, s.nt, s.rec_iz[:3], s.rec_ix[:3], s.stride)
         b = fd.green_samples_c(v, s.nb, s.h, s.dt, s.nt, s.rec_iz[:3], s.rec_ix[:3], s.stride)
         assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+
+
+# ---------------------------------------------------------------------------
+# the absorbing layer (reading of "appropriate boundary conditions"): a
+# quadratic damping profile eta(d) = eta_max (d/nb)^2 with
+# eta_max = 3 vmax ln(1000) / (2 nb h), entering the wave equation as the
+# centred term m eta du/dt, over an edge-replicated extension of the model
+# ---------------------------------------------------------------------------
+
+def _plane_wave_trace(vel, nb, h, dt, nt, src_row, rec_row, f0=25.0):
+    """Trace at the centre column of ``rec_row`` for a Ricker line source along
+    the whole padded row ``src_row`` (interior row indices): a plane wave
+    travelling up and down, away from the side layers."""
+    med = fd.Medium(vel, nb, h, dt)
+    w = synth.ricker(nt, dt, f0)
+    f = np.zeros((1,) + med.shape)
+    out = []
+
+    def inject(n):
+        f[0, src_row + nb, :] = w[n]
+        return f
+
+    cx = vel.shape[1] // 2 + nb
+    fd.propagate(med, nt, 1, inject, lambda n, u: out.append(u[0, rec_row + nb, cx]))
+    return np.array(out)
+
+
+def test_sponge_absorbs_as_the_damped_wave_equation_predicts():
+    # u_tt + eta u_t = v^2 lap u damps a wave travelling through the layer by
+    # exp(-int eta / (2 v) ds) (WKB, eta << w, eta slowly varying).  A plane
+    # wave going up into the top layer, reflected by the zero field beyond the
+    # grid and coming back therefore returns with
+    #   exp(-sum_{d=1}^{nb} eta(d) h / v)
+    # of its amplitude.  The record ends before the side layers' disturbance or
+    # the bottom layer's return reaches the receiver.  A wrong eta_max (say a
+    # dropped factor 3, or twice the damping) or a linear profile moves the
+    # ratio by a factor of 3 or more.
+    nz, nx, nb, h, dt, v0 = 150, 401, 40, 10.0, 1.0e-3, 2000.0
+    src_row, rec_row, nt = 40, 20, 1000
+    vel = np.full((nz, nx), v0, dtype=np.float32)
+    g = _plane_wave_trace(vel, nb, h, dt, nt, src_row, rec_row)
+    t = np.arange(1, nt + 1) * dt
+    t_inc = (src_row - rec_row) * h / v0
+    t_ret = t_inc + 2.0 * (rec_row + nb + 1) * h / v0      # the zero field starts one cell beyond the layer
+    inc = g[(t > t_inc - 0.02) & (t < t_inc + 0.15)]
+    ret = g[(t > t_ret - 0.02) & (t < t_ret + 0.15)]
+    ratio = np.ptp(ret) / np.ptp(inc)
+    eta_max = 3.0 * v0 * math.log(1000.0) / (2.0 * nb * h)
+    expected = math.exp(-sum(eta_max * (d / nb) ** 2 * h for d in range(1, nb + 1)) / v0)
+    print("returned / incident amplitude", ratio, "WKB", expected)
+    assert 0.75 * expected < ratio < 1.15 * expected
+
+
+def test_layer_carries_the_edge_velocity():
+    # v(z) = 2000 + 0.5 z in the interior; the layer above it must hold the top
+    # row's velocity, so the pulse that goes up through the layer to the zero
+    # field and back returns after 2 (int_0^{z_r} dz / v + (nb + 1) h / v(0)).
+    # Mirrored or ramped extensions change that delay by 12-16 ms.
+    nz, nx, nb, h, dt = 150, 401, 40, 10.0, 1.0e-3
+    src_row, rec_row, nt = 40, 20, 1150
+    grad = 0.5
+    z = np.arange(nz) * h
+    vel = np.ascontiguousarray(np.broadcast_to((2000.0 + grad * z)[:, None], (nz, nx)), dtype=np.float32)
+    g = _plane_wave_trace(vel, nb, h, dt, nt, src_row, rec_row)
+    t = np.arange(1, nt + 1) * dt
+    v = lambda zz: 2000.0 + grad * zz
+    t_inc = math.log(v(src_row * h) / v(rec_row * h)) / grad
+    delay = 2.0 * (math.log(v(rec_row * h) / v(0.0)) / grad + (nb + 1) * h / v(0.0))
+    inc = np.where((t > t_inc - 0.02) & (t < t_inc + 0.15), g, 0.0)
+    ret = np.where((t > t_inc + delay - 0.02) & (t < t_inc + delay + 0.15), g, 0.0)
+    # the zero field inverts the pulse: the returned pulse is the negative of a
+    # delayed copy of the incident one
+    cc = np.correlate(ret, inc, mode="full")
+    lag = (int(np.argmax(-cc)) - (nt - 1)) * dt
+    print("measured delay", lag, "travel time", delay)
+    assert abs(lag - delay) <= 7.0e-3
+
+
+def test_windowed_c_spectra_match_numpy():
+    # the C recurrence advanced window by window with the DFT of each window
+    # added to the running spectra equals the NumPy recurrence followed by the
+    # DFT of the whole record (windows of 64 with a partial last one)
+    if fd._core() is None:
+        pytest.skip("oracle/_fdcore.so not built")
+    for s in (synth.ragged(nt=157), synth.tiny().with_(nt=150)):
+        v = s.velocity()
+        ref = fd.green_dft(s, v, engine="numpy")
+        got = fd.green_dft_windowed(v, s.nb, s.h, s.dt, s.nt, s.rec_iz, s.rec_ix, s.freqs_hz,
+                                    s.stride, window=64)
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+        # receivers in groups of 2 (a ragged last group)
+        got = fd.green_dft_windowed(v, s.nb, s.h, s.dt, s.nt, s.rec_iz, s.rec_ix, s.freqs_hz,
+                                    s.stride, window=64, max_window_bytes=8 * 64 * s.nsub * 2)
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
