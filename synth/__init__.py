@@ -180,6 +180,24 @@ def residuals_device(nf: int, ns: int, nr: int, seed: int, device) -> "torch.Ten
     return torch.complex(z[0], z[1])
 
 
+def spectra(nf: int, nr: int, nsub: int, seed: int, decades: float = 4.0) -> np.ndarray:
+    """Seeded stand-in for Green-function spectra, complex64 ``[nf][nr][nsub]``:
+    per frequency U diag(s) V with U a random unitary nr x nr matrix (QR of a
+    complex Gaussian), s_k = 10^(-decades k / nr) and V complex Gaussian rows
+    scaled by 1/sqrt(nsub), so the Gram matrix of the rows spans about
+    2 * decades decades (the spread of a survey's low-frequency Hessians).
+    Draw order per frequency: the Gaussian for U (real, imaginary), then V."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((nf, nr, nsub), dtype=np.complex64)
+    sv = 10.0 ** (-decades * np.arange(nr) / nr)
+    for f in range(nf):
+        a = rng.standard_normal((nr, nr)) + 1j * rng.standard_normal((nr, nr))
+        q, _ = np.linalg.qr(a)
+        v = (rng.standard_normal((nr, nsub)) + 1j * rng.standard_normal((nr, nsub))) / math.sqrt(2.0 * nsub)
+        out[f] = ((q * sv[None, :]) @ v).astype(np.complex64)
+    return out
+
+
 def time_residuals(ns: int, nr: int, nt: int, seed: int) -> np.ndarray:
     """Time-domain data residuals ``[ns][nr][nt]`` float32, i.i.d. N(0, 1)."""
     rng = np.random.default_rng(seed)

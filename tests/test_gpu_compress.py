@@ -16,8 +16,7 @@ from oracle import fd, hessian, solve
 pytestmark = pytest.mark.gpu
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+from parity import check, rel  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -42,13 +41,12 @@ def test_compressed_hessian(ehi, case, keep):
     ref = hessian.hessian_compressed(G.astype(np.complex128), s.nzs, s.nxs, *keep)
     sv, H = _gpu_hessian(ehi, s, G, keep)
     sv.close()
-    errs = [rel(H[f], ref[f]) for f in range(s.nf)]
     full = hessian.hessian_r1(G.astype(np.complex128))
     approx = [rel(ref[f], full[f]) for f in range(s.nf)]
-    print(case, keep, "compressed Hhat rel err", errs, "| compression error of the method", approx)
-    assert max(errs) < 5e-7
+    print(case, keep, "compression error of the method", approx)
+    check(H, ref, 5e-7, 5e-7, 1e-6, f"{case} {keep} compressed Hhat")
     if keep == (s.nzs, s.nxs):
-        assert max(rel(H[f], full[f]) for f in range(s.nf)) < 5e-7
+        check(H, full, 5e-7, 5e-7, 1e-6, f"{case} all coefficients vs uncompressed Hhat")
 
 
 def test_compressed_end_to_end_plain_and_split(ehi):
@@ -63,6 +61,4 @@ def test_compressed_end_to_end_plain_and_split(ehi):
     sv.factor(mu)
     X = sv.apply_multipliers(torch.from_numpy(R).cuda()).cpu().numpy()
     sv.close()
-    errs = [rel(X[f], Xr[f]) for f in range(s.nf)]
-    print("compressed multipliers rel err", errs)
-    assert max(errs) < 1e-6
+    check(X, Xr, 1e-6, 1e-6, 2e-6, "compressed multipliers")

@@ -15,9 +15,7 @@ from oracle import fd, hessian, krylov
 pytestmark = pytest.mark.gpu
 
 
-def rel(a, b):
-    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+from parity import check, rel  # noqa: E402
 
 
 @pytest.fixture(scope="module")

@@ -17,8 +17,7 @@ from oracle import fd, hessian, solve
 pytestmark = pytest.mark.gpu
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+from parity import check, rel  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -48,11 +47,9 @@ def test_finite_record_hessian(ehi, case):
     ref = _oracle_r2(s, v)
     sv, H = _gpu_r2(ehi, s, v)
     sv.close()
-    errs = [rel(H[f], ref[f]) for f in range(s.nf)]
-    print(case, "finite-record Hhat rel err per freq", errs)
     for f in range(s.nf):
         np.testing.assert_array_equal(H[f], H[f].conj().T)
-    assert max(errs) < 5e-6
+    check(H, ref, 5e-6, 5e-6, 1e-5, f"{case} finite-record Hhat")
     # the weighting changes the result: it is not the final-spectrum Gram
     r1 = hessian.hessian_r1(fd.green_dft(s, v))
     assert min(rel(H[f], r1[f] / s.nt) for f in range(s.nf)) > 1e-3
@@ -69,9 +66,7 @@ def test_finite_record_end_to_end_tiny(ehi):
     sv.factor(mu)
     X = sv.apply_multipliers(torch.from_numpy(R).cuda()).cpu().numpy()
     sv.close()
-    errs = [rel(X[f], Xr[f]) for f in range(s.nf)]
-    print("finite-record multipliers rel err per freq", errs, "Hhat", [rel(H[f], ref[f]) for f in range(s.nf)])
-    assert max(errs) < 1e-5
+    check(X, Xr, 1e-5, 1e-5, 2e-5, "finite-record multipliers")
 
 
 def test_finite_record_refuses_given_spectra(ehi):

@@ -14,6 +14,8 @@ import torch
 
 import synth
 
+from parity import check  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 
 
@@ -77,6 +79,4 @@ def test_one_served_request_matches_oracle(served):
     R = synth.residuals_device(s.nf, r.ns, s.nr, r.seed, "cuda").cpu().numpy().astype(np.complex128)
     Xr = solve.multipliers(H, mu, R)
     X = srv.results[r.rid].cpu().numpy()
-    err = max(np.linalg.norm(X[f] - Xr[f]) / np.linalg.norm(Xr[f]) for f in range(s.nf))
-    print("served request vs oracle: max rel err", err)
-    assert err < 1e-5
+    check(X, Xr, 1e-5, 1e-5, 2e-5, "served request vs oracle")

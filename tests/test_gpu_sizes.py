@@ -1,0 +1,91 @@
+"""Parity of the contraction and of the factor + solve at every receiver count
+the surveys use, from given inputs (the stage isolated from the stepping).
+
+Seeded spectra (synth.spectra: rows mixed by a random unitary matrix, singular
+values over four decades, so the Hessians' eigenvalues span eight) are loaded
+through ehi_load_green_dft; the Hessian comes back through ehi_copy_hessian and
+is compared with the oracle's FP64 contraction of the same complex64 values.
+The receiver counts cover every form of the kernel: one 32 x 32 block (16), a
+ragged block count (33), the whole-matrix split-BF16 form up to its limit (200,
+224) and the tile-pair form past it (225, 256, 400, the largest batch survey),
+in both precision modes.  The subgrid (61 x 203 = 12,383 points) spans several
+grid partitions and ends on a ragged tail.
+
+Factor + solve from a given Hessian (the oracle's FP64 Hhat of the same
+spectra, mu = 1e-3 lambda_max, so cond(Qhat) ~ 1e3 as in the surveys' low
+frequencies) at 200 and 400 receivers: the FP64 factor against scipy's, the
+multipliers of 64 sources against the oracle's solve.
+
+Tolerances as for the tiny survey (tests/test_gpu_parity.py): 2e-6 per
+frequency for the Hessian and the solve, 1e-12 for the FP64 factor; the
+element-wise and per-row measures of tests/parity.py beside them.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import hessian, solve
+from parity import check
+
+pytestmark = pytest.mark.gpu
+
+NZ, NX, NF = 61, 203, 3
+
+
+def _survey(nr, ns=64):
+    s = synth.ragged(nz=NZ, nx=NX, nb=4, nt=16, nr=1, stride=1)
+    return s.with_(rec_iz=tuple(k % 3 for k in range(nr)), rec_ix=tuple((7 * k) % NX for k in range(nr)),
+                   freqs_hz=(4.0, 7.5, 11.0)[:NF], ns=ns)
+
+
+@pytest.fixture(scope="module")
+def ehi():
+    from paper_2512_16642_amd import ehi as mod
+    mod.lib()
+    return mod
+
+
+_CACHE = {}
+
+
+def _spectra(nr):
+    if nr not in _CACHE:
+        G = synth.spectra(NF, nr, NZ * NX, seed=500 + nr)
+        _CACHE[nr] = (G, hessian.hessian_r1(G.astype(np.complex128)))
+    return _CACHE[nr]
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "plain_fp32"])
+@pytest.mark.parametrize("nr", [16, 33, 200, 224, 225, 256, 400])
+def test_hessian_from_given_spectra_sizes(ehi, nr, prec):
+    s = _survey(nr)
+    G, ref = _spectra(nr)
+    sv = ehi.survey_from(s, precision=prec, nr_batch=8)
+    sv.load_green_dft(torch.from_numpy(G.reshape(NF, nr, NZ, NX)).cuda())
+    sv.build_hessian()
+    H = sv.copy_hessian().cpu().numpy()
+    sv.close()
+    check(H, ref, 2e-6, 2e-6, 4e-6, f"nr={nr} {prec} hessian")
+    for f in range(NF):
+        np.testing.assert_array_equal(H[f], H[f].conj().T)
+        d = np.diagonal(H[f])
+        assert np.all(d.imag == 0) and np.all(d.real > 0)
+
+
+@pytest.mark.parametrize("nr", [33, 200, 400])
+def test_factor_and_solve_from_given_hessian_sizes(ehi, nr):
+    s = _survey(nr)
+    _, H = _spectra(nr)
+    mu = 1e-3 * solve.lambda_max(H)
+    R = synth.residuals(NF, s.ns, nr, seed=900 + nr)
+    L = solve.cholesky(solve.penalize(H, mu))
+    X = solve.solve(L, R.astype(np.complex128))
+    sv = ehi.survey_from(s, precision="split_bf16", nr_batch=8)
+    sv.load_hessian(torch.from_numpy(H).cuda())
+    sv.factor(mu)
+    Lg = sv.copy_factor().cpu().numpy()
+    Xg = sv.apply_multipliers(torch.from_numpy(R).cuda()).cpu().numpy()
+    sv.close()
+    check(Lg, L, 1e-12, 1e-12, 1e-11, f"nr={nr} FP64 factor")
+    check(Xg, X, 2e-6, 2e-6, 4e-6, f"nr={nr} solve")

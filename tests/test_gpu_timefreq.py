@@ -17,9 +17,7 @@ from oracle import fd, hessian, solve, timefreq
 pytestmark = pytest.mark.gpu
 
 
-def rel(a, b):
-    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+from parity import check, rel  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -50,9 +48,8 @@ def test_forward_subgrid_matches_oracle(ehi):
     d = sv.forward_subgrid(torch.from_numpy(f).cuda()).cpu().numpy()
     sv.close()
     op = _op(s)
-    errs = [rel(d[k], op.apply(f[k].astype(np.float64))) for k in range(3)]
-    print("forward S rel err", errs)
-    assert max(errs) < 2e-6
+    ref = np.stack([op.apply(f[k].astype(np.float64)) for k in range(3)])
+    check(d, ref, 2e-6, 2e-6, 4e-6, "forward S")
 
 
 def test_backpropagate_matches_oracle(ehi):
@@ -62,9 +59,8 @@ def test_backpropagate_matches_oracle(ehi):
     db = sv.backpropagate(torch.from_numpy(x).cuda()).cpu().numpy()
     sv.close()
     op = _op(s)
-    errs = [rel(db[k].reshape(s.nt, -1), op.adjoint(x[k].astype(np.float64))) for k in range(3)]
-    print("adjoint S^T rel err", errs)
-    assert max(errs) < 2e-6
+    ref = np.stack([op.adjoint(x[k].astype(np.float64)) for k in range(3)])
+    check(db.reshape(ref.shape), ref, 2e-6, 2e-6, None, "adjoint S^T")
 
 
 def test_modelling_needs_a_medium(ehi):
@@ -84,9 +80,7 @@ def test_residual_spectra_match_oracle(ehi, case):
     R = sv.residual_spectra(torch.from_numpy(dd).cuda()).cpu().numpy()
     sv.close()
     ref = timefreq.residual_spectra(dd, s.freqs_hz, s.dt)
-    errs = [rel(R[f], ref[f]) for f in range(s.nf)]
-    print(case, "residual spectra rel err", errs)
-    assert max(errs) < 3e-7
+    check(R, ref, 3e-7, 3e-7, 6e-7, f"{case} residual spectra")
 
 
 def test_inverse_transform_matches_oracle(ehi):
@@ -98,9 +92,7 @@ def test_inverse_transform_matches_oracle(ehi):
     x = sv.multipliers_to_time(torch.from_numpy(X).cuda()).cpu().numpy()
     sv.close()
     ref = timefreq.to_time(X.astype(np.complex128), s.freqs_hz, s.dt, s.nt)
-    err = rel(x, ref)
-    print("inverse transform rel err", err)
-    assert err < 3e-7
+    check(x, ref, 3e-7, 3e-7, 6e-7, "inverse transform")
 
 
 def test_inverse_transform_rejects_off_bin_frequencies(ehi):
@@ -171,6 +163,11 @@ def test_accuracy_test_matches_oracle(ehi):
     print("accuracy test vs oracle:", e, "| RelErr", out[4], "oracle", relerr_r)
     assert e["dde"] < 1e-6 and e["db"] < 5e-6 and e["pred"] < 5e-6
     assert e["err"] < 5e-6 and e["relerr"] < 1e-6
+    # element-wise beside the norms (per source)
+    check(out[0], dde_r, 1e-6, 1e-6, None, "accuracy test: multipliers in time")
+    check(out[1].reshape(db_r.shape), db_r, 5e-6, 5e-6, None, "accuracy test: source extension")
+    check(out[2], pred_r, 5e-6, 5e-6, None, "accuracy test: prediction")
+    check(out[3], err_r, 5e-6, 5e-6, None, "accuracy test: data error")
 
 
 @pytest.mark.parametrize("case", ["shared_cell", "four_levels"])
@@ -189,10 +186,10 @@ def test_single_level_fallback_matches_oracle(ehi, case):
     db = sv.backpropagate(torch.from_numpy(x).cuda()).cpu().numpy()
     sv.close()
     op = _op(s)
-    ef = [rel(d[k], op.apply(f[k].astype(np.float64))) for k in range(2)]
-    eb = [rel(db[k].reshape(s.nt, -1), op.adjoint(x[k].astype(np.float64))) for k in range(2)]
-    print(case, "fallback S", ef, "S^T", eb)
-    assert max(ef) < 2e-6 and max(eb) < 2e-6
+    ref_f = np.stack([op.apply(f[k].astype(np.float64)) for k in range(2)])
+    ref_b = np.stack([op.adjoint(x[k].astype(np.float64)) for k in range(2)])
+    check(d, ref_f, 2e-6, 2e-6, 4e-6, f"{case} fallback S")
+    check(db.reshape(ref_b.shape), ref_b, 2e-6, 2e-6, None, f"{case} fallback S^T")
 
 
 def test_march_modelling_independent_of_launch_shape(ehi):
