@@ -31,6 +31,8 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE x 1 KiB, scales from a 1 GiB copy), keyed by (workload,
 # precision, time levels, segment rows, band width, receivers per launch); recorded in
 # profiles/survey_layered-1000x300_pmc.md.  Any other shape reports null.
+TRAFFIC_SOURCE = ("not measured in this run: the counters of a separate rocprofv3 --pmc collection of "
+                  "the same launch shape, profiles/survey_layered-1000x300_pmc.md")
 MEASURED_TRAFFIC = {
     ("layered-1000x300-nr200-nt4000-nf30-ns200", "split_bf16", 8, 256, 256, 200): (417499.0 * 2 + 1150910.0) * 1024,
 }
@@ -69,7 +71,8 @@ def parse():
     ap.add_argument("--reuse", type=int, default=5, help="randomized: iterations per selection")
     ap.add_argument("--iters", type=int, default=20, help="randomized: timed iterations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=1500, help="FD steps in the CPU sample")
+    ap.add_argument("--cpu-steps", type=int, default=512, help="FD steps in the CPU sample")
+    ap.add_argument("--cpu-receivers", type=int, default=32, help="Green functions in the CPU sample")
     ap.add_argument("--cpu-hessians", type=int, default=3, help="full-size Hessians in the CPU sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (a known-size kernel "
@@ -77,8 +80,18 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(s, fd_steps, n_hess=1):
-    """Time the FP64 oracle on a bounded sample and scale it to one survey."""
+def cpu_baseline(s, fd_steps, n_hess=1, fd_receivers=32):
+    """Time the FP64 oracle on a bounded sample of the survey and scale it to one
+    survey, stage by stage, each on all the host threads it can use.
+
+    FD + DFT: the oracle's C recurrence (OpenMP over grid rows, all receivers of
+    the sample stepped together) with the DFT taken window by window as BLAS
+    matrix products, for ``fd_receivers`` Green functions over ``fd_steps``
+    steps on the full grid, scaled to nr receivers x nt steps (the cost is
+    linear in both).  Hessian: the FP64 contraction of ``n_hess`` frequencies
+    (multithreaded BLAS), scaled to nf.  Cholesky and the multi-source solve:
+    all frequencies at full size.
+    """
     import numpy as np
 
     from oracle import fd, hessian, solve
@@ -87,13 +100,13 @@ def cpu_baseline(s, fd_steps, n_hess=1):
         blas_threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
         blas_threads = os.cpu_count() or 1
+    fd_threads = fd.c_threads()
     v = s.velocity()
-    # FD + DFT of one Green function over fd_steps steps on the full grid
+    nrs = max(1, min(int(fd_receivers), s.nr))
     t0 = time.perf_counter()
-    gt = fd.green_samples(v, s.nb, s.h, s.dt, fd_steps, s.rec_iz[:1], s.rec_ix[:1], s.stride)
-    fd.dft(gt, s.freqs_hz, s.dt)
+    fd.green_dft_windowed(v, s.nb, s.h, s.dt, fd_steps, s.rec_iz[:nrs], s.rec_ix[:nrs], s.freqs_hz,
+                          s.stride)
     t_fd = time.perf_counter() - t0
-    del gt
     # n_hess frequencies' Hessians at full size from seeded spectra
     n_hess = max(1, min(int(n_hess), s.nf))
     rng = np.random.default_rng(0)
@@ -111,17 +124,26 @@ def cpu_baseline(s, fd_steps, n_hess=1):
     t0 = time.perf_counter()
     solve.solve(L, R)
     t_s = time.perf_counter() - t0
-    survey_s = t_fd / fd_steps * s.nt * s.nr + t_h * s.nf + t_c
+    fd_survey = t_fd * (s.nr / nrs) * (s.nt / fd_steps)
+    survey_s = fd_survey + t_h * s.nf + t_c
     return {
         "value": survey_s,
         "unit": "s/survey",
-        "cores": int(blas_threads),
+        "cores": int(max(fd_threads, blas_threads)),
         "kind": "oracle",
-        "sample": (f"FP64 numpy oracle: 1 Green function x {fd_steps} steps of FD+DFT on the full "
-                   f"grid ({t_fd:.2f} s), {n_hess} of {s.nf} Hessians at full size ({t_h * n_hess:.2f} s), all "
-                   f"{s.nf} Cholesky factorisations ({t_c:.2f} s); scaled to {s.nr} Green functions "
-                   f"x {s.nt} steps and {s.nf} Hessians. Multi-source solve {t_s:.3f} s "
-                   f"({s.nf * s.ns / t_s:.0f} solves/s)"),
+        "sample": (f"FP64 oracle: {nrs} Green functions x {fd_steps} steps of FD+DFT on the full grid "
+                   f"({t_fd:.2f} s, C recurrence on {fd_threads} OpenMP threads, DFT by BLAS on "
+                   f"{blas_threads} threads), {n_hess} of {s.nf} Hessians at full size ({t_h * n_hess:.2f} s, "
+                   f"BLAS on {blas_threads} threads), all {s.nf} Cholesky factorisations ({t_c:.2f} s); "
+                   f"scaled to {s.nr} Green functions x {s.nt} steps and {s.nf} Hessians. Multi-source "
+                   f"solve {t_s:.3f} s ({s.nf * s.ns / t_s:.0f} solves/s)"),
+        "stages": {
+            "fd_dft": {"s_per_survey": round(fd_survey, 2), "threads": int(fd_threads),
+                       "sampled_s": round(t_fd, 3)},
+            "hessian": {"s_per_survey": round(t_h * s.nf, 3), "threads": int(blas_threads)},
+            "cholesky": {"s_per_survey": round(t_c, 4), "threads": int(blas_threads)},
+            "solve": {"s": round(t_s, 4), "threads": int(blas_threads)},
+        },
         "solves_per_s": s.nf * s.ns / t_s,
     }
 
@@ -562,6 +584,7 @@ def main():
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": MEASURED_TRAFFIC.get((s.name, args.precision, tblock, seg_rows, band, nrb)),
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "traffic_source": TRAFFIC_SOURCE,
         "avg_launch_us": round(avg_step_s * 1e6, 2),
         "bytes_per_launch": round(bytes_launch),
         "bytes_per_cell_update": round(bpc, 4),
@@ -620,9 +643,16 @@ def main():
     # BF16 matrix cores; the DFT on the FP32 matrix cores, its bytes beside)
     herk_exec = out["herk_mfma_bf16_tflops"]
     if herk_exec is not None:
+        # the planning count: three BF16 products (hi.hi, hi.lo, lo.hi) per real
+        # product of the useful Hermitian contraction; the executed count
+        # (every product the kernel issues, lo.lo and block padding included)
+        # beside it
+        planned = 3.0 * herk_flops / (herk_ms / 1e3) / 1e12
         out["roofline_herk"] = {"kernel": "k_herk_bf16_whole" if whole else "k_herk_bf16", "bound": "mfma",
-                                "achieved": herk_exec, "peak": 2500.0, "unit": "TFLOP/s",
-                                "frac": round(herk_exec / 2500.0, 4)}
+                                "achieved": round(planned, 1), "peak": 2500.0, "unit": "TFLOP/s",
+                                "frac": round(planned / 2500.0, 4),
+                                "count": "3 BF16 products x useful Hermitian flops (8 nr(nr+1)/2 nsub nf)",
+                                "executed_tflops": herk_exec, "executed_frac": round(herk_exec / 2500.0, 4)}
     if dft_ms > 0:
         dft_tf = dft_flops / (dft_ms / 1e3) / 1e12
         out["roofline_dft"] = {"kernel": "k_dft_mfma", "bound": "mfma", "achieved": round(dft_tf, 2),
@@ -630,7 +660,7 @@ def main():
                                "hbm_frac": round(dft_bytes / (dft_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
     if not args.no_cpu_baseline:
         print("# timing the oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(s, args.cpu_steps, args.cpu_hessians)
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_steps, args.cpu_hessians, args.cpu_receivers)
     sv.close()
     print(json.dumps(out), flush=True)
 
