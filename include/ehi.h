@@ -185,6 +185,22 @@ ehi_status ehi_factor_batch(ehi_survey* const* surveys, int32_t n, const double*
                             void* batch_ws, size_t ws_bytes, void* stream, int32_t* bad_survey,
                             int32_t* bad_freq);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * batched factorisation as ehi_factor_batch, with the job table in a static
+ * device array of the library instead of a caller-provided batch_ws.  The
+ * array holds up to 4096 (survey, frequency) jobs (288 KiB); each device the
+ * library runs on keeps its own copy until the process ends.  Every survey
+ * must live on the current device.  EHI_EINVAL if the batch has more jobs
+ * than the table holds or a survey is on another device; otherwise the
+ * arguments, stream ordering, waiting and EHI_ENOTPD reporting are those of
+ * ehi_factor_batch, and the results are identical.  Allocates nothing.  The
+ * table is shared by every call on a device: calls that overlap on one device
+ * (from several host threads, before the previous call has returned) race and
+ * must be serialised by the caller. */
+ehi_status ehi_factor_batch_static(ehi_survey* const* surveys, int32_t n, const double* mu,
+                                   void* stream, int32_t* bad_survey, int32_t* bad_freq);
+
 /* Routes all later work of the survey to stream (a hipStream_t; NULL = the
  * default stream), e.g. to capture a build into a HIP graph or to run surveys
  * concurrently. */

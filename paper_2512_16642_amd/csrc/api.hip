@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <initializer_list>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -567,8 +568,14 @@ size_t ehi_batch_workspace_bytes(ehi_survey* const* surveys, int32_t n) {
   return ehi::align_up(sizeof(ehi::FactorJob) * jobs, ehi::kAlign);
 }
 
-ehi_status ehi_factor_batch(ehi_survey* const* surveys, int32_t n, const double* mu, void* batch_ws,
-                            size_t ws_bytes, void* stream, int32_t* bad_survey, int32_t* bad_freq) {
+}  // extern "C"
+
+namespace {
+
+// The batched factorisation with its job table at djobs_raw (capacity
+// cap_bytes, device memory of the current device).
+ehi_status factor_batch_impl(ehi_survey* const* surveys, int32_t n, const double* mu, void* djobs_raw,
+                             size_t cap_bytes, void* stream, int32_t* bad_survey, int32_t* bad_freq) {
   g_err.clear();
   if (bad_survey) *bad_survey = -1;
   if (bad_freq) *bad_freq = -1;
@@ -600,11 +607,11 @@ ehi_status ehi_factor_batch(ehi_survey* const* surveys, int32_t n, const double*
     }
     max_nr = std::max(max_nr, g.nr);
   }
-  if (!batch_ws || ws_bytes < sizeof(ehi::FactorJob) * jobs.size())
+  if (!djobs_raw || cap_bytes < sizeof(ehi::FactorJob) * jobs.size())
     return fail(EHI_ENOMEM, "batch workspace too small");
   hipStream_t st = static_cast<hipStream_t>(stream);
   ehi_survey* s = surveys[0];
-  ehi::FactorJob* djobs = static_cast<ehi::FactorJob*>(batch_ws);
+  ehi::FactorJob* djobs = static_cast<ehi::FactorJob*>(djobs_raw);
   PROF(EHI_PROF_FACTOR, st);
   EHI_TRY(hipMemcpyAsync(djobs, jobs.data(), sizeof(ehi::FactorJob) * jobs.size(),
                          hipMemcpyHostToDevice, st),
@@ -644,6 +651,66 @@ ehi_status ehi_factor_batch(ehi_survey* const* surveys, int32_t n, const double*
     }
   }
   return result;
+}
+
+// Job table of the batched factorisation for callers that cannot allocate:
+// one copy per device, held until the process ends.  Host code never passes
+// the array's name to a kernel or a copy: each device's address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kStaticJobs = 4096;
+static __device__ __align__(256) unsigned char scratch[kStaticJobs * sizeof(ehi::FactorJob)];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+ehi_status scratch_for_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(EHI_EINVAL, "device index beyond the static table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(EHI_EHIP, "hipGetSymbolAddress returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return EHI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ehi_status ehi_factor_batch(ehi_survey* const* surveys, int32_t n, const double* mu, void* batch_ws,
+                            size_t ws_bytes, void* stream, int32_t* bad_survey, int32_t* bad_freq) {
+  return factor_batch_impl(surveys, n, mu, batch_ws, ws_bytes, stream, bad_survey, bad_freq);
+}
+
+ehi_status ehi_factor_batch_static(ehi_survey* const* surveys, int32_t n, const double* mu, void* stream,
+                                   int32_t* bad_survey, int32_t* bad_freq) {
+  g_err.clear();
+  if (bad_survey) *bad_survey = -1;
+  if (bad_freq) *bad_freq = -1;
+  if (!surveys || n < 1 || !mu) return fail(EHI_EINVAL, "no surveys or no mu");
+  size_t jobs = 0;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  for (int k = 0; k < n; ++k) {
+    if (!surveys[k]) return fail(EHI_EINVAL, "survey is NULL");
+    if (surveys[k]->device != dev) return fail(EHI_EINVAL, "every survey must live on the current device");
+    jobs += (size_t)surveys[k]->g.nf;
+  }
+  if (jobs > kStaticJobs)
+    return fail(EHI_EINVAL, "batch of " + std::to_string(jobs) + " (survey, frequency) jobs exceeds the "
+                            "static job table (" + std::to_string(kStaticJobs) + ")");
+  void* table = nullptr;
+  ehi_status st = scratch_for_current_device(&table);
+  if (st != EHI_OK) return st;
+  return factor_batch_impl(surveys, n, mu, table, sizeof(scratch), stream, bad_survey, bad_freq);
 }
 
 ehi_status ehi_set_stream(ehi_survey* s, void* stream) {

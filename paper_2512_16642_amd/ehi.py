@@ -33,7 +33,7 @@ SYMBOLS = (
     "ehi_apply_multipliers", "ehi_lambda_max", "ehi_copy_green_dft", "ehi_load_green_dft",
     "ehi_copy_hessian", "ehi_load_hessian", "ehi_copy_factor", "ehi_destroy", "ehi_last_error",
     "ehi_version", "ehi_profile_enable", "ehi_profile_read", "ehi_batch_workspace_bytes",
-    "ehi_factor_batch", "ehi_set_stream", "ehi_set_launch", "ehi_get_launch",
+    "ehi_factor_batch", "ehi_factor_batch_static", "ehi_set_stream", "ehi_set_launch", "ehi_get_launch",
     "ehi_set_medium", "ehi_forward_subgrid", "ehi_backpropagate", "ehi_residual_spectra",
     "ehi_multipliers_to_time", "ehi_misfit", "ehi_cg_init", "ehi_cg_shift_dot", "ehi_cg_update",
     "ehi_cg_direction", "ehi_mdot", "ehi_combine",
@@ -101,6 +101,9 @@ def lib() -> ctypes.CDLL:
     L.ehi_factor_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(ctypes.c_double), vp,
                                    ctypes.c_size_t, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.ehi_factor_batch.restype = st
+    L.ehi_factor_batch_static.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(ctypes.c_double), vp,
+                                          ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.ehi_factor_batch_static.restype = st
     L.ehi_set_stream.argtypes = [vp, vp]
     L.ehi_set_stream.restype = st
     L.ehi_set_launch.argtypes = [vp, i32, i32, i32]
@@ -435,6 +438,28 @@ def factor_batch(surveys: Sequence["Survey"], mu: Sequence[float],
     bs, bf = ctypes.c_int32(-1), ctypes.c_int32(-1)
     rc = L.ehi_factor_batch(handles, len(surveys), mus, ctypes.c_void_p(ptr), ctypes.c_size_t(nbytes),
                             ctypes.c_void_p(st.cuda_stream), ctypes.byref(bs), ctypes.byref(bf))
+    if rc != EHI_OK:
+        err = EhiError(rc, L.ehi_last_error().decode(), bf.value)
+        err.bad_survey = bs.value
+        raise err
+
+
+def factor_batch_static(surveys: Sequence["Survey"], mu: Sequence[float],
+                        stream: Optional[torch.cuda.Stream] = None):
+    """``factor_batch`` with the library's static job table (no device
+    allocation: ehi_factor_batch_static); at most 4096 (survey, frequency)
+    jobs, all surveys on the current device."""
+    if len(surveys) != len(mu) or not surveys:
+        raise ValueError("one mu per survey")
+    L = lib()
+    for sv in surveys:
+        torch.cuda.synchronize(sv.device)
+    handles = (ctypes.c_void_p * len(surveys))(*[sv._h.value for sv in surveys])
+    st = stream if stream is not None else torch.cuda.current_stream(surveys[0].device)
+    mus = (ctypes.c_double * len(mu))(*[float(m) for m in mu])
+    bs, bf = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    rc = L.ehi_factor_batch_static(handles, len(surveys), mus, ctypes.c_void_p(st.cuda_stream),
+                                   ctypes.byref(bs), ctypes.byref(bf))
     if rc != EHI_OK:
         err = EhiError(rc, L.ehi_last_error().decode(), bf.value)
         err.bad_survey = bs.value
