@@ -49,9 +49,15 @@ def parse():
                          "accuracy test on the 1000 x 300 survey) or randomized (one receiver per "
                          "subset, factors reused over iterations, on the 1000 x 300 survey)")
     ap.add_argument("--batch-nt", type=int, default=4000, help="time steps of the batch8 surveys")
+    ap.add_argument("--staging-gb", type=float, default=6.0,
+                    help="batch8: staging budget per survey (sets the receivers stepped together)")
+    ap.add_argument("--batch-chunk", type=int, default=256, choices=[256, 512, 1024],
+                    help="batch8: time samples per staging window")
     ap.add_argument("--precision", default="split_bf16", choices=["split_bf16", "plain_fp32"])
     ap.add_argument("--weighting", default="long_record", choices=["long_record", "finite_record"],
                     help="Fourier-diagonal weighting: final-spectrum Gram (default) or the finite-record W")
+    ap.add_argument("--decim", type=int, default=1,
+                    help="finite-record weighting: keep every D-th low-pass filtered sample of the record")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: mean arrivals per second")
     ap.add_argument("--p-build", type=float, default=0.02, help="serve: probability a request is a build")
     ap.add_argument("--duration", type=float, default=120.0, help="serve: seconds of arrivals")
@@ -162,9 +168,10 @@ def run_batch(args):
     torch.cuda.set_device(dev)
     vels = [torch.from_numpy(s.velocity()).to(dev) for s in specs]
     Rs = [torch.from_numpy(s.residuals()).to(dev) for s in specs]
-    b = batch.SurveyBatch(specs, precision=args.precision, tune=True)
-    print(f"# batch8: workspaces {b.workspace_bytes / 1e9:.1f} GB, launch shapes tuned", file=sys.stderr,
-          flush=True)
+    b = batch.SurveyBatch(specs, precision=args.precision, tune=True,
+                          staging_budget_bytes=int(args.staging_gb * (1 << 30)), chunk=args.batch_chunk)
+    print(f"# batch8: workspaces {b.workspace_bytes / 1e9:.1f} GB, receivers per batch "
+          f"{[sv.nr_batch for sv in b.surveys]}, launch shapes tuned", file=sys.stderr, flush=True)
     b.build(vels, graph=True)
     mu = [1e-3 * l for l in b.lambda_max()]
     for _ in range(args.warmup):
@@ -207,7 +214,9 @@ def run_batch(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "batch8-layered-uneven", "precision": args.precision, "nt": args.batch_nt,
-                   "surveys": [s.name for s in specs]},
+                   "surveys": [s.name for s in specs], "staging_gb": args.staging_gb,
+                   "chunk": args.batch_chunk, "nr_batch": [sv.nr_batch for sv in b.surveys]},
+        "workspace_gb": round(b.workspace_bytes / 1e9, 2),
         "stage_ms": {"build_graph": round(tb / K, 2), "factor_batched": round(tf / K, 3),
                      "apply": round(ta / K, 3)},
         "surveys_per_s": round(len(specs) / ((tb + tf) / K / 1e3), 3),
@@ -518,7 +527,8 @@ def main():
     X = torch.empty_like(R)
     keep = tuple(args.keep)
     sv = ehi.survey_from(s, precision=args.precision, max_ns=s.ns, nr_batch=args.nr_batch,
-                         weighting=args.weighting, chunk=args.chunk, windows=args.windows, keep=keep)
+                         weighting=args.weighting, chunk=args.chunk, windows=args.windows, keep=keep,
+                         decim=args.decim)
     print(f"# workload {s.name} precision {args.precision} workspace {sv.workspace_bytes / 1e9:.2f} GB",
           file=sys.stderr, flush=True)
 
@@ -594,7 +604,7 @@ def main():
     dft_flops = costs.dft_flops_per_survey(s.nz, s.nx, s.stride, s.nr, s.nt, s.nf)
     # the finite-record form contracts the running spectra after every step: nt
     # times the final-spectrum contraction
-    rep = s.nt if args.weighting == "finite_record" else 1
+    rep = (s.nt + args.decim - 1) // args.decim if args.weighting == "finite_record" else 1
     herk_flops = costs.herk_flops_per_survey(s.nz, s.nx, s.stride, s.nr, s.nf) * rep
     compressed = keep[0] > 0 and keep[1] > 0
     if compressed:
@@ -621,10 +631,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": s.name, "precision": args.precision, "weighting": args.weighting,
+                   "decim": args.decim,
                    "chunk": args.chunk, "windows": args.windows, "keep": list(keep),
                    "nz": s.nz, "nx": s.nx,
                    "nb": s.nb, "nr": s.nr, "nt": s.nt, "nf": s.nf, "ns": s.ns, "stride": s.stride,
                    "nr_batch": nrb},
+        "workspace_gb": round(sv.workspace_bytes / 1e9, 3),
         "solves_per_s": round(solves_per_s, 1),
         "sources_per_s": round(s.ns / (stage_ms["apply"] / 1e3), 2),
         "stage_ms": {k: round(v, 3) for k, v in stage_ms.items()},
@@ -648,7 +660,9 @@ def main():
         # (every product the kernel issues, lo.lo and block padding included)
         # beside it
         planned = 3.0 * herk_flops / (herk_ms / 1e3) / 1e12
-        out["roofline_herk"] = {"kernel": "k_herk_bf16_whole" if whole else "k_herk_bf16", "bound": "mfma",
+        kname = ("k_herk_r2 (finite-record, per kept sample)" if args.weighting == "finite_record"
+                 else "k_herk_bf16_whole" if whole else "k_herk_bf16")
+        out["roofline_herk"] = {"kernel": kname, "bound": "mfma",
                                 "achieved": round(planned, 1), "peak": 2500.0, "unit": "TFLOP/s",
                                 "frac": round(planned / 2500.0, 4),
                                 "count": "3 BF16 products x useful Hermitian flops (8 nr(nr+1)/2 nsub nf)",

@@ -115,6 +115,19 @@ typedef enum {
  *             window runs on a second, library-owned stream while the time
  *             steps fill the other window, at twice the staging memory.
  *             Results do not depend on it.
+ *   decim     time-axis resampling of the finite-record weighting (0 or 1 =
+ *             every sample; D = 2..64 keeps every D-th sample; the paper's
+ *             numerical examples resample the record in time before forming
+ *             the Hessian).  The record is low-pass filtered first (zero-phase
+ *             Kaiser-windowed sinc, 120 dB: passband up to the highest
+ *             frequency f_max, stopband from 1/(D dt) - f_max, half-length
+ *             K = ceil((120 - 7.95) / (2 * 14.36 * (1/D - 2 f_max dt))),
+ *             unit sum), kept at the times n_q = 1 - K + q D, and
+ *               Hhat(w) = (D / Nt) sum_{q: 1 <= n_q <= Nt} Gt_q(w) Gt_q(w)^H,
+ *               Gt_q(w) = (D / H(w)) sum_{m <= q} y_m exp(-i w n_m dt),
+ *             H(w) the filter's response; the spectra of ehi_copy_green_dft
+ *             are Gt_last.  Requires EHI_WEIGHT_FINITE_RECORD, windows 1,
+ *             1/(D dt) > 2 f_max, K <= 512 and 2K <= chunk, D <= chunk / 2.
  */
 typedef struct {
   int32_t nz, nx, nb;
@@ -133,6 +146,7 @@ typedef struct {
   int32_t chunk;
   int32_t keep_z, keep_x;
   int32_t windows;
+  int32_t decim;
 } ehi_survey_desc;
 
 typedef struct ehi_survey ehi_survey;
@@ -230,8 +244,19 @@ ehi_status ehi_apply_multipliers(ehi_survey* s, const void* resid_dev, void* mul
 ehi_status ehi_lambda_max(ehi_survey* s, double* out);
 
 /* Copies Ghat, complex64 [nf][nr][nzs][nxs] (nzs = ceil(nz/stride),
- * nxs = ceil(nx/stride)), to the device buffer out_dev.  Asynchronous. */
+ * nxs = ceil(nx/stride)), to the device buffer out_dev.  Asynchronous.
+ * EHI_EINVAL for a compressed survey (keep_z > 0), which holds one receiver
+ * batch's spectra at a time and keeps only their compressed form. */
 ehi_status ehi_copy_green_dft(ehi_survey* s, void* out_dev);
+
+/* Compressed surveys: copies the compressed spectra (the leading keep_z x
+ * keep_x coefficients of the orthonormal 2D DCT-II of every spectrum row,
+ * the orthonormal spatial transform of the paper's discussion), complex64
+ * [nf][nr][keep_z][keep_x], to out_dev.  They are formed batch by batch
+ * during ehi_build_green (or from the input of ehi_load_green_dft), so the
+ * full spectra are never held.  EHI_EINVAL if the survey is not compressed.
+ * Asynchronous. */
+ehi_status ehi_copy_compressed(ehi_survey* s, void* out_dev);
 
 /* Replaces Ghat by the caller's complex64 [nf][nr][nzs][nxs] device array, so
  * the later stages can be run on given spectra.  Asynchronous.  EHI_ESTATE for

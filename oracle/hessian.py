@@ -26,8 +26,18 @@ Forms computed here (all for one survey; receivers i, j; grid points x):
   the 2Nt transform as the time average of running-DFT Gram matrices:
   Hhat_W(w) = (1/Nt) sum_{p=1}^{Nt} Ghat_p(w) Ghat_p(w)^H with Ghat_p the DFT
   truncated after sample p.  Equals 2 qhat of the literal algorithm with W.
+* ``hessian_r2_decimated``: the same time average on the record resampled in
+  time (the numerical examples resample the Green functions and data to the
+  Nyquist rate before forming the Hessian): every D-th sample of the record
+  low-pass filtered by ``decimation_filter``, the running spectra taken at the
+  kept samples and corrected by D / H(w), the Gram average over the kept
+  samples that fall inside the record, each weighted D / Nt.
 
-Pins (tests/test_oracle_hessian.py): the Toeplitz blocks against S S^T built
+Pins (tests/test_oracle_hessian.py): the decimation filter's response
+(numpy FFT of the taps) in the passband and the stopband, the decimated record
+against numpy's convolution, the decimated transform against the DFT of the
+whole record, and the decimated Hessian at D = 1 against ``hessian_r2``; the
+Toeplitz blocks against S S^T built
 column by column from PDE solves; the diagonal-sum structure of Q; the literal
 algorithm against the diagonal of the 2Nt-point transform of the zero-embedded
 brute-force Q (computed with numpy's FFT); R1 and R2 against the literal
@@ -164,3 +174,97 @@ def running_dft_gram(gt: np.ndarray, freqs_hz, dt: float) -> np.ndarray:
 def hessian_r2(gt: np.ndarray, freqs_hz, dt: float) -> np.ndarray:
     """Finite-record (W-weighted) Hessian without penalty, ``[nf][nr][nr]``."""
     return running_dft_gram(gt, freqs_hz, dt)
+
+
+# ---------------------------------------------------------------------------
+# time-axis resampling of the record before the finite-record Hessian
+# ---------------------------------------------------------------------------
+
+def _bessel_i0(x: np.ndarray) -> np.ndarray:
+    return np.i0(x)
+
+
+def decimation_filter(D: int, dt: float, f_max: float, atten_db: float = 120.0) -> np.ndarray:
+    """Zero-phase low-pass taps h_j, j = -K..K, for keeping every D-th sample.
+
+    Kaiser-windowed sinc (Kaiser's design rules): the passband ends at f_max
+    (the highest frequency the Hessian needs), the stopband starts at
+    fs/D - f_max (the lowest frequency that folds onto the passband once every
+    D-th sample is kept), the cutoff fc = fs/(2D) lies halfway;
+    beta = 0.1102 (A - 8.7), filter order N = (A - 7.95) / (14.36 df / fs)
+    with df = fs/D - 2 f_max, half-length K = ceil(N / 2); taps
+    (1/D) sinc(j / D) I0(beta sqrt(1 - (j/K)^2)) / I0(beta), scaled to unit
+    sum.  D = 1 gives the single tap 1.
+    """
+    if D <= 1:
+        return np.ones(1)
+    fs = 1.0 / dt
+    df = fs / D - 2.0 * f_max
+    if df <= 0:
+        raise ValueError("decimation factor too large for the highest frequency")
+    beta = 0.1102 * (atten_db - 8.7)
+    order = (atten_db - 7.95) / (14.36 * df / fs)
+    K = int(math.ceil(order / 2.0))
+    j = np.arange(-K, K + 1, dtype=np.float64)
+    w = _bessel_i0(beta * np.sqrt(np.maximum(0.0, 1.0 - (j / K) ** 2))) / _bessel_i0(np.array(beta))
+    h = np.sinc(j / D) / D * w
+    return h / h.sum()
+
+
+def decimation_times(nt: int, D: int, K: int):
+    """Times (sample indices) n_q = 1 - K + q D of the kept samples, q = 0..M-1,
+    M the count whose filter support [n_q - K, n_q + K] meets the record
+    1..nt; and the range [qa, qb] of those inside the record (1 <= n_q <= nt)."""
+    if D <= 1:
+        n = np.arange(1, nt + 1)
+        return n, 0, nt - 1
+    M = (nt - 1 + 2 * K) // D + 1
+    n = 1 - K + D * np.arange(M)
+    inside = np.nonzero((n >= 1) & (n <= nt))[0]
+    return n, int(inside[0]), int(inside[-1])
+
+
+def decimate(gt: np.ndarray, D: int, h: np.ndarray) -> np.ndarray:
+    """y_q(x) = sum_{j=-K}^{K} h_j g(n_q + j, x) at the kept times n_q of
+    ``decimation_times``, with g(n) = 0 outside 1..nt.  ``gt`` is
+    ``[nr][nt][...]``; returns ``[nr][M][...]``."""
+    K = (len(h) - 1) // 2
+    nr, nt = gt.shape[:2]
+    n, _, _ = decimation_times(nt, D, K)
+    out = np.zeros((nr, len(n)) + gt.shape[2:])
+    for q, nq in enumerate(n):
+        for jj, hj in enumerate(h):
+            m = nq + jj - K                  # sample index 1..nt
+            if 1 <= m <= nt:
+                out[:, q] += hj * gt[:, m - 1]
+    return out
+
+
+def hessian_r2_decimated(gt: np.ndarray, freqs_hz, dt: float, D: int, atten_db: float = 120.0) -> np.ndarray:
+    """Finite-record Hessian on the record resampled to every D-th sample.
+
+    With h = decimation_filter(D, dt, max f), y = decimate(g), the kept times
+    n_q and H(w) = sum_j h_j exp(-i w j dt) (real), the running spectra are
+    Gt_q(w) = (D / H(w)) sum_{m <= q} y_m exp(-i w n_m dt) and
+        Hhat_W^D(w) = (D / Nt) sum_{q: 1 <= n_q <= Nt} Gt_q(w) Gt_q(w)^H.
+    ``gt`` is ``[nr][Nt][nsub]``; returns ``[nf][nr][nr]``.  D = 1 is
+    ``hessian_r2``."""
+    nr, nt, nsub = gt.shape
+    fmax = float(np.max(freqs_hz))
+    h = decimation_filter(D, dt, fmax, atten_db)
+    K = (len(h) - 1) // 2
+    y = decimate(gt, D, h)
+    n, qa, qb = decimation_times(nt, D, K)
+    w = 2.0 * math.pi * np.asarray(freqs_hz, dtype=np.float64)
+    j = np.arange(-K, K + 1)
+    out = np.zeros((len(w), nr, nr), dtype=np.complex128)
+    for f, wf in enumerate(w):
+        Hw = float(np.real(np.sum(h * np.exp(-1j * wf * j * dt))))
+        c = D / Hw
+        acc = np.zeros((nr, nsub), dtype=np.complex128)
+        for q in range(len(n)):
+            acc += y[:, q, :] * np.exp(-1j * wf * n[q] * dt)
+            if qa <= q <= qb:
+                g = c * acc
+                out[f] += g @ g.conj().T
+    return out * (D / nt)

@@ -20,14 +20,14 @@ from . import autotune, ehi
 class SurveyBatch:
     def __init__(self, specs: Sequence, precision: str = "split_bf16",
                  staging_budget_bytes: int = 6 << 30, tune: bool = False,
-                 device: Optional[torch.device] = None):
+                 device: Optional[torch.device] = None, chunk: int = 256):
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
         self.specs = list(specs)
         self.surveys: List[ehi.Survey] = []
         self.streams = [torch.cuda.Stream(self.device) for _ in self.specs]
         for spec, st in zip(self.specs, self.streams):
-            nrb = staging_receivers(spec, staging_budget_bytes)
-            sv = ehi.survey_from(spec, precision=precision, nr_batch=nrb, stream=st)
+            nrb = staging_receivers(spec, staging_budget_bytes, chunk)
+            sv = ehi.survey_from(spec, precision=precision, nr_batch=nrb, stream=st, chunk=chunk)
             if tune:
                 autotune.apply(sv, spec)
             self.surveys.append(sv)

@@ -35,6 +35,54 @@ ehi_status hip_fail(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
+// Resampling filter design (host, FP64): Kaiser-windowed sinc with 120 dB of
+// attenuation, passband up to f_max, stopband from fs/D - f_max, cutoff
+// fs/(2D); beta = 0.1102 (A - 8.7), order (A - 7.95) / (14.36 df/fs).
+constexpr double kDecimAtten = 120.0;
+
+double max_freq(const ehi_survey_desc* d) {
+  double m = 0.0;
+  for (int f = 0; f < d->nf; ++f) m = std::max(m, d->freq_hz[f]);
+  return m;
+}
+
+// half-length K, or -1 if the stopband would start below the passband
+int decim_half_length(int D, double dt, double fmax) {
+  const double df_fs = 1.0 / D - 2.0 * fmax * dt;  // (fs/D - 2 f_max) / fs
+  if (!(df_fs > 0)) return -1;
+  const double order = (kDecimAtten - 7.95) / (14.36 * df_fs);
+  return (int)std::ceil(order / 2.0);
+}
+
+// modified Bessel function of the first kind, order 0, by its power series
+double bessel_i0(double x) {
+  double sum = 1.0, term = 1.0;
+  const double q = 0.25 * x * x;
+  for (int k = 1; k < 500; ++k) {
+    term *= q / ((double)k * k);
+    sum += term;
+    if (term < 1e-17 * sum) break;
+  }
+  return sum;
+}
+
+std::vector<double> decim_taps(int D, int K) {
+  const double beta = 0.1102 * (kDecimAtten - 8.7);
+  const double pi = 3.14159265358979323846;
+  std::vector<double> h(2 * K + 1);
+  double sum = 0.0;
+  for (int j = -K; j <= K; ++j) {
+    const double x = (double)j / D;
+    const double sinc = j == 0 ? 1.0 : std::sin(pi * x) / (pi * x);
+    const double r = (double)j / K;
+    const double w = bessel_i0(beta * std::sqrt(std::max(0.0, 1.0 - r * r))) / bessel_i0(beta);
+    h[j + K] = sinc / D * w;
+    sum += h[j + K];
+  }
+  for (double& v : h) v /= sum;
+  return h;
+}
+
 bool validate(const ehi_survey_desc* d, std::string* why) {
   auto bad = [&](const char* m) {
     *why = m;
@@ -84,6 +132,18 @@ bool validate(const ehi_survey_desc* d, std::string* why) {
       return bad("spatial compression applies to the final-spectrum contraction only");
   }
   if (d->windows < 0 || d->windows > 2) return bad("windows must be 0, 1 or 2");
+  if (d->decim < 0 || d->decim > ehi::kMaxDecim) return bad("decim must be in [0, 64]");
+  if (d->decim >= 2) {
+    if (d->weighting != EHI_WEIGHT_FINITE_RECORD)
+      return bad("time-axis resampling applies to the finite-record weighting");
+    if (d->windows == 2) return bad("time-axis resampling needs one staging window");
+    const int K = decim_half_length(d->decim, d->dt, max_freq(d));
+    if (K < 0) return bad("decimation factor too large for the highest frequency (1/(D dt) must exceed 2 f_max)");
+    if (K > ehi::kMaxDecimK) return bad("resampling filter longer than 1025 taps");
+    const int chunk = d->chunk ? d->chunk : 256;
+    if (2 * K > chunk || 2 * d->decim > chunk)
+      return bad("staging window shorter than the resampling filter (raise chunk)");
+  }
   const long long chunk = d->chunk ? d->chunk : 256;
   if ((nsub + 256) * chunk * 4 >= (1LL << 31)) return bad("subgrid too large for the staging buffer");
   return true;
@@ -117,6 +177,28 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   g.weighting = d->weighting;
   g.keep_z = d->keep_z;
   g.keep_x = d->keep_x;
+  // compressed surveys hold one receiver batch's spectra at a time: each batch
+  // is transformed into the compressed spectra as soon as its DFT is complete
+  g.gh_rows = g.keep_z > 0 ? g.nrb : g.nr;
+  g.decim = 1;
+  g.dK = 0;
+  g.dM = d->nt;
+  g.dqa = 0;
+  g.dqb = d->nt - 1;
+  g.dhist = 0;
+  g.drows = 0;
+  if (d->decim >= 2) {
+    // kept samples n_q = 1 - K + q D whose filter support [n_q - K, n_q + K]
+    // meets the record 1..nt
+    g.decim = d->decim;
+    g.dK = decim_half_length(d->decim, d->dt, max_freq(d));
+    g.dM = (d->nt - 1 + 2 * g.dK) / g.decim + 1;
+    g.dqa = ehi::cdiv(g.dK, g.decim);                   // first q with n_q >= 1
+    g.dqb = (d->nt - 1 + g.dK) / g.decim;               // last q with n_q <= nt
+    g.dhist = 2 * g.dK;
+    const int chunk = d->chunk ? d->chunk : 256;
+    g.drows = chunk / g.decim + ehi::cdiv(2 * g.dK, g.decim) + 2;
+  }
   int ntile = ehi::cdiv(g.nr, g.split_bf16 ? 64 : ehi::kHerkTile);
   int pairs = ntile * (ntile + 1) / 2;
   int want = ehi::cdiv(2048, pairs * g.nf);
@@ -180,12 +262,19 @@ ehi::Layout make_layout(const ehi::Geometry& g) {
   L.w0 = take(sizeof(float) * g.plane() * g.nrb);
   L.w1 = take(sizeof(float) * g.plane() * g.nrb);
   L.stage = take(sizeof(float) * (size_t)g.windows * g.nrb * g.chunk * g.nsub_p);
-  L.ghat = take(sizeof(float2) * (size_t)g.nf * g.nr * g.nsub);
+  L.ghat = take(sizeof(float2) * (size_t)g.nf * g.gh_rows * g.nsub);
   L.hpart = take(sizeof(float2) * (size_t)g.herk_split * g.nf * nn);
   L.hpart64 = take(g.weighting == EHI_WEIGHT_FINITE_RECORD ? sizeof(double2) * (size_t)g.herk_split * g.nf * nn : 0);
+  L.r2scale = take(sizeof(double) * g.nf);
+  L.gscale = take(sizeof(double) * g.nf);
+  const bool dec = g.decim > 1;
+  L.dtaps = take(dec ? sizeof(float) * (2 * g.dK + 1) : 0);
+  L.dtw = take(dec ? sizeof(float2) * (size_t)g.dM * g.nf : 0);
+  L.dhistbuf = take(dec ? sizeof(float) * (size_t)g.nrb * g.dhist * g.nsub_p : 0);
+  L.ddec = take(dec ? sizeof(float) * (size_t)g.nrb * g.drows * g.nsub_p : 0);
   L.dctz = take(sizeof(float2) * (size_t)g.keep_z * g.nzs);
   L.dctx = take(sizeof(float2) * (size_t)g.keep_x * g.nxs);
-  L.dtmp = take(sizeof(float2) * (size_t)g.nf * g.nr * g.nxs * g.keep_z);
+  L.dtmp = take(sizeof(float2) * (size_t)g.nf * g.gh_rows * g.nxs * g.keep_z);
   L.gcomp = take(sizeof(float2) * (size_t)g.nf * g.nr * g.keep_z * g.keep_x);
   L.hhat = take(sizeof(double2) * g.nf * nn);
   L.qhat = take(sizeof(double2) * g.nf * nn);
@@ -330,6 +419,33 @@ ehi_status ehi_create(const ehi_survey_desc* desc, void* workspace_dev, size_t w
     e = hipMemcpyAsync(s->ptr<int32_t>(L.rowrec), rowrec.data(), sizeof(int32_t) * rowrec.size(),
                        hipMemcpyHostToDevice, s->stream);
   if (e == hipSuccess) e = ehi::launch_twiddles(g, s->ptr<double>(L.freq), s->ptr<float2>(L.tw), s->stream);
+  // finite-record Gram scale per frequency; with time-axis resampling the
+  // filter taps, the twiddles at the kept samples and D / H(w)
+  std::vector<double> r2scale(g.nf, 1.0 / g.nt), gscale(g.nf, 1.0);
+  std::vector<float> taps32;
+  if (g.decim > 1) {
+    const std::vector<double> h = decim_taps(g.decim, g.dK);
+    taps32.assign(h.begin(), h.end());
+    for (int f = 0; f < g.nf; ++f) {
+      const double w = 2.0 * 3.14159265358979323846 * s->freq[f];
+      double H = h[g.dK];
+      for (int j = 1; j <= g.dK; ++j) H += 2.0 * h[g.dK + j] * std::cos(w * j * g.dt);
+      gscale[f] = g.decim / H;
+      r2scale[f] = gscale[f] * gscale[f] * g.decim / g.nt;
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->ptr<float>(L.dtaps), taps32.data(), sizeof(float) * taps32.size(),
+                         hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+      e = ehi::launch_twiddles_at(g.dM, g.nf, g.dt, s->ptr<double>(L.freq), 1 - g.dK, g.decim,
+                                  s->ptr<float2>(L.dtw), s->stream);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->ptr<double>(L.r2scale), r2scale.data(), sizeof(double) * g.nf, hipMemcpyHostToDevice,
+                       s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->ptr<double>(L.gscale), gscale.data(), sizeof(double) * g.nf, hipMemcpyHostToDevice,
+                       s->stream);
   if (e == hipSuccess && g.keep_z > 0) {
     e = ehi::launch_dct_matrix(g.nzs, g.keep_z, s->ptr<float2>(L.dctz), s->stream);
     if (e == hipSuccess) e = ehi::launch_dct_matrix(g.nxs, g.keep_x, s->ptr<float2>(L.dctx), s->stream);
@@ -433,8 +549,18 @@ ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev) {
     pending[b] = false;
     return hipStreamWaitEvent(st, s->ev_dft[b], 0);
   };
+  const bool resample = g.weighting == EHI_WEIGHT_FINITE_RECORD && g.decim > 1;
+  // the kept-sample buffer as a staging buffer of drows rows per receiver
+  ehi::Geometry gd = g;
+  gd.chunk = g.drows;
+  // the spectra buffer as the DFT sees it (one batch's rows when compressed)
+  ehi::Geometry gb = g;
+  gb.nr = g.gh_rows;
+  const float2* dtw = s->ptr<float2>(L.dtw);
+  float* ddec = s->ptr<float>(L.ddec);
   for (int r0 = 0; r0 < g.nr; r0 += g.nrb) {
     const int nb_now = std::min(g.nrb, g.nr - r0);
+    int q_done = 0;  // kept samples already produced (resampling)
     float* ub[2] = {s->ptr<float>(L.u0), s->ptr<float>(L.u1)};
     float* wb[2] = {s->ptr<float>(L.w0), s->ptr<float>(L.w1)};
     int b = 0;  // window buffer being filled
@@ -458,18 +584,63 @@ ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev) {
           EHI_TRY(hipEventRecord(s->ev_marched[b], st), "window event");
           EHI_TRY(hipStreamWaitEvent(dst, s->ev_marched[b], 0), "window wait");
         }
-        if (g.weighting == EHI_WEIGHT_FINITE_RECORD) {
-          // the running spectra of this window, before the DFT advances them
-          PROF(EHI_PROF_HERK, dst);
-          EHI_TRY(ehi::launch_herk_r2_chunk(g, stage[b], tw, ghat, n0, n_cur - n0 + 1, n0 == 1,
-                                            s->ptr<double2>(L.hpart64), dst),
-                  "finite-record contraction");
+        if (resample) {
+          // kept samples whose filter support ends in this window (all that
+          // remain at the end of the record), then the running spectra and
+          // their Gram on them; the window's last 2K samples are kept for the
+          // next window's filter
+          const bool last = n_cur == g.nt;
+          const int q_hi = last ? g.dM : std::min(g.dM, (n_cur - 1) / g.decim + 1);
+          const int cnt = q_hi - q_done;
+          if (cnt > 0) {
+            PROF(EHI_PROF_DFT, dst);
+            EHI_TRY(ehi::launch_decimate(g, stage[b], s->ptr<float>(L.dhistbuf), s->ptr<float>(L.dtaps), q_done, cnt,
+                                         n0, n_cur, nb_now, ddec, dst),
+                    "resampling filter");
+            PROF_N(1);
+            PROF(EHI_PROF_HERK, dst);
+            EHI_TRY(ehi::launch_herk_r2_chunk(gd, ddec, dtw, ghat, q_done + 1, cnt, q_done == 0, g.dqa - q_done,
+                                              g.dqb - q_done, s->ptr<double2>(L.hpart64), dst),
+                    "finite-record contraction");
+            PROF_N(1);
+            PROF(EHI_PROF_DFT, dst);
+            EHI_TRY(ehi::launch_dft_chunk(gd, ddec, dtw, q_done + 1, cnt, q_done == 0, r0, nb_now, ghat, dst),
+                    "dft chunk");
+            PROF_N(1);
+            q_done = q_hi;
+          }
+          if (!last)
+            EHI_TRY(ehi::launch_hist_copy(g, stage[b], n_cur, nb_now, s->ptr<float>(L.dhistbuf), dst),
+                    "resampling history");
+        } else {
+          if (g.weighting == EHI_WEIGHT_FINITE_RECORD) {
+            // the running spectra of this window, before the DFT advances them
+            PROF(EHI_PROF_HERK, dst);
+            EHI_TRY(ehi::launch_herk_r2_chunk(g, stage[b], tw, ghat, n0, n_cur - n0 + 1, n0 == 1, 0,
+                                              n_cur - n0, s->ptr<double2>(L.hpart64), dst),
+                    "finite-record contraction");
+            PROF_N(1);
+          }
+          PROF(EHI_PROF_DFT, dst);
+          if (g.keep_z > 0) {
+            // the batch's own rows of the spectra buffer
+            EHI_TRY(ehi::launch_dft_chunk(gb, stage[b], tw, n0, n_cur - n0 + 1, n0 == 1, 0, nb_now, ghat, dst),
+                    "dft chunk");
+          } else {
+            EHI_TRY(ehi::launch_dft_chunk(g, stage[b], tw, n0, n_cur - n0 + 1, n0 == 1, r0, nb_now, ghat, dst),
+                    "dft chunk");
+          }
           PROF_N(1);
+          if (g.keep_z > 0 && n_cur == g.nt) {
+            // the batch's spectra are complete: into the compressed spectra
+            PROF(EHI_PROF_HERK, dst);
+            EHI_TRY(ehi::launch_dct_compress(g, ghat, g.gh_rows, r0, nb_now, s->ptr<float2>(L.dctz),
+                                             s->ptr<float2>(L.dctx), s->ptr<float2>(L.dtmp),
+                                             s->ptr<float2>(L.gcomp), dst),
+                    "spatial compression");
+            PROF_N(2 * g.nf);
+          }
         }
-        PROF(EHI_PROF_DFT, dst);
-        EHI_TRY(ehi::launch_dft_chunk(g, stage[b], tw, n0, n_cur - n0 + 1, n0 == 1, r0, nb_now, ghat, dst),
-                "dft chunk");
-        PROF_N(1);
         if (two) {
           EHI_TRY(hipEventRecord(s->ev_dft[b], dst), "window event");
           pending[b] = true;
@@ -492,6 +663,12 @@ ehi_status ehi_build_green(ehi_survey* s, const float* vel_dev) {
   // the survey's stream resumes after the last DFT
   EHI_TRY(free_window(0), "window wait");
   EHI_TRY(free_window(1), "window wait");
+  if (resample) {
+    // the resampled running spectra to the record's spectra: times D / H(w)
+    PROF(EHI_PROF_DFT, st);
+    EHI_TRY(ehi::launch_scale_spectra(g, s->ptr<double>(L.gscale), ghat, st), "spectra scale");
+    PROF_N(1);
+  }
   PROF_END();
   s->state = ehi::State::Green;
   return EHI_OK;
@@ -507,7 +684,8 @@ ehi_status ehi_build_hessian(ehi_survey* s) {
   PROF(EHI_PROF_HERK, s->stream);
   if (g.weighting == EHI_WEIGHT_FINITE_RECORD) {
     // accumulated during build_green; only the reduction remains
-    EHI_TRY(ehi::launch_herk_r2_reduce(g, s->ptr<double2>(L.hpart64), s->ptr<double2>(L.hhat), s->stream),
+    EHI_TRY(ehi::launch_herk_r2_reduce(g, s->ptr<double2>(L.hpart64), s->ptr<double>(L.r2scale),
+                                       s->ptr<double2>(L.hhat), s->stream),
             "finite-record reduce");
     PROF_N(1);
     PROF_END();
@@ -520,13 +698,12 @@ ehi_status ehi_build_hessian(ehi_survey* s) {
     // the energy in few terms, where the split-BF16 form's per-term rounding no
     // longer averages out, so this contraction sums FP32 products in FP64
     // (either precision mode)
-    EHI_TRY(ehi::launch_dct_compress(g, spectra, s->ptr<float2>(L.dctz), s->ptr<float2>(L.dctx),
-                                     s->ptr<float2>(L.dtmp), s->ptr<float2>(L.gcomp), s->stream),
-            "spatial compression");
+    // (the compressed spectra were formed batch by batch in build_green or
+    // load_green_dft)
     EHI_TRY(ehi::launch_herk_compressed(g, s->ptr<float2>(L.gcomp), g.keep_z * g.keep_x,
                                         s->ptr<double2>(L.hhat), s->stream),
             "compressed contraction");
-    PROF_N(4);
+    PROF_N(2);
     PROF_END();
     s->state = ehi::State::Hessian;
     return EHI_OK;
@@ -792,9 +969,22 @@ ehi_status ehi_copy_green_dft(ehi_survey* s, void* out_dev) {
   g_err.clear();
   if (!s || !out_dev) return fail(EHI_EINVAL, "NULL argument");
   if (s->state < ehi::State::Green) return fail(EHI_ESTATE, "no Green-function spectra yet");
+  if (s->g.keep_z > 0)
+    return fail(EHI_EINVAL, "a compressed survey holds the compressed spectra only (ehi_copy_compressed)");
   size_t bytes = sizeof(float2) * (size_t)s->g.nf * s->g.nr * s->g.nsub;
   EHI_TRY(hipMemcpyAsync(out_dev, s->ws + s->L.ghat, bytes, hipMemcpyDeviceToDevice, s->stream),
           "copy green");
+  return EHI_OK;
+}
+
+ehi_status ehi_copy_compressed(ehi_survey* s, void* out_dev) {
+  g_err.clear();
+  if (!s || !out_dev) return fail(EHI_EINVAL, "NULL argument");
+  if (s->g.keep_z <= 0) return fail(EHI_EINVAL, "the survey is not compressed");
+  if (s->state < ehi::State::Green) return fail(EHI_ESTATE, "no Green-function spectra yet");
+  size_t bytes = sizeof(float2) * (size_t)s->g.nf * s->g.nr * s->g.keep_z * s->g.keep_x;
+  EHI_TRY(hipMemcpyAsync(out_dev, s->ws + s->L.gcomp, bytes, hipMemcpyDeviceToDevice, s->stream),
+          "copy compressed");
   return EHI_OK;
 }
 
@@ -803,7 +993,21 @@ ehi_status ehi_load_green_dft(ehi_survey* s, const void* in_dev) {
   if (!s || !in_dev) return fail(EHI_EINVAL, "NULL argument");
   if (s->g.weighting == EHI_WEIGHT_FINITE_RECORD)
     return fail(EHI_ESTATE, "the finite-record weighting is built from the time samples (ehi_build_green)");
-  size_t bytes = sizeof(float2) * (size_t)s->g.nf * s->g.nr * s->g.nsub;
+  const ehi::Geometry& g = s->g;
+  if (g.keep_z > 0) {
+    // straight into the compressed spectra, gh_rows receivers at a time
+    const float2* in = static_cast<const float2*>(in_dev);
+    for (int r0 = 0; r0 < g.nr; r0 += g.gh_rows) {
+      const int nb_now = std::min(g.gh_rows, g.nr - r0);
+      EHI_TRY(ehi::launch_dct_compress(g, in + (size_t)r0 * g.nsub, g.nr, r0, nb_now, s->ptr<float2>(s->L.dctz),
+                                       s->ptr<float2>(s->L.dctx), s->ptr<float2>(s->L.dtmp),
+                                       s->ptr<float2>(s->L.gcomp), s->stream),
+              "spatial compression");
+    }
+    s->state = ehi::State::Green;
+    return EHI_OK;
+  }
+  size_t bytes = sizeof(float2) * (size_t)g.nf * g.nr * g.nsub;
   EHI_TRY(hipMemcpyAsync(s->ws + s->L.ghat, in_dev, bytes, hipMemcpyDeviceToDevice, s->stream),
           "load green");
   s->state = ehi::State::Green;

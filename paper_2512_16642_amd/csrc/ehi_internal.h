@@ -19,6 +19,8 @@ constexpr int kMaxSponge = 512;  // largest absorbing-layer width (cells)
 constexpr int kHerkTile = 32;    // Hessian output tile (rows = cols)
 constexpr int kHerkSplitMax = 64;  // max split-K partitions of the grid sum
 constexpr size_t kAlign = 256;
+constexpr int kMaxDecim = 64;    // largest time-axis resampling factor
+constexpr int kMaxDecimK = 512;  // largest half-length of its low-pass filter
 
 __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 __host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
@@ -38,6 +40,14 @@ struct Geometry {
   int split_bf16;  // 1: split-BF16 contraction, 0: plain FP32
   int weighting;   // EHI_WEIGHT_LONG_RECORD or EHI_WEIGHT_FINITE_RECORD
   int keep_z, keep_x;  // leading DCT-II coefficients kept along z and x of the subgrid (0 = no transform)
+  int gh_rows;     // receivers per frequency held in the spectra buffer: nr, or nrb when compressed
+  // time-axis resampling of the finite-record weighting (decim = 1: every sample)
+  int decim;       // D: every D-th filtered sample is kept
+  int dK;          // filter half-length (taps j = -dK..dK)
+  int dM;          // kept samples: n_q = 1 - dK + q D, q = 0..dM-1 (support meets the record)
+  int dqa, dqb;    // kept samples inside the record (1 <= n_q <= nt): q in [dqa, dqb]
+  int dhist;       // samples of the previous window kept for the filter (2 dK)
+  int drows;       // rows of the kept-sample buffer per receiver (most kept samples one window yields)
   int tblock;      // time levels per marching launch (2, 4 or 8; divides chunk)
   int seg_rows;    // output rows per marching segment
   int band;        // columns per marching workgroup (256, 384, 448 or 512)
@@ -60,11 +70,17 @@ struct Layout {
   size_t u0, u1;    // float [nrb][Zp][Xp]  (ping-pong)
   size_t w0, w1;    // float [nrb][Zp][Xp]  (ping-pong)
   size_t stage;     // float [windows][nrb][chunk][nsub_p]
-  size_t ghat;      // float2 [nf][nr][nsub]
+  size_t ghat;      // float2 [nf][gh_rows][nsub]  (compressed: one receiver batch's spectra)
   size_t hpart;     // float2 [split][nf][nr][nr]
   size_t hpart64;   // double2 [split][nf][nr][nr]  finite-record partial sums (else empty)
+  size_t r2scale;   // double [nf]  finite-record Gram scale: 1/nt, or (D / H(w))^2 D / nt when resampled
+  size_t gscale;    // double [nf]  D / H(w): the resampled running spectra to the record's spectra
+  size_t dtaps;     // float [2 dK + 1]  resampling filter
+  size_t dtw;       // float2 [dM][nf]  exp(-i w n_q dt) at the kept samples
+  size_t dhistbuf;  // float [nrb][dhist][nsub_p]  last samples of the previous window
+  size_t ddec;      // float [nrb][drows][nsub_p]  kept (filtered) samples of the current window
   size_t dctz, dctx;  // complex64 [keep_z][nzs], [keep_x][nxs] DCT-II rows (compression only)
-  size_t dtmp;      // complex64 [nf][nr][nxs][keep_z]  first pass of the 2D transform
+  size_t dtmp;      // complex64 [nf][gh_rows][nxs][keep_z]  first pass of the 2D transform
   size_t gcomp;     // complex64 [nf][nr][keep_z * keep_x]  compressed spectra
   size_t hhat;      // double2 [nf][nr][nr]
   size_t qhat;      // double2 [nf][nr][nr]   Hhat + mu I (Hermitian, full)
@@ -207,14 +223,26 @@ hipError_t launch_dft_chunk(const Geometry& g, const float* stage, const float2*
 hipError_t launch_herk_fp32(const Geometry& g, const float2* ghat, float2* hpart, hipStream_t st);
 hipError_t launch_herk_split_bf16(const Geometry& g, const float2* ghat, float2* hpart,
                                   hipStream_t st);
+// the Gram of the running spectra enters the sums for steps gram_lo..gram_hi
+// of the launch (every step without resampling)
 hipError_t launch_herk_r2_chunk(const Geometry& g, const float* stage, const float2* tw,
-                                const float2* ghat, int n0, int cnt, bool first, double2* hpart64,
-                                hipStream_t st);
-hipError_t launch_herk_r2_reduce(const Geometry& g, const double2* hpart64, double2* hhat,
+                                const float2* ghat, int n0, int cnt, bool first, int gram_lo, int gram_hi,
+                                double2* hpart64, hipStream_t st);
+hipError_t launch_herk_r2_reduce(const Geometry& g, const double2* hpart64, const double* scale, double2* hhat,
                                  hipStream_t st);
+// time-axis resampling (finite-record weighting)
+hipError_t launch_decimate(const Geometry& g, const float* stage, const float* hist, const float* taps, int q0,
+                           int cnt, int n_w0, int n_end, int nrb_now, float* dec, hipStream_t st);
+hipError_t launch_hist_copy(const Geometry& g, const float* stage, int n_end, int nrb_now, float* hist,
+                            hipStream_t st);
+hipError_t launch_twiddles_at(int count, int nf, double dt, const double* freq, int n_first, int n_step,
+                              float2* tw, hipStream_t st);
+hipError_t launch_scale_spectra(const Geometry& g, const double* scale, float2* ghat, hipStream_t st);
 hipError_t launch_dct_matrix(int n, int keep, float2* d, hipStream_t st);
-hipError_t launch_dct_compress(const Geometry& g, const float2* ghat, const float2* dz, const float2* dx,
-                               float2* tmp, float2* gcomp, hipStream_t st);
+// compressed spectra of nrows receivers: input rows f * rows_per_f + i, output
+// rows f * nr + row0 + i of gcomp (tmp: [nf][nrows][nxs][keep_z])
+hipError_t launch_dct_compress(const Geometry& g, const float2* ghat, int rows_per_f, int row0, int nrows,
+                               const float2* dz, const float2* dx, float2* tmp, float2* gcomp, hipStream_t st);
 hipError_t launch_herk_reduce(const Geometry& g, const float2* hpart, double2* hhat,
                               hipStream_t st);
 int herk_whole_groups(int nr);  // workgroups per (frequency, partition) of the whole-matrix contraction

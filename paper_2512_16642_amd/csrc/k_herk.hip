@@ -497,7 +497,7 @@ __global__ void __launch_bounds__(512)
 // All receivers must be stepped together.
 __global__ void __launch_bounds__(256)
     k_herk_r2(Geometry g, const float* __restrict__ stage, const float2* __restrict__ tw,
-              const float2* __restrict__ ghat, int n0, int cnt, int first,
+              const float2* __restrict__ ghat, int n0, int cnt, int first, int gram_lo, int gram_hi,
               double2* __restrict__ hpart64) {
   __shared__ double acc_s[32][256];  // per lane: [a][b][re/im][v] FP64 sums
   // work: the 32 x 32 block pairs (bi <= bj) of the upper triangle, four to a
@@ -582,13 +582,19 @@ __global__ void __launch_bounds__(256)
       for (int u = 0; u < 4; ++u) {
         const float gv[8] = {q[u][0][0], q[u][0][1], q[u][0][2], q[u][0][3],
                              q[u][1][0], q[u][1][1], q[u][1][2], q[u][1][3]};
-        unsigned wd[4][4];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const float x = gv[e];
           S[u][e].x = fmaf(w.x, x, S[u][e].x);
           S[u][e].y = fmaf(w.y, x, S[u][e].y);
         }
+      }
+      // kept samples before or after the record advance the running spectra
+      // only (wave-uniform)
+      if (t < gram_lo || t > gram_hi) return;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        unsigned wd[4][4];
 #pragma unroll
         for (int e = 0; e < 8; e += 2) {
           const float2 z0 = S[u][e], z1 = S[u][e + 1];
@@ -629,7 +635,7 @@ __global__ void __launch_bounds__(256)
           grp[a][b][1] += m;
         }
       }
-      if ((t & 15) == 15 || t == cnt - 1) {
+      if ((t & 15) == 15 || t == min(cnt - 1, gram_hi)) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -667,8 +673,8 @@ __global__ void __launch_bounds__(256)
       }
 }
 
-// hhat = (1/nt) sum_ks hpart64[ks] (FP64, ascending ks), mirrored, Im(diag) = 0.
-__global__ void k_herk_r2_reduce(Geometry g, const double2* __restrict__ hpart64,
+// hhat = scale[f] sum_ks hpart64[ks] (FP64, ascending ks), mirrored, Im(diag) = 0.
+__global__ void k_herk_r2_reduce(Geometry g, const double2* __restrict__ hpart64, const double* __restrict__ scale,
                                  double2* __restrict__ hhat) {
   const int f = blockIdx.y;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -681,8 +687,8 @@ __global__ void k_herk_r2_reduce(Geometry g, const double2* __restrict__ hpart64
     sr += v.x;
     si += v.y;
   }
-  sr /= (double)g.nt;
-  si /= (double)g.nt;
+  sr *= scale[f];
+  si *= scale[f];
   double2* H = hhat + (size_t)f * g.nr * g.nr;
   if (i == j) {
     H[(size_t)i * g.nr + i] = make_double2(sr, 0.0);
@@ -757,20 +763,20 @@ hipError_t launch_herk_split_bf16(const Geometry& g, const float2* ghat, float2*
 }
 
 hipError_t launch_herk_r2_chunk(const Geometry& g, const float* stage, const float2* tw,
-                                const float2* ghat, int n0, int cnt, bool first, double2* hpart64,
-                                hipStream_t st) {
+                                const float2* ghat, int n0, int cnt, bool first, int gram_lo, int gram_hi,
+                                double2* hpart64, hipStream_t st) {
   const int nb32 = cdiv(g.nr, 32);
   const long long items = (long long)cdiv(nb32 * (nb32 + 1) / 2, 4) * g.herk_split * g.nf;
   if (items > 0x7fffffffLL || cnt < 1 || cnt > g.chunk || g.nrb < g.nr) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_herk_r2, dim3((unsigned)items), dim3(256), 0, st, g, stage, tw, ghat, n0, cnt,
-                     first ? 1 : 0, hpart64);
+                     first ? 1 : 0, gram_lo, gram_hi, hpart64);
   return hipGetLastError();
 }
 
-hipError_t launch_herk_r2_reduce(const Geometry& g, const double2* hpart64, double2* hhat,
+hipError_t launch_herk_r2_reduce(const Geometry& g, const double2* hpart64, const double* scale, double2* hhat,
                                  hipStream_t st) {
   dim3 grid(cdiv(g.nr * g.nr, 256), g.nf);
-  hipLaunchKernelGGL(k_herk_r2_reduce, grid, dim3(256), 0, st, g, hpart64, hhat);
+  hipLaunchKernelGGL(k_herk_r2_reduce, grid, dim3(256), 0, st, g, hpart64, scale, hhat);
   return hipGetLastError();
 }
 

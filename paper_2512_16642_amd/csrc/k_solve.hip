@@ -626,28 +626,30 @@ hipError_t launch_apply(const Geometry& g, const float2* m32, const double2* qha
   return hipSuccess;
 }
 
-hipError_t launch_dct_compress(const Geometry& g, const float2* ghat, const float2* dz, const float2* dx,
-                               float2* tmp, float2* gcomp, hipStream_t st) {
+hipError_t launch_dct_compress(const Geometry& g, const float2* ghat, int rows_per_f, int row0, int nrows,
+                               const float2* dz, const float2* dx, float2* tmp, float2* gcomp, hipStream_t st) {
   // per spectrum row (frequency, receiver), seen as an nzs x nxs image:
   //   T(ix, kz) = sum_iz Dz(kz, iz) G(iz, ix),  stored [row][ix][kz]
   //   C(kz, kx) = sum_ix Dx(kx, ix) T(ix, kz),  stored [row][kz][kx]
-  // (complex64 operands, products and sums in FP64)
-  const int rows = g.nf * g.nr;
-  for (int r0 = 0; r0 < rows; r0 += 65535) {
-    const int nb = std::min(65535, rows - r0);
+  // (complex64 operands, products and sums in FP64).  Input rows
+  // f * rows_per_f + i, i < nrows; output rows f * nr + row0 + i.
+  if (nrows < 1 || nrows > 65535 || row0 < 0 || row0 + nrows > g.nr) return hipErrorInvalidValue;
+  for (int f = 0; f < g.nf; ++f) {
+    float2* t = tmp + (size_t)f * nrows * g.nxs * g.keep_z;
     GemmArgs p{};
     p.A = dz; p.sA = 0; p.lda = g.nzs; p.arows = g.keep_z;
-    p.B = ghat + (size_t)r0 * g.nsub; p.sB = (size_t)g.nsub; p.ldb = g.nxs;
+    p.B = ghat + (size_t)f * rows_per_f * g.nsub; p.sB = (size_t)g.nsub; p.ldb = g.nxs;
     p.n = g.keep_z; p.ns = g.nxs; p.kdim = g.nzs;
-    p.C = tmp + (size_t)r0 * g.nxs * g.keep_z; p.sC = (size_t)g.nxs * g.keep_z; p.ldc = g.keep_z;
-    hipError_t e = run_gemm<float, 0, kEpiStore, 1, double>(p, nb, st);
+    p.C = t; p.sC = (size_t)g.nxs * g.keep_z; p.ldc = g.keep_z;
+    hipError_t e = run_gemm<float, 0, kEpiStore, 1, double>(p, nrows, st);
     if (e != hipSuccess) return e;
     GemmArgs q{};
     q.A = dx; q.sA = 0; q.lda = g.nxs; q.arows = g.keep_x;
-    q.B = tmp + (size_t)r0 * g.nxs * g.keep_z; q.sB = (size_t)g.nxs * g.keep_z; q.ldb = g.keep_z;
+    q.B = t; q.sB = (size_t)g.nxs * g.keep_z; q.ldb = g.keep_z;
     q.n = g.keep_x; q.ns = g.keep_z; q.kdim = g.nxs;
-    q.C = gcomp + (size_t)r0 * g.keep_z * g.keep_x; q.sC = (size_t)g.keep_z * g.keep_x; q.ldc = g.keep_x;
-    e = run_gemm<float, 0, kEpiStore, 1, double>(q, nb, st);
+    q.C = gcomp + ((size_t)f * g.nr + row0) * g.keep_z * g.keep_x; q.sC = (size_t)g.keep_z * g.keep_x;
+    q.ldc = g.keep_x;
+    e = run_gemm<float, 0, kEpiStore, 1, double>(q, nrows, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -30,7 +30,7 @@ _WEIGHT = {"long_record": WEIGHT_LONG_RECORD, "finite_record": WEIGHT_FINITE_REC
 # every symbol declared in include/ehi.h
 SYMBOLS = (
     "ehi_workspace_bytes", "ehi_create", "ehi_build_green", "ehi_build_hessian", "ehi_factor",
-    "ehi_apply_multipliers", "ehi_lambda_max", "ehi_copy_green_dft", "ehi_load_green_dft",
+    "ehi_apply_multipliers", "ehi_lambda_max", "ehi_copy_green_dft", "ehi_copy_compressed", "ehi_load_green_dft",
     "ehi_copy_hessian", "ehi_load_hessian", "ehi_copy_factor", "ehi_destroy", "ehi_last_error",
     "ehi_version", "ehi_profile_enable", "ehi_profile_read", "ehi_batch_workspace_bytes",
     "ehi_factor_batch", "ehi_factor_batch_static", "ehi_set_stream", "ehi_set_launch", "ehi_get_launch",
@@ -59,6 +59,7 @@ class SurveyDesc(ctypes.Structure):
         ("precision", ctypes.c_int32), ("max_ns", ctypes.c_int32), ("nr_batch", ctypes.c_int32),
         ("weighting", ctypes.c_int32), ("chunk", ctypes.c_int32),
         ("keep_z", ctypes.c_int32), ("keep_x", ctypes.c_int32), ("windows", ctypes.c_int32),
+        ("decim", ctypes.c_int32),
     ]
 
 
@@ -88,8 +89,8 @@ def lib() -> ctypes.CDLL:
     L.ehi_apply_multipliers.restype = st
     L.ehi_lambda_max.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.ehi_lambda_max.restype = st
-    for name in ("ehi_copy_green_dft", "ehi_load_green_dft", "ehi_copy_hessian", "ehi_load_hessian",
-                 "ehi_copy_factor"):
+    for name in ("ehi_copy_green_dft", "ehi_copy_compressed", "ehi_load_green_dft", "ehi_copy_hessian",
+                 "ehi_load_hessian", "ehi_copy_factor"):
         getattr(L, name).argtypes = [vp, vp]
         getattr(L, name).restype = st
     L.ehi_profile_enable.argtypes = [vp, ctypes.c_int]
@@ -164,7 +165,7 @@ def _require(t: torch.Tensor, dtype, shape, name: str, device: torch.device):
 
 
 def make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision, max_ns,
-              nr_batch, weighting="long_record", chunk=0, keep=(0, 0), windows=1):
+              nr_batch, weighting="long_record", chunk=0, keep=(0, 0), windows=1, decim=1):
     riz = np.ascontiguousarray(rec_iz, dtype=np.int32)
     rix = np.ascontiguousarray(rec_ix, dtype=np.int32)
     fr = np.ascontiguousarray(freqs_hz, dtype=np.float64)
@@ -177,7 +178,8 @@ def make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision
                    nf=len(fr), freq_hz=fr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                    precision=prec, max_ns=max_ns, nr_batch=nr_batch,
                    weighting=_WEIGHT[weighting] if isinstance(weighting, str) else int(weighting),
-                   chunk=int(chunk), keep_z=int(keep[0]), keep_x=int(keep[1]), windows=int(windows))
+                   chunk=int(chunk), keep_z=int(keep[0]), keep_x=int(keep[1]), windows=int(windows),
+                   decim=int(decim))
     return d, (riz, rix, fr)   # keep the arrays alive with the descriptor
 
 
@@ -195,7 +197,8 @@ class Survey:
     def __init__(self, *, nz: int, nx: int, nb: int, h: float, dt: float, nt: int, stride: int,
                  rec_iz: Sequence[int], rec_ix: Sequence[int], freqs_hz: Sequence[float],
                  precision="split_bf16", max_ns: int = 256, nr_batch: int = 0,
-                 weighting="long_record", chunk: int = 0, keep=(0, 0), windows: int = 1, device=None,
+                 weighting="long_record", chunk: int = 0, keep=(0, 0), windows: int = 1, decim: int = 1,
+                 device=None,
                  stream: Optional[torch.cuda.Stream] = None):
         self._h = None
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
@@ -206,8 +209,9 @@ class Survey:
         self.precision = precision
         self.max_ns = max_ns
         self.nr_batch = nr_batch
-        d, keep = make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision,
-                            max_ns, nr_batch, weighting, chunk, keep, windows)
+        self.keep = (int(keep[0]), int(keep[1]))
+        d, _alive = make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision,
+                              max_ns, nr_batch, weighting, chunk, keep, windows, decim)
         self.weighting = weighting
         L = lib()
         nbytes = L.ehi_workspace_bytes(ctypes.byref(d))
@@ -320,6 +324,13 @@ class Survey:
     def copy_green_dft(self) -> torch.Tensor:
         out = torch.empty((self.nf, self.nr, self.nzs, self.nxs), dtype=torch.complex64, device=self.device)
         _check(lib().ehi_copy_green_dft(self._h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def copy_compressed(self) -> torch.Tensor:
+        """Compressed spectra of a compressed survey: complex64 [nf][nr][keep_z][keep_x]."""
+        kz, kx = self.keep
+        out = torch.empty((self.nf, self.nr, kz, kx), dtype=torch.complex64, device=self.device)
+        _check(lib().ehi_copy_compressed(self._h, ctypes.c_void_p(out.data_ptr())))
         return out
 
     def load_green_dft(self, g: torch.Tensor):

@@ -152,3 +152,16 @@ def test_block_calls_validate_on_the_host(ehi):
     assert L.ehi_mdot(None, 10, 2, None, 1, 10, None, None) == ehi.EHI_EINVAL
     assert L.ehi_combine(None, 10, 2000, None, 1, 10, d, None, None) == ehi.EHI_EINVAL
     assert L.ehi_combine(None, 10, 1, None, 1, 0, d, None, None) == ehi.EHI_EINVAL
+
+
+def test_compressed_workspace_smaller():
+    from paper_2512_16642_amd import ehi as mod
+    import synth
+    s = synth.layered_1000x300()
+    kw = dict(nz=s.nz, nx=s.nx, nb=s.nb, h=s.h, dt=s.dt, nt=s.nt, stride=s.stride, rec_iz=s.rec_iz,
+              rec_ix=s.rec_ix, freqs_hz=s.freqs_hz, precision="split_bf16", max_ns=s.ns, nr_batch=50,
+              chunk=1024)
+    plain = mod.workspace_bytes(**kw)
+    comp = mod.workspace_bytes(**kw, keep=(38, 125))
+    print("workspace (50-receiver batches): uncompressed %.2f GB, compressed %.2f GB" % (plain / 1e9, comp / 1e9))
+    assert comp < plain

@@ -62,3 +62,27 @@ def test_compressed_end_to_end_plain_and_split(ehi):
     X = sv.apply_multipliers(torch.from_numpy(R).cuda()).cpu().numpy()
     sv.close()
     check(X, Xr, 1e-6, 1e-6, 2e-6, "compressed multipliers")
+
+
+def test_compressed_build_in_receiver_batches(ehi):
+    # build_green on a compressed survey transforms each receiver batch's
+    # spectra as soon as they are complete (batches of 3 and 2 receivers): the
+    # compressed spectra against the oracle's transform of its own spectra,
+    # the Hessian end to end; the full spectra are not held
+    s = synth.ragged()
+    keep = (9, 17)
+    v = s.velocity()
+    G = fd.green_dft(s, v)
+    Cref = hessian.compress_spectra(G, s.nzs, s.nxs, *keep)
+    Href = hessian.hessian_r1(Cref)
+    sv = ehi.survey_from(s, precision="split_bf16", keep=keep, nr_batch=3)
+    sv.build_green(torch.from_numpy(v).cuda())
+    sv.build_hessian()
+    C = sv.copy_compressed().reshape(s.nf, s.nr, -1).cpu().numpy()
+    H = sv.copy_hessian().cpu().numpy()
+    with pytest.raises(ehi.EhiError):
+        sv.copy_green_dft()
+    sv.close()
+    check(C, Cref, 5e-6, 5e-6, 2e-5, "compressed spectra, built in batches")
+    check(H, Href, 1e-5, 1e-5, 2e-5, "compressed Hhat end to end")
+

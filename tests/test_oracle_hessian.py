@@ -172,3 +172,87 @@ def test_compression_exact_with_all_coefficients_and_converges():
     for k in (2, 5):
         c = hessian.hessian_compressed(g, nzs, nxs, k, k)
         assert np.all(np.diagonal(c, axis1=1, axis2=2).real <= np.diagonal(full, axis1=1, axis2=2).real + 1e-12)
+
+
+# ---------------------------------------------------------------------------
+# time-axis resampling before the finite-record Hessian
+# ---------------------------------------------------------------------------
+
+def _response(h, dt, nfft=1 << 16):
+    # H(f) of the zero-phase taps h_{-K..K}, evaluated with numpy's FFT
+    K = (len(h) - 1) // 2
+    x = np.zeros(nfft)
+    x[:K + 1] = h[K:]
+    x[nfft - K:] = h[:K]
+    return np.fft.fftfreq(nfft, dt), np.fft.fft(x)
+
+
+def test_decimation_filter_response():
+    # passband (|f| <= f_max) within 5e-6 of one, stopband (|f| >= fs/D - f_max,
+    # everything that folds onto the passband) below 5e-6 (the 120 dB design)
+    dt, fmax = 0.8e-3, 15.0
+    for D in (2, 5, 10, 16):
+        h = hessian.decimation_filter(D, dt, fmax)
+        assert np.allclose(h, h[::-1]) and abs(h.sum() - 1.0) < 1e-12
+        f, H = _response(h, dt)
+        fs = 1.0 / dt
+        assert np.abs(H[np.abs(f) <= fmax] - 1.0).max() < 5e-6, D
+        assert np.abs(H[np.abs(f) >= fs / D - fmax]).max() < 5e-6, D
+    assert np.array_equal(hessian.decimation_filter(1, dt, fmax), np.ones(1))
+
+
+def test_decimate_matches_convolution():
+    rng = np.random.default_rng(11)
+    g = rng.standard_normal((2, 137, 3))
+    D = 5
+    h = hessian.decimation_filter(D, 1e-3, 20.0)
+    K = (len(h) - 1) // 2
+    y = hessian.decimate(g, D, h)
+    n, qa, qb = hessian.decimation_times(137, D, K)
+    for r in range(2):
+        for x in range(3):
+            full = np.convolve(g[r, :, x], h)            # full[i] = sum h[k] g[i - k], g index 0 = n 1
+            # y_q = sum_j h_j g(n_q + j) = full[n_q - 1 + K]  (h symmetric)
+            idx = n - 1 + K
+            ok = (idx >= 0) & (idx < len(full))
+            ref = np.where(ok, full[np.clip(idx, 0, len(full) - 1)], 0.0)
+            np.testing.assert_allclose(y[r, :, x], ref, rtol=1e-12, atol=1e-14)
+    assert n[qa] >= 1 and n[qb] <= 137 and (qa == 0 or n[qa - 1] < 1) and (qb == len(n) - 1 or n[qb + 1] > 137)
+    assert n[0] + K <= 1 + D - 1 and n[-1] - K <= 137      # every kept sample whose support meets the record
+
+
+def test_decimated_transform_matches_the_whole_record():
+    # (D / H(w)) sum_q y_q exp(-i w n_q dt) equals the DFT of the whole record
+    # up to the stopband's folding (5e-6 of the aliased content)
+    s = synth.micro(nz=30, nx=36, nb=6, nt=400, nr=2)
+    gt = fd.green_samples(s.velocity(), s.nb, s.h, s.dt, s.nt, s.rec_iz, s.rec_ix, 1).reshape(2, s.nt, -1)
+    G = fd.dft(gt, s.freqs_hz, s.dt)
+    for D in (2, 10):
+        h = hessian.decimation_filter(D, s.dt, max(s.freqs_hz))
+        K = (len(h) - 1) // 2
+        y = hessian.decimate(gt, D, h)
+        n, _, _ = hessian.decimation_times(s.nt, D, K)
+        for f, fr in enumerate(s.freqs_hz):
+            w = 2 * math.pi * fr
+            Hw = np.real(np.sum(h * np.exp(-1j * w * np.arange(-K, K + 1) * s.dt)))
+            Gd = (D / Hw) * np.einsum("q,rqx->rx", np.exp(-1j * w * n * s.dt), y)
+            assert np.linalg.norm(Gd - G[f]) <= 1e-6 * np.linalg.norm(G[f]), (D, f)
+
+
+def test_decimated_hessian_reduces_to_r2():
+    g = _rand_g(nr=3, nt=40, nsub=6, seed=4)
+    freqs = (3.0, 7.0, 11.0)
+    a = hessian.hessian_r2_decimated(g, freqs, 1e-3, 1)
+    b = hessian.hessian_r2(g, freqs, 1e-3)
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-13 * np.abs(b).max())
+    # on a Green-function record, keeping every 5th sample changes the
+    # time average by the resampling's approximation only (recorded: ~5e-3)
+    s = synth.micro(nz=30, nx=36, nb=6, nt=400, nr=3)
+    gt = fd.green_samples(s.velocity(), s.nb, s.h, s.dt, s.nt, s.rec_iz, s.rec_ix, 1).reshape(3, s.nt, -1)
+    full = hessian.hessian_r2(gt, s.freqs_hz, s.dt)
+    dec = hessian.hessian_r2_decimated(gt, s.freqs_hz, s.dt, 5)
+    err = max(np.linalg.norm(dec[f] - full[f]) / np.linalg.norm(full[f]) for f in range(len(s.freqs_hz)))
+    print("decimated (D = 5) vs whole-record finite-record Hessian", err)
+    assert err < 5e-2
+    for f in range(len(s.freqs_hz)):
+        np.testing.assert_allclose(dec[f], dec[f].conj().T, atol=1e-12 * np.abs(dec[f]).max())
