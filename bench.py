@@ -49,7 +49,7 @@ def parse():
                          "accuracy test on the 1000 x 300 survey) or randomized (one receiver per "
                          "subset, factors reused over iterations, on the 1000 x 300 survey)")
     ap.add_argument("--batch-nt", type=int, default=4000, help="time steps of the batch8 surveys")
-    ap.add_argument("--staging-gb", type=float, default=6.0,
+    ap.add_argument("--staging-gb", type=float, default=64.0,
                     help="batch8: staging budget per survey (sets the receivers stepped together)")
     ap.add_argument("--batch-chunk", type=int, default=256, choices=[256, 512, 1024],
                     help="batch8: time samples per staging window")
@@ -669,9 +669,21 @@ def main():
                                 "executed_tflops": herk_exec, "executed_frac": round(herk_exec / 2500.0, 4)}
     if dft_ms > 0:
         dft_tf = dft_flops / (dft_ms / 1e3) / 1e12
-        out["roofline_dft"] = {"kernel": "k_dft_mfma", "bound": "mfma", "achieved": round(dft_tf, 2),
-                               "peak": 157.3, "unit": "TFLOP/s", "frac": round(dft_tf / 157.3, 4),
-                               "hbm_frac": round(dft_bytes / (dft_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        dft_gbs = dft_bytes / (dft_ms / 1e3) / 1e9
+        if os.environ.get("EHI_DFT_FORM") == "0":
+            # FP32 matrix cores: 4 flops per sample and frequency at 32 flop/B,
+            # bound by the FP32 matrix peak and the HBM together
+            out["roofline_dft"] = {"kernel": "k_dft_mfma (FP32 matrix cores)", "bound": "mfma",
+                                   "achieved": round(dft_tf, 2), "peak": 157.3, "unit": "TFLOP/s",
+                                   "frac": round(dft_tf / 157.3, 4), "hbm_frac": round(dft_gbs / HBM_PEAK_GBS, 4)}
+        else:
+            # three-part BF16 products (six per product) leave the BF16 matrix
+            # cores at a fraction of their peak: the staged samples' bytes bound it
+            out["roofline_dft"] = {"kernel": "k_dft_bf16x3 (three-part BF16 on the BF16 matrix cores)",
+                                   "bound": "hbm", "achieved": round(dft_gbs, 1), "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": round(dft_gbs / HBM_PEAK_GBS, 4),
+                                   "bytes_per_survey": dft_bytes, "useful_tflops": round(dft_tf, 2),
+                                   "bf16_mfma_frac": round(dft_tf * 6 / 2500.0, 4)}
     if not args.no_cpu_baseline:
         print("# timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_steps, args.cpu_hessians, args.cpu_receivers)

@@ -128,6 +128,13 @@ typedef enum {
  *             H(w) the filter's response; the spectra of ehi_copy_green_dft
  *             are Gt_last.  Requires EHI_WEIGHT_FINITE_RECORD, windows 1,
  *             1/(D dt) > 2 f_max, K <= 512 and 2K <= chunk, D <= chunk / 2.
+ *   herk_split  partitions of the grid sum in the contraction (0 = chosen
+ *             from the sizes; 1..64).  Changes the order of the FP32 partial
+ *             sums only (partitions are reduced in FP64 in a fixed order).
+ *   herk_form   split-BF16 final-spectrum contraction: 0 = chosen from the
+ *             sizes, 1 = whole-matrix form (every row of a grid stage staged
+ *             once per group of block pairs; nr <= 224), 2 = 64 x 64 tile
+ *             pairs.  Ignored by the other contractions.
  */
 typedef struct {
   int32_t nz, nx, nb;
@@ -147,6 +154,8 @@ typedef struct {
   int32_t keep_z, keep_x;
   int32_t windows;
   int32_t decim;
+  int32_t herk_split;
+  int32_t herk_form;
 } ehi_survey_desc;
 
 typedef struct ehi_survey ehi_survey;

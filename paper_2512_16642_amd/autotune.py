@@ -1,4 +1,4 @@
-"""Launch-shape autotuner for the Green-function stepping.
+"""Launch-shape autotuner for the Green-function stepping and the contraction.
 
 The marching kernel's time levels per launch trade HBM traffic against
 redundant halo work, and its rows per segment trade redundant halo rows against
@@ -7,6 +7,12 @@ receivers are stepped together.  ``tune`` times a short build (nt_probe steps)
 for each candidate pair on the real grid and receivers and caches the winner in
 a JSON file keyed by (padded grid, receivers per batch, arch).  Results never
 depend on the launch shape.
+
+``tune_contraction`` does the same for the Hessian contraction: the form
+(whole-matrix or tile pairs, split-BF16 final-spectrum surveys) and the number
+of grid partitions, timed on random spectra of the survey's sizes (receivers,
+subgrid points, frequencies).  The partition count changes only the order of
+FP32 partial sums, so results agree to rounding.
 """
 from __future__ import annotations
 
@@ -87,3 +93,47 @@ def apply(sv: "ehi.Survey", spec):
 
 def sv_nrb(sv, spec) -> int:
     return getattr(sv, "nr_batch", 0) or spec.nr
+
+
+HERK_SPLITS = (2, 4, 8, 12, 17, 24, 32, 48, 64)
+
+
+def _herk_key(spec, precision: str) -> str:
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "none"
+    return f"{arch}:herk:nr{spec.nr}:nsub{spec.nsub}:nf{spec.nf}:{precision}:v1"
+
+
+def tune_contraction(spec, precision: str = "split_bf16", repeats: int = 3) -> dict:
+    """Best (form, partitions) of the final-spectrum contraction for this
+    survey's sizes (cached).  form 1 = whole-matrix (up to 224 receivers),
+    2 = 64 x 64 tile pairs; the plain FP32 form has one kernel."""
+    key = _herk_key(spec, precision)
+    cache = _load()
+    if key in cache:
+        return cache[key]
+    forms = [0] if precision != "split_bf16" else ([1, 2] if spec.nr <= 224 else [2])
+    kmax = max(1, spec.nsub // 1024)
+    splits = sorted({s for s in HERK_SPLITS if s <= kmax} | {min(kmax, 64)})
+    probe = spec.with_(nt=8)
+    g = torch.randn((spec.nf, spec.nr, spec.nzs, spec.nxs), dtype=torch.complex64, device="cuda")
+    times = {}
+    for form in forms:
+        for split in splits:
+            sv = ehi.survey_from(probe, precision=precision, max_ns=1, nr_batch=1, herk_split=split,
+                                 herk_form=form)
+            sv.load_green_dft(g)
+            sv.build_hessian()           # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(repeats):
+                sv.build_hessian()
+            torch.cuda.synchronize()
+            times[(form, split)] = (time.perf_counter() - t0) / repeats
+            sv.close()
+    del g
+    best = min(times, key=times.get)
+    entry = {"herk_form": best[0], "herk_split": best[1],
+             "probe_ms": {f"{k[0]}x{k[1]}": round(v * 1e3, 4) for k, v in times.items()}}
+    cache[key] = entry
+    _store(cache)
+    return entry

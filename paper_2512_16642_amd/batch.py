@@ -27,9 +27,14 @@ class SurveyBatch:
         self.streams = [torch.cuda.Stream(self.device) for _ in self.specs]
         for spec, st in zip(self.specs, self.streams):
             nrb = staging_receivers(spec, staging_budget_bytes, chunk)
-            sv = ehi.survey_from(spec, precision=precision, nr_batch=nrb, stream=st, chunk=chunk)
-            if tune:
-                autotune.apply(sv, spec)
+            # launch shapes are tuned on a short probe before the survey's own
+            # workspace is allocated (the probe needs a workspace of its own)
+            shape = autotune.tune(spec, nrb=nrb) if tune else None
+            herk = autotune.tune_contraction(spec, precision) if tune else {"herk_form": 0, "herk_split": 0}
+            sv = ehi.survey_from(spec, precision=precision, nr_batch=nrb, stream=st, chunk=chunk,
+                                 herk_form=herk["herk_form"], herk_split=herk["herk_split"])
+            if shape is not None:
+                sv.set_launch(shape["tblock"], shape["seg_rows"], shape.get("band", 0))
             self.surveys.append(sv)
         self.graph: Optional[torch.cuda.CUDAGraph] = None
         self._vels = None

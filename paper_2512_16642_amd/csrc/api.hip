@@ -132,6 +132,9 @@ bool validate(const ehi_survey_desc* d, std::string* why) {
       return bad("spatial compression applies to the final-spectrum contraction only");
   }
   if (d->windows < 0 || d->windows > 2) return bad("windows must be 0, 1 or 2");
+  if (d->herk_split < 0 || d->herk_split > ehi::kHerkSplitMax) return bad("herk_split must be in [0, 64]");
+  if (d->herk_form < 0 || d->herk_form > 2) return bad("herk_form must be 0, 1 or 2");
+  if (d->herk_form == 1 && d->nr > 224) return bad("the whole-matrix contraction holds at most 224 receivers");
   if (d->decim < 0 || d->decim > ehi::kMaxDecim) return bad("decim must be in [0, 64]");
   if (d->decim >= 2) {
     if (d->weighting != EHI_WEIGHT_FINITE_RECORD)
@@ -180,6 +183,13 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   // compressed surveys hold one receiver batch's spectra at a time: each batch
   // is transformed into the compressed spectra as soon as its DFT is complete
   g.gh_rows = g.keep_z > 0 ? g.nrb : g.nr;
+  // the three-part BF16 DFT: FP32-equivalent operands, faster than the FP32
+  // matrix-core form and with half its element-wise error (measured)
+  g.dft_form = 1;
+  if (const char* e = std::getenv("EHI_DFT_FORM")) {
+    int v = std::atoi(e);
+    if (v == 0 || v == 1) g.dft_form = v;
+  }
   g.decim = 1;
   g.dK = 0;
   g.dM = d->nt;
@@ -207,8 +217,11 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   // about four full rounds of workgroups (a partial last round costs a round)
   g.herk_whole = (g.split_bf16 && g.weighting == EHI_WEIGHT_LONG_RECORD && g.nr <= 224) ? 1 : 0;
   if (g.herk_whole) want = std::max(1, 1024 / (g.nf * ehi::herk_whole_groups(g.nr)));
+  if (d->herk_form == 2) g.herk_whole = 0;
+  if (g.herk_whole == 0 && d->herk_form == 2) want = ehi::cdiv(2048, pairs * g.nf);
   int kmax = std::max(1, g.nsub / 1024);
   g.herk_split = std::max(1, std::min(want, std::min(ehi::kHerkSplitMax, kmax)));
+  if (d->herk_split > 0) g.herk_split = d->herk_split;
   g.tblock = 8;
   g.seg_rows = 256;  // measured best for the 1000 x 300 benchmark grid (1-2 % over 128)
   // tuning overrides (launch shapes only; results do not depend on them)

@@ -41,6 +41,7 @@ struct Geometry {
   int weighting;   // EHI_WEIGHT_LONG_RECORD or EHI_WEIGHT_FINITE_RECORD
   int keep_z, keep_x;  // leading DCT-II coefficients kept along z and x of the subgrid (0 = no transform)
   int gh_rows;     // receivers per frequency held in the spectra buffer: nr, or nrb when compressed
+  int dft_form;    // 0: FP32 matrix-core DFT; 1: three-part BF16 split on the BF16 matrix cores (default)
   // time-axis resampling of the finite-record weighting (decim = 1: every sample)
   int decim;       // D: every D-th filtered sample is kept
   int dK;          // filter half-length (taps j = -dK..dK)

@@ -451,6 +451,153 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT <= 
     }
 }
 
+// The same DFT on the BF16 matrix cores with FP32-equivalent operands: every
+// FP32 value x (staged sample or twiddle) is split into three BF16 parts,
+// x = hi + mid + lo + O(2^-24 x) (hi = bf16(x), mid = bf16(x - hi),
+// lo = bf16(x - hi - mid), round to nearest even), and a product is taken as
+// the six terms down to 2^-16 of its size (mid.mid, lo.hi, hi.lo, mid.hi,
+// hi.mid, hi.hi, smallest first); the three dropped terms are below 2^-24 of
+// it.  v_mfma_f32_16x16x32_bf16 contracts 32 samples per instruction, so the
+// six products cost less matrix-core time than the four 16x16x4 FP32 steps
+// they replace by a factor of about 2.7, which moves the kernel off the
+// matrix-core limit onto the HBM one.  Each 32-sample group's six products are
+// chained from zero and added to the running sum with an ordinary FP32 add
+// (the matrix core's own accumulation is biased over long chains).
+//
+// Operand layouts (16 x 16 x 32): lane l holds A[row l % 16][k 8 (l / 16) ..
+// + 7] and B[k 8 (l / 16) .. + 7][col l % 16]; the result D[4 (l / 16) + v]
+// [l % 16] as in the FP32 kernel, so the epilogue is the same.  Points are
+// mapped as there (tile j, column i <-> point 4i + j): a lane loads its eight
+// samples of four consecutive points as eight 16-byte loads.  The twiddle
+// stage in LDS holds the three BF16 planes [plane][row][sample] with rows
+// padded by 8 samples (16 B), so the 16 rows a half-wave reads land on
+// different banks.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kDft3Ks = 128;            // samples per LDS twiddle stage
+constexpr int kDft3Kp = kDft3Ks + 8;    // padded row (bf16 elements)
+
+__device__ __forceinline__ void split3(float x, __bf16& h, __bf16& m, __bf16& l) {
+  h = (__bf16)x;
+  const float r = x - (float)h;
+  m = (__bf16)r;
+  l = (__bf16)(r - (float)m);
+}
+
+template <int MT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+    k_dft_bf16x3(Geometry g, const float* __restrict__ stage, const float2* __restrict__ tw, int n0,
+                 int cnt, int first, int r0, float2* __restrict__ ghat) {
+  constexpr int MP = 16 * MT;
+  __shared__ __bf16 As[3][MP][kDft3Kp];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int r = blockIdx.y;
+  const int col = blockIdx.x * 256 + wave * 64 + 4 * (lane & 15);  // this lane's 4 grid points
+  const int kg = lane >> 4;                                          // sample octet of the lane
+  const __amdgpu_buffer_rsrc_t rs =
+      make_rsrc(stage + (size_t)r * g.chunk * g.nsub_p, (size_t)cnt * g.nsub_p * sizeof(float));
+  const int pitch = g.nsub_p * 4;
+  const int voff = 8 * kg * pitch + col * 4;
+  floatx4 acc[MT][4];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[mt][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int twoF = 2 * g.nf;
+  // the lane's eight samples (rows k32 + 8 kg + e) of its four points
+  auto load_b = [&](floatx4* b, int k32) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      b[e] = __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, (k32 + e) * pitch, 0));
+  };
+  const int ngrp = (cnt + 31) / 32;
+  floatx4 bnext[8];
+  load_b(bnext, 0);
+  for (int gi = 0; gi < ngrp; ++gi) {
+    const int k32 = gi * 32;
+    const int kl = k32 % kDft3Ks;
+    if (kl == 0) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < kDft3Ks * MP; e += 256) {
+        const int m = e / kDft3Ks, t = e % kDft3Ks;
+        float v = 0.f;
+        if (k32 + t < cnt && m < twoF) {
+          const float2 z = tw[(size_t)(n0 - 1 + k32 + t) * g.nf + (m >> 1)];
+          v = (m & 1) ? z.y : z.x;
+        }
+        __bf16 h, mm, l;
+        split3(v, h, mm, l);
+        As[0][m][t] = h;
+        As[1][m][t] = mm;
+        As[2][m][t] = l;
+      }
+      __syncthreads();
+    }
+    // B fragments per tile j and plane: the lane's eight samples of point 4i + j
+    // (split before the next group's loads reuse the sample registers)
+    bf16x8_t B[3][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      unsigned w[3][4];
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        __bf16 h0, m0, l0, h1, m1, l1;
+        split3(bnext[e][j], h0, m0, l0);
+        split3(bnext[e + 1][j], h1, m1, l1);
+        w[0][e >> 1] = __builtin_bit_cast(unsigned, bf16x2_t{h0, h1});
+        w[1][e >> 1] = __builtin_bit_cast(unsigned, bf16x2_t{m0, m1});
+        w[2][e >> 1] = __builtin_bit_cast(unsigned, bf16x2_t{l0, l1});
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) B[q][j] = __builtin_bit_cast(bf16x8_t, u32x4_t{w[q][0], w[q][1], w[q][2], w[q][3]});
+    }
+    if (gi + 1 < ngrp) load_b(bnext, k32 + 32);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int row = 16 * mt + (lane & 15);
+      bf16x8_t A[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) A[q] = *reinterpret_cast<const bf16x8_t*>(&As[q][row][kl + 8 * kg]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        floatx4 t = floatx4{0.f, 0.f, 0.f, 0.f};
+        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[1][j], t, 0, 0, 0);  // mid.mid
+        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2], B[0][j], t, 0, 0, 0);  // lo.hi
+        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[2][j], t, 0, 0, 0);  // hi.lo
+        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1], B[0][j], t, 0, 0, 0);  // mid.hi
+        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[1][j], t, 0, 0, 0);  // hi.mid
+        t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0], B[0][j], t, 0, 0, 0);  // hi.hi
+        acc[mt][j] += t;
+      }
+    }
+  }
+  // lane holds rows m = 16 mt + 4 (lane >> 4) + i, i.e. f = 8 mt + 2 (lane >> 4) + i / 2
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int f = 8 * mt + 2 * (lane >> 4) + h;
+      if (f >= g.nf) continue;
+      float2* out = ghat + ((size_t)f * g.nr + r0 + r) * g.nsub;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int x = col + j;
+        if (x < g.nsub) {
+          float2 v = make_float2(acc[mt][j][2 * h], acc[mt][j][2 * h + 1]);
+          if (!first) {
+            const float2 o = out[x];
+            v.x += o.x;
+            v.y += o.y;
+          }
+          out[x] = v;
+        }
+      }
+    }
+}
+
 }  // namespace
 
 // Row table for the current launch shape: entry ti of segment sg describes
@@ -575,6 +722,25 @@ hipError_t launch_dft_chunk(const Geometry& g, const float* stage, const float2*
   dim3 grid(cdiv(g.nsub, 256), nrb_now);
   const int fi = first ? 1 : 0;
   const int mt = cdiv(2 * g.nf, 16);
+  if (g.dft_form == 1) {
+#define EHI_DFT3(M)                                                                                \
+  hipLaunchKernelGGL(k_dft_bf16x3<M>, grid, dim3(256), 0, st, g, stage, tw, n0, cnt, fi, r0, ghat); \
+  break;
+    switch (mt) {
+      case 1: EHI_DFT3(1)
+      case 2: EHI_DFT3(2)
+      case 3: EHI_DFT3(3)
+      case 4: EHI_DFT3(4)
+      case 5:
+      case 6: EHI_DFT3(6)
+      case 7:
+      case 8: EHI_DFT3(8)
+      default:
+        return hipErrorInvalidValue;
+    }
+#undef EHI_DFT3
+    return hipGetLastError();
+  }
 #define EHI_DFT(M)                                                                             \
   hipLaunchKernelGGL(k_dft_mfma<M>, grid, dim3(256), 0, st, g, stage, tw, n0, cnt, fi, r0, ghat); \
   break;

@@ -59,7 +59,7 @@ class SurveyDesc(ctypes.Structure):
         ("precision", ctypes.c_int32), ("max_ns", ctypes.c_int32), ("nr_batch", ctypes.c_int32),
         ("weighting", ctypes.c_int32), ("chunk", ctypes.c_int32),
         ("keep_z", ctypes.c_int32), ("keep_x", ctypes.c_int32), ("windows", ctypes.c_int32),
-        ("decim", ctypes.c_int32),
+        ("decim", ctypes.c_int32), ("herk_split", ctypes.c_int32), ("herk_form", ctypes.c_int32),
     ]
 
 
@@ -165,7 +165,8 @@ def _require(t: torch.Tensor, dtype, shape, name: str, device: torch.device):
 
 
 def make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision, max_ns,
-              nr_batch, weighting="long_record", chunk=0, keep=(0, 0), windows=1, decim=1):
+              nr_batch, weighting="long_record", chunk=0, keep=(0, 0), windows=1, decim=1,
+              herk_split=0, herk_form=0):
     riz = np.ascontiguousarray(rec_iz, dtype=np.int32)
     rix = np.ascontiguousarray(rec_ix, dtype=np.int32)
     fr = np.ascontiguousarray(freqs_hz, dtype=np.float64)
@@ -179,7 +180,7 @@ def make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision
                    precision=prec, max_ns=max_ns, nr_batch=nr_batch,
                    weighting=_WEIGHT[weighting] if isinstance(weighting, str) else int(weighting),
                    chunk=int(chunk), keep_z=int(keep[0]), keep_x=int(keep[1]), windows=int(windows),
-                   decim=int(decim))
+                   decim=int(decim), herk_split=int(herk_split), herk_form=int(herk_form))
     return d, (riz, rix, fr)   # keep the arrays alive with the descriptor
 
 
@@ -198,7 +199,7 @@ class Survey:
                  rec_iz: Sequence[int], rec_ix: Sequence[int], freqs_hz: Sequence[float],
                  precision="split_bf16", max_ns: int = 256, nr_batch: int = 0,
                  weighting="long_record", chunk: int = 0, keep=(0, 0), windows: int = 1, decim: int = 1,
-                 device=None,
+                 herk_split: int = 0, herk_form: int = 0, device=None,
                  stream: Optional[torch.cuda.Stream] = None):
         self._h = None
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
@@ -211,7 +212,7 @@ class Survey:
         self.nr_batch = nr_batch
         self.keep = (int(keep[0]), int(keep[1]))
         d, _alive = make_desc(nz, nx, nb, h, dt, nt, stride, rec_iz, rec_ix, freqs_hz, precision,
-                              max_ns, nr_batch, weighting, chunk, keep, windows, decim)
+                              max_ns, nr_batch, weighting, chunk, keep, windows, decim, herk_split, herk_form)
         self.weighting = weighting
         L = lib()
         nbytes = L.ehi_workspace_bytes(ctypes.byref(d))

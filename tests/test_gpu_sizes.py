@@ -89,3 +89,21 @@ def test_factor_and_solve_from_given_hessian_sizes(ehi, nr):
     sv.close()
     check(Lg, L, 1e-12, 1e-12, 1e-11, f"nr={nr} FP64 factor")
     check(Xg, X, 2e-6, 2e-6, 4e-6, f"nr={nr} solve")
+
+
+@pytest.mark.parametrize("form,split", [(1, 1), (1, 7), (2, 3), (2, 12), (0, 64)])
+def test_hessian_contraction_shapes(ehi, form, split):
+    # every form and partition count the autotuner may choose: the same
+    # Hessian to rounding (partitions change only the order of FP32 partial
+    # sums), within the contraction's tolerance of the oracle
+    nr = 200
+    s = _survey(nr)
+    G, ref = _spectra(nr)
+    sv = ehi.survey_from(s, precision="split_bf16", nr_batch=8, herk_form=form, herk_split=split)
+    sv.load_green_dft(torch.from_numpy(G.reshape(NF, nr, NZ, NX)).cuda())
+    sv.build_hessian()
+    H = sv.copy_hessian().cpu().numpy()
+    sv.close()
+    check(H, ref, 2e-6, 2e-6, 4e-6, f"form {form} split {split} hessian")
+    for f in range(NF):
+        np.testing.assert_array_equal(H[f], H[f].conj().T)
