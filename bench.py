@@ -227,6 +227,118 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_compare(args):
+    """The chosen (split-BF16) and the plain FP32 form on one and the same
+    workspace allocation, built in turn in one process, so that both see the
+    same physical placement: survey time and multiplier solves/s of each."""
+    import torch
+
+    import synth
+    from paper_2512_16642_amd import ehi
+
+    s = synth.WORKLOADS["layered_1000x300"]()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    vel = torch.from_numpy(s.velocity()).to(dev)
+    R = torch.from_numpy(s.residuals()).to(dev)
+    X = torch.empty_like(R)
+    kw = dict(max_ns=s.ns, chunk=args.chunk)
+    need = max(ehi.workspace_bytes(nz=s.nz, nx=s.nx, nb=s.nb, h=s.h, dt=s.dt, nt=s.nt, stride=s.stride,
+                                   rec_iz=s.rec_iz, rec_ix=s.rec_ix, freqs_hz=s.freqs_hz, precision=p,
+                                   nr_batch=0, **kw)
+               for p in ("split_bf16", "plain_fp32"))
+    ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    res = {}
+    mu = None
+    for prec in ("split_bf16", "plain_fp32", "split_bf16"):
+        sv = ehi.survey_from(s, precision=prec, workspace=ws, **kw)
+        sv.build_green(vel)
+        sv.build_hessian()
+        if mu is None:
+            mu = 1e-3 * sv.lambda_max()
+        sv.factor(mu)
+        sv.apply_multipliers(R, out=X)
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        tb = ta = 0.0
+        sv.read_profile()
+        sv.profile(True)
+        for _ in range(args.steps):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(st)
+            sv.build_green(vel)
+            sv.build_hessian()
+            sv.factor(mu)
+            e[1].record(st)
+            sv.apply_multipliers(R, out=X)
+            e[2].record(st)
+            e[2].synchronize()
+            tb += e[0].elapsed_time(e[1])
+            ta += e[1].elapsed_time(e[2])
+        sv.profile(False)
+        prof = sv.read_profile()
+        sv.close()
+        key = prec if prec not in res else prec + "_again"
+        res[key] = {"s_per_survey": round(tb / args.steps / 1e3, 5),
+                    "solves_per_s": round(s.nf * s.ns / (ta / args.steps / 1e3), 1),
+                    "kernel_ms": {k: round(v[0] / args.steps, 3) for k, v in prof.items()}}
+        print(f"# {key}: {res[key]}", file=sys.stderr, flush=True)
+    out = {"metric": "chosen vs plain FP32 form on one workspace: s/survey and multiplier solves/s",
+           "value": res["split_bf16"]["s_per_survey"], "unit": "s/survey", "n_gpus": 1, "steps": args.steps,
+           "warmup": 1, "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic", "config": {"workload": s.name, "chunk": args.chunk}, "forms": res}
+    print(json.dumps(out), flush=True)
+
+
+def run_hbm_probe(args):
+    """The HBM rate plain streaming kernels reach for the access mixes of the
+    hot kernels (1 GiB per array): the practical ceiling for the stepping
+    kernel's mix (two planes read; two planes and the staged samples written)
+    and for the DFT's (reads)."""
+    import torch
+
+    from paper_2512_16642_amd import ehi
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    nbytes = 1 << 30
+    # the stepping kernel's launch per cell: u, w read and written (16 B) and
+    # 8 staged samples on the stride-2 subgrid (8 x 4 B x 75,000 / 410,400 =
+    # 5.85 B, 1.46 planes of 4 B)
+    efrac = 1.462
+    bufs = [torch.zeros(nbytes, dtype=torch.uint8, device=dev) for _ in range(4)]
+    bufs.append(torch.zeros(int(nbytes * 2), dtype=torch.uint8, device=dev))
+    grids = (2048, 4096, 8192, 16384)
+    sink = torch.zeros(max(grids) * 256 * 16, dtype=torch.uint8, device=dev)
+    mixes = {0: ("copy: 1 read + 1 write", 2.0), 1: ("read", 1.0), 2: ("2 reads + 2 writes", 4.0),
+             3: (f"2 reads + {2 + efrac:.3f} writes (the stepping kernel's mix)", 4.0 + efrac),
+             4: ("2 reads", 2.0)}
+    st = torch.cuda.current_stream()
+    res = {}
+    for mode, (label, mult) in mixes.items():
+        best = 0.0
+        per = {}
+        for gsz in grids:
+            for _ in range(3):
+                ehi.hbm_probe(mode, *bufs, e_frac=efrac, grid=gsz, sink=sink)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(20):
+                ehi.hbm_probe(mode, *bufs, e_frac=efrac, grid=gsz, sink=sink)
+            e1.record(st)
+            e1.synchronize()
+            tbs = mult * nbytes / (e0.elapsed_time(e1) / 20 / 1e3) / 1e12
+            per[gsz] = round(tbs, 3)
+            best = max(best, tbs)
+        res[label] = {"best_tb_s": round(best, 3), "by_grid": per}
+        print(f"# {label}: {per}", file=sys.stderr, flush=True)
+    out = {"metric": "HBM rate of plain streaming kernels by access mix", "value": res[mixes[3][0]]["best_tb_s"],
+           "unit": "TB/s", "n_gpus": 1, "steps": 20, "warmup": 3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "hbm-probe-1GiB-arrays"}, "mixes": res, "peak_tb_s": HBM_PEAK_GBS / 1e3}
+    print(json.dumps(out), flush=True)
+
+
 def run_serve(args):
     """Serving mix: Poisson arrivals (mean args.rate req/s, rng 2400) of rebuilds
     of the eight uneven surveys (probability args.p_build) and deblurs of
@@ -495,12 +607,12 @@ def run_accuracy(args):
 
 def main():
     args = parse()
-    if args.workload in ("batch8", "serve", "accuracy", "randomized"):
+    if args.workload in ("batch8", "serve", "accuracy", "randomized", "compare", "hbm_probe"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
         {"batch8": run_batch, "serve": run_serve, "accuracy": run_accuracy,
-         "randomized": run_randomized}[args.workload](args)
+         "randomized": run_randomized, "compare": run_compare, "hbm_probe": run_hbm_probe}[args.workload](args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "

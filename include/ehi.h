@@ -62,7 +62,8 @@ typedef enum {
   /* FP32 contraction, FP32 Cholesky, FP32 solves without refinement */
   EHI_PREC_PLAIN_FP32 = 0,
   /* split-BF16 (hi+lo) MFMA contraction with FP32 accumulation, FP64
-     Cholesky, FP32 triangular solves + 2 FP64 iterative-refinement steps */
+     Cholesky, FP32 triangular solves + FP64 iterative refinement (one step
+     by default, ehi_set_refinement) */
   EHI_PREC_SPLIT_BF16 = 1
 } ehi_precision;
 
@@ -131,10 +132,12 @@ typedef enum {
  *   herk_split  partitions of the grid sum in the contraction (0 = chosen
  *             from the sizes; 1..64).  Changes the order of the FP32 partial
  *             sums only (partitions are reduced in FP64 in a fixed order).
- *   herk_form   split-BF16 final-spectrum contraction: 0 = chosen from the
- *             sizes, 1 = whole-matrix form (every row of a grid stage staged
- *             once per group of block pairs; nr <= 224), 2 = 64 x 64 tile
- *             pairs.  Ignored by the other contractions.
+ *   herk_form   final-spectrum contraction: 0 = chosen from the sizes;
+ *             split-BF16: 1 = whole-matrix form (every row of a grid stage
+ *             staged once per group of block pairs; nr <= 224), 2 = 64 x 64
+ *             tile pairs; plain FP32: 0-2 = 64 x 64 tile pairs on the FP32
+ *             matrix cores, 3 = FP32 products on the vector units.  Ignored by
+ *             the other contractions.
  */
 typedef struct {
   int32_t nz, nx, nb;
@@ -223,6 +226,26 @@ ehi_status ehi_factor_batch(ehi_survey* const* surveys, int32_t n, const double*
  * must be serialised by the caller. */
 ehi_status ehi_factor_batch_static(ehi_survey* const* surveys, int32_t n, const double* mu,
                                    void* stream, int32_t* bad_survey, int32_t* bad_freq);
+
+/* Measurement aid (the roofline of the stepping kernel): a plain streaming
+ * kernel over device buffers of `bytes` bytes each (a multiple of 16), to
+ * measure the HBM rate the memory system delivers for an access mix.
+ * mode 0: c = a + a (copy-like, 1 read + 1 write); 1: read a (sums to sink);
+ * 2: read a, b, write c, d; 3: as 2 plus e over its first e_frac * bytes
+ * (0 <= e_frac <= 2; e holds that many bytes) (the stepping kernel's mix:
+ * u, w read; u, w and the staged samples written);
+ * 4: read a, b (sums to sink).  sink: device float4 [grid * 256] (modes 1
+ * and 4).  grid: workgroups of 256 threads (grid-stride loop).  Enqueued on
+ * stream; the caller times it. */
+ehi_status ehi_hbm_probe(int32_t mode, const void* a, const void* b, void* c, void* d, void* e, size_t bytes,
+                         double e_frac, int32_t grid, void* sink, void* stream);
+
+/* Refinement steps of ehi_apply_multipliers in the split-BF16 form (default
+ * 1; 0..4): each step forms r = R - Qhat X in FP64 (X kept in FP64) and adds
+ * the FP32 solve of r.  One step leaves an error of about (cond(Qhat) 2^-24)^2
+ * of the solution; more steps matter only for very ill-conditioned systems.
+ * EHI_EINVAL for steps > 0 in the plain FP32 form (no FP64 factors). */
+ehi_status ehi_set_refinement(ehi_survey* s, int32_t steps);
 
 /* Routes all later work of the survey to stream (a hipStream_t; NULL = the
  * default stream), e.g. to capture a build into a HIP graph or to run surveys

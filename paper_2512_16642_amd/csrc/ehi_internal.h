@@ -37,6 +37,7 @@ struct Geometry {
   int nt, nr, nf, nrb, max_ns;
   int herk_split;  // split-K partitions
   int herk_whole;  // 1: one workgroup per (frequency, partition) forms all of Hhat (nr <= 224)
+  int herk_form;   // descriptor request: 0 auto, 1 whole-matrix, 2 tile pairs, 3 plain form on vector units
   int split_bf16;  // 1: split-BF16 contraction, 0: plain FP32
   int weighting;   // EHI_WEIGHT_LONG_RECORD or EHI_WEIGHT_FINITE_RECORD
   int keep_z, keep_x;  // leading DCT-II coefficients kept along z and x of the subgrid (0 = no transform)
@@ -154,6 +155,7 @@ struct ehi_survey {
   bool medium;      // ca, bd hold a velocity model (build_green or set_medium)
   bool rec_distinct; // no two receivers share a cell (the marching modelling path applies)
   double mu;
+  int refine;       // FP64-residual refinement steps of each deblur
   ehi::Profiler prof;
   template <class T>
   T* ptr(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -289,5 +291,7 @@ hipError_t launch_cg_update(float* x, float* r, const float* p, const float* Ap,
 hipError_t launch_cg_direction(float* p, const float* r, const double* rr_new, const double* rr, int ns,
                                size_t len, hipStream_t st);
 hipError_t launch_c64_from_c128(const double2* in, float2* out, size_t n, hipStream_t st);
+hipError_t launch_stream_probe(int mode, const void* a, const void* b, void* c, void* d, void* e, size_t bytes,
+                               double e_frac, int grid, void* sink, hipStream_t st);
 
 }  // namespace ehi

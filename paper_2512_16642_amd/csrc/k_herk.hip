@@ -673,6 +673,126 @@ __global__ void __launch_bounds__(256)
       }
 }
 
+// Plain FP32 form on the FP32 matrix cores (v_mfma_f32_16x16x4f32): the same
+// 64 x 64 tile pairs (bi <= bj), XCD-aware work order and partitions as the
+// split-BF16 tile-pair kernel; a wave owns a 32 x 32 quarter as 2 x 2 tiles,
+// Re = A_i A_j^T + B_i B_j^T, Im = B_i A_j^T - A_i B_j^T with the FP32 real and
+// imaginary planes A, B.  Stages of 32 points of the 128 rows are
+// double-buffered in LDS as [point][row] planes (lane l of a 16 x 16 x 4 step
+// reads point k0 + l / 16 of row l % 16); each stage's products are chained
+// from zero and added to the running FP32 sum (the matrix core's accumulation
+// is biased over long chains).
+template <bool VEC>
+__global__ void __launch_bounds__(256)
+    k_herk_fp32_mfma(Geometry g, const float2* __restrict__ ghat, float2* __restrict__ hpart, int split) {
+  constexpr int RS = 2 * kBt + 4;                 // row stride of an LDS point row (words)
+  __shared__ float sre[2][kBk][RS];
+  __shared__ float sim[2][kBk][RS];
+  const int nblk = cdiv(g.nr, kBt);
+  const int npair = nblk * (nblk + 1) / 2;
+  const int n = blockIdx.x;
+  const int n8 = gridDim.x / kXcd * kXcd;
+  const int item = n < n8 ? (n % kXcd) * (n8 / kXcd) + n / kXcd : n;
+  int bi, bj;
+  {
+    int p = item % npair, i = 0;
+    while (p >= nblk - i) {
+      p -= nblk - i;
+      ++i;
+    }
+    bi = i;
+    bj = i + p;
+  }
+  const int ks = (item / npair) % split;
+  const int f = item / (npair * split);
+  const int kchunk = cdiv(cdiv(g.nsub, split), kBk) * kBk;
+  const int k0 = ks * kchunk;
+  const int k1 = min(g.nsub, k0 + kchunk);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const float2* G = ghat + (size_t)f * g.nr * g.nsub;
+  // load tasks: row lrow (0..127), points 16 (tid >> 7) .. + 15 of the stage
+  const int lrow = tid & (2 * kBt - 1);
+  const int grow = lrow < kBt ? bi * kBt + lrow : bj * kBt + (lrow - kBt);
+  const bool rowv = grow < g.nr;
+  const float2* Grow = G + (size_t)(rowv ? grow : 0) * g.nsub;
+  const int kofs = 16 * (tid >> 7);
+  float2 v[16];
+  auto gload = [&](int kb) {
+    const int k = kb + kofs;
+    if (VEC && rowv && k + 16 <= k1) {
+      // rows start 16-byte aligned (nsub even): eight 16-byte loads
+      const floatx4* src = reinterpret_cast<const floatx4*>(Grow + k);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const floatx4 q = src[e];
+        v[2 * e] = make_float2(q[0], q[1]);
+        v[2 * e + 1] = make_float2(q[2], q[3]);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = (rowv && k + e < k1) ? Grow[k + e] : make_float2(0.f, 0.f);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      sre[buf][kofs + e][lrow] = v[e].x;
+      sim[buf][kofs + e][lrow] = v[e].y;
+    }
+  };
+  floatx4 re[2][2], im[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) re[a][b] = im[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int nst = cdiv(k1 - k0, kBk);
+  if (nst > 0) {
+    gload(k0);
+    lstore(0);
+  }
+  __syncthreads();
+  const int fr = lane & 15, fk = lane >> 4;
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nst) gload(k0 + (st + 1) * kBk);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int ri = wi * 32 + a * 16 + fr;
+        const int rj = kBt + wj * 32 + b * 16 + fr;
+        floatx4 r = floatx4{0.f, 0.f, 0.f, 0.f}, m = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < kBk; kk += 4) {
+          const float ar = sre[buf][kk + fk][ri], ai = sim[buf][kk + fk][ri];
+          const float br = sre[buf][kk + fk][rj], bim = sim[buf][kk + fk][rj];
+          r = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, r, 0, 0, 0);
+          r = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bim, r, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, m, 0, 0, 0);
+          m = __builtin_amdgcn_mfma_f32_16x16x4f32(-ar, bim, m, 0, 0, 0);
+        }
+        re[a][b] += r;
+        im[a][b] += m;
+      }
+    if (st + 1 < nst) lstore(buf ^ 1);
+    __syncthreads();
+  }
+  // D[4 (lane / 16) + v][lane % 16] of tile (a, b)
+  float2* out = hpart + ((size_t)ks * g.nf + f) * g.nr * g.nr;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v4 = 0; v4 < 4; ++v4) {
+        const int i = bi * kBt + wi * 32 + a * 16 + 4 * (lane >> 4) + v4;
+        const int j = bj * kBt + wj * 32 + b * 16 + (lane & 15);
+        if (i < g.nr && j < g.nr) out[(size_t)i * g.nr + j] = make_float2(re[a][b][v4], im[a][b][v4]);
+      }
+}
+
 // hhat = scale[f] sum_ks hpart64[ks] (FP64, ascending ks), mirrored, Im(diag) = 0.
 __global__ void k_herk_r2_reduce(Geometry g, const double2* __restrict__ hpart64, const double* __restrict__ scale,
                                  double2* __restrict__ hhat) {
@@ -725,9 +845,21 @@ __global__ void k_herk_reduce(Geometry g, const float2* __restrict__ hpart, doub
 }  // namespace
 
 hipError_t launch_herk_fp32(const Geometry& g, const float2* ghat, float2* hpart, hipStream_t st) {
-  int ntile = cdiv(g.nr, T);
-  dim3 grid(ntile * (ntile + 1) / 2, g.nf, g.herk_split);
-  hipLaunchKernelGGL(k_herk_fp32, grid, dim3(256), 0, st, g, ghat, hpart, g.herk_split);
+  if (g.herk_form == 3) {
+    // FP32 products and sums on the vector units (16 x 16 threads per 32 x 32 tile)
+    int ntile = cdiv(g.nr, T);
+    dim3 grid(ntile * (ntile + 1) / 2, g.nf, g.herk_split);
+    hipLaunchKernelGGL(k_herk_fp32, grid, dim3(256), 0, st, g, ghat, hpart, g.herk_split);
+    return hipGetLastError();
+  }
+  const int nb = cdiv(g.nr, kBt);
+  const long long items = (long long)nb * (nb + 1) / 2 * g.herk_split * g.nf;
+  if (items > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (g.nsub % 2 == 0)
+    hipLaunchKernelGGL(k_herk_fp32_mfma<true>, dim3((unsigned)items), dim3(256), 0, st, g, ghat, hpart, g.herk_split);
+  else
+    hipLaunchKernelGGL(k_herk_fp32_mfma<false>, dim3((unsigned)items), dim3(256), 0, st, g, ghat, hpart,
+                       g.herk_split);
   return hipGetLastError();
 }
 

@@ -36,7 +36,7 @@ SYMBOLS = (
     "ehi_factor_batch", "ehi_factor_batch_static", "ehi_set_stream", "ehi_set_launch", "ehi_get_launch",
     "ehi_set_medium", "ehi_forward_subgrid", "ehi_backpropagate", "ehi_residual_spectra",
     "ehi_multipliers_to_time", "ehi_misfit", "ehi_cg_init", "ehi_cg_shift_dot", "ehi_cg_update",
-    "ehi_cg_direction", "ehi_mdot", "ehi_combine",
+    "ehi_cg_direction", "ehi_mdot", "ehi_combine", "ehi_hbm_probe", "ehi_set_refinement",
 )
 PROF_KINDS = ("setup", "step", "dft", "herk", "factor", "solve", "model")
 _PROF_N = 8
@@ -131,6 +131,10 @@ def lib() -> ctypes.CDLL:
     for name in ("ehi_cg_init", "ehi_cg_shift_dot", "ehi_cg_update", "ehi_cg_direction", "ehi_mdot",
                  "ehi_combine"):
         getattr(L, name).restype = st
+    L.ehi_set_refinement.argtypes = [vp, i32]
+    L.ehi_set_refinement.restype = st
+    L.ehi_hbm_probe.argtypes = [i32, vp, vp, vp, vp, vp, ctypes.c_size_t, ctypes.c_double, i32, vp, vp]
+    L.ehi_hbm_probe.restype = st
     L.ehi_destroy.argtypes = [vp]
     L.ehi_destroy.restype = st
     L.ehi_last_error.argtypes = []
@@ -199,7 +203,8 @@ class Survey:
                  rec_iz: Sequence[int], rec_ix: Sequence[int], freqs_hz: Sequence[float],
                  precision="split_bf16", max_ns: int = 256, nr_batch: int = 0,
                  weighting="long_record", chunk: int = 0, keep=(0, 0), windows: int = 1, decim: int = 1,
-                 herk_split: int = 0, herk_form: int = 0, device=None,
+                 herk_split: int = 0, herk_form: int = 0, workspace: Optional[torch.Tensor] = None,
+                 device=None,
                  stream: Optional[torch.cuda.Stream] = None):
         self._h = None
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
@@ -220,7 +225,15 @@ class Survey:
             raise EhiError(EHI_EINVAL, L.ehi_last_error().decode())
         self.workspace_bytes = int(nbytes)
         with torch.cuda.device(self.device):
-            raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            if workspace is not None:
+                # a caller-owned uint8 buffer (e.g. shared by surveys built in turn)
+                if workspace.dtype != torch.uint8 or workspace.device != self.device or not workspace.is_contiguous():
+                    raise ValueError("workspace must be a contiguous uint8 tensor on the survey's device")
+                if workspace.numel() < nbytes + 256:
+                    raise ValueError(f"workspace has {workspace.numel()} bytes, needs {nbytes + 256}")
+                raw = workspace
+            else:
+                raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
             off = (-raw.data_ptr()) % 256
             self._ws = raw
             self._ws_ptr = raw.data_ptr() + off
@@ -354,6 +367,10 @@ class Survey:
         _check(lib().ehi_copy_factor(self._h, ctypes.c_void_p(out.data_ptr())))
         return out
 
+    def set_refinement(self, steps: int):
+        """FP64-residual refinement steps of each deblur (split-BF16 form; default 1)."""
+        _check(lib().ehi_set_refinement(self._h, int(steps)))
+
     def set_stream(self, stream: Optional[torch.cuda.Stream]):
         """Route this survey's later work to ``stream`` (None = the default stream)."""
         _check(lib().ehi_set_stream(self._h, ctypes.c_void_p(0 if stream is None else stream.cuda_stream)))
@@ -486,3 +503,12 @@ def survey_from(spec, precision="split_bf16", max_ns=None, nr_batch=0, **kw) -> 
                   freqs_hz=spec.freqs_hz, precision=precision,
                   max_ns=max_ns if max_ns is not None else max(1, spec.ns),
                   nr_batch=nr_batch, **kw)
+
+
+def hbm_probe(mode: int, a: torch.Tensor, b=None, c=None, d=None, e=None, e_frac: float = 0.0,
+              grid: int = 8192, sink=None, stream: Optional[torch.cuda.Stream] = None):
+    """Enqueue one streaming probe launch (ehi_hbm_probe) over equally sized
+    uint8 device tensors a..e (unused ones may be None)."""
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+    _check(lib().ehi_hbm_probe(int(mode), ptr(a), ptr(b), ptr(c), ptr(d), ptr(e), ctypes.c_size_t(a.numel()),
+                               ctypes.c_double(e_frac), int(grid), ptr(sink), ctypes.c_void_p(_stream_ptr(stream))))

@@ -165,3 +165,15 @@ def test_compressed_workspace_smaller():
     comp = mod.workspace_bytes(**kw, keep=(38, 125))
     print("workspace (50-receiver batches): uncompressed %.2f GB, compressed %.2f GB" % (plain / 1e9, comp / 1e9))
     assert comp < plain
+
+
+def test_hbm_probe_argument_checks():
+    import ctypes
+    from paper_2512_16642_amd import ehi
+    L = ehi.lib()
+    p = ctypes.c_void_p(1)
+    assert L.ehi_hbm_probe(5, p, p, p, p, p, 1024, 0.0, 4, p, None) == ehi.EHI_EINVAL      # mode
+    assert L.ehi_hbm_probe(0, p, p, p, p, p, 1000, 0.0, 4, p, None) == ehi.EHI_EINVAL      # bytes % 16
+    assert L.ehi_hbm_probe(3, p, p, p, p, p, 1024, 2.5, 4, p, None) == ehi.EHI_EINVAL      # e_frac
+    assert L.ehi_hbm_probe(2, p, None, p, p, p, 1024, 0.0, 4, p, None) == ehi.EHI_EINVAL   # b missing
+    assert L.ehi_hbm_probe(1, p, p, p, p, p, 1024, 0.0, 0, p, None) == ehi.EHI_EINVAL      # grid

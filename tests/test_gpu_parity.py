@@ -7,7 +7,7 @@ Tolerances, derived from the arithmetic of each stage:
   * Hessian from given spectra: FP32 products, two-level FP32 accumulation and
     an FP64 reduction of the grid partitions: 2e-6.
   * Factor + solve from a given Hessian, split-BF16 mode: FP64 Cholesky, FP32
-    solves refined twice in FP64, output rounded to complex64: 2e-6.
+    solves refined once in FP64 (the default), output rounded to complex64: 2e-6.
   * End to end (split-BF16 mode): the multiplier target 1e-5.
 Beside each relative Frobenius bound, the largest element-wise difference is
 bounded relative to the largest reference entry of the frequency slice, and
@@ -290,3 +290,25 @@ def test_error_paths(ehi, tiny_ref):
         sv.apply_multipliers(R[:, :, :3].contiguous())
     with pytest.raises(TypeError):
         sv.apply_multipliers(R.to(torch.complex128))
+
+
+def test_refinement_steps(ehi, tiny_ref):
+    # no refinement leaves the FP32 solve's error (~cond x 2^-24); one step
+    # (the default) reaches the complex64 output's rounding, and a second one
+    # changes nothing above it
+    s = tiny_ref["s"]
+    out = {}
+    for steps in (0, 1, 2):
+        sv = ehi.survey_from(s, precision="split_bf16")
+        sv.load_hessian(dev(tiny_ref["H"]))
+        sv.factor(tiny_ref["mu"])
+        sv.set_refinement(steps)
+        out[steps] = sv.apply_multipliers(dev(tiny_ref["R"])).cpu().numpy()
+        sv.close()
+    check(out[1], tiny_ref["X"], 2e-6, 2e-6, 4e-6, "one refinement step")
+    check(out[2], tiny_ref["X"], 2e-6, 2e-6, 4e-6, "two refinement steps")
+    check(out[0], tiny_ref["X"], 1e-3, 1e-3, None, "no refinement")
+    sp = ehi.survey_from(s, precision="plain_fp32")
+    with pytest.raises(ehi.EhiError):
+        sp.set_refinement(1)
+    sp.close()

@@ -107,3 +107,17 @@ def test_hessian_contraction_shapes(ehi, form, split):
     check(H, ref, 2e-6, 2e-6, 4e-6, f"form {form} split {split} hessian")
     for f in range(NF):
         np.testing.assert_array_equal(H[f], H[f].conj().T)
+
+
+@pytest.mark.parametrize("form", [0, 3])
+def test_plain_contraction_forms(ehi, form):
+    # the plain FP32 form on the FP32 matrix cores (0) and on the vector units (3)
+    nr = 225
+    s = _survey(nr)
+    G, ref = _spectra(nr)
+    sv = ehi.survey_from(s, precision="plain_fp32", nr_batch=8, herk_form=form)
+    sv.load_green_dft(torch.from_numpy(G.reshape(NF, nr, NZ, NX)).cuda())
+    sv.build_hessian()
+    H = sv.copy_hessian().cpu().numpy()
+    sv.close()
+    check(H, ref, 2e-6, 2e-6, 4e-6, f"plain form {form} hessian")
