@@ -77,8 +77,8 @@ def parse():
     ap.add_argument("--reuse", type=int, default=5, help="randomized: iterations per selection")
     ap.add_argument("--iters", type=int, default=20, help="randomized: timed iterations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=512, help="FD steps in the CPU sample")
-    ap.add_argument("--cpu-receivers", type=int, default=32, help="Green functions in the CPU sample")
+    ap.add_argument("--cpu-steps", type=int, default=2048, help="FD steps in the CPU sample")
+    ap.add_argument("--cpu-receivers", type=int, default=64, help="Green functions in the CPU sample")
     ap.add_argument("--cpu-hessians", type=int, default=3, help="full-size Hessians in the CPU sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (a known-size kernel "

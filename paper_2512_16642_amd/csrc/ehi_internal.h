@@ -18,6 +18,11 @@ constexpr int kRowAlign = 64;    // padded row pitch is a multiple of 64 floats 
 constexpr int kMaxSponge = 512;  // largest absorbing-layer width (cells)
 constexpr int kHerkTile = 32;    // Hessian output tile (rows = cols)
 constexpr int kHerkSplitMax = 64;  // max split-K partitions of the grid sum
+// Default partitions hold at most this many 32-point stages: each partition
+// adds its stages into FP32 running sums, whose rounding error grows about
+// linearly with the number of stages added, and the low-frequency systems
+// amplify that error in the multipliers (partial sums are combined in FP64).
+constexpr int kHerkMaxStages = 40;
 constexpr size_t kAlign = 256;
 constexpr int kMaxDecim = 64;    // largest time-axis resampling factor
 constexpr int kMaxDecimK = 512;  // largest half-length of its low-pass filter

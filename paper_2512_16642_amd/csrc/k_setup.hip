@@ -48,11 +48,44 @@ __global__ void k_vmax(const float* __restrict__ vel, int n, uint32_t* __restric
 // distance into the absorbing layer.  Computed in FP64, rounded once:
 // ca[cell] = kappa / (12 h^2 a) on the padded plane (0 on the ghost ring) and
 // bd[d] = b / a for d = 0..nb (b/a depends on d only).
+//
+// ca is rounded stochastically, to the FP32 neighbour above or below with the
+// probabilities that make its expected value exact (the choice drawn from a
+// hash of the cell index, so it is reproducible).  Rounding to nearest would
+// give every cell of a constant-velocity layer the same relative error (up to
+// 2^-25): a uniformly perturbed medium whose phase error grows with travel
+// time, and the largest part of the Green functions' FP32 error at low
+// frequencies.  Dithered, the perturbation has zero mean and no coherent
+// effect.
 __device__ inline double sponge_eta(const Geometry& g, double vmax, int d) {
   if (g.nb <= 0 || d <= 0) return 0.0;
   double emax = 3.0 * vmax * log(1000.0) / (2.0 * g.nb * g.h);
   double r = (double)d / g.nb;
   return emax * r * r;
+}
+
+// 32-bit integer finaliser ("lowbias32", C. Wellons' hash-prospector
+// search): a bijection whose output bits are close to independent of the input.
+__device__ inline uint32_t cell_hash(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+
+// ce rounded to one of its two FP32 neighbours, the upper with probability
+// equal to ce's fractional position between them (exact values stay exact).
+__device__ inline float dithered_float(double ce, uint32_t key) {
+  const float c = (float)ce;
+  float lo = c, hi = c;
+  if ((double)c > ce) lo = nextafterf(c, 0.f);
+  else if ((double)c < ce) hi = nextafterf(c, __builtin_huge_valf());
+  else return c;
+  const double f = (ce - (double)lo) / ((double)hi - (double)lo);
+  const double r = (double)cell_hash(key) * (1.0 / 4294967296.0);
+  return r < f ? hi : lo;
 }
 
 __global__ void k_coefficients(Geometry g, const float* __restrict__ vel,
@@ -80,7 +113,7 @@ __global__ void k_coefficients(Geometry g, const float* __restrict__ vel,
   double eta = sponge_eta(g, vmax, max(dz, dx));
   double a = 1.0 + eta * g.dt * 0.5;
   double kappa = v * v * g.dt * g.dt;
-  ca[o] = (float)(kappa / (12.0 * g.h * g.h * a));
+  ca[o] = dithered_float(kappa / (12.0 * g.h * g.h * a), (uint32_t)o);
 }
 
 // tw[n-1][f] = exp(-i 2 pi f_hz n dt), n = 1..nt, evaluated in FP64.
