@@ -49,10 +49,12 @@ def parse():
                          "accuracy test on the 1000 x 300 survey) or randomized (one receiver per "
                          "subset, factors reused over iterations, on the 1000 x 300 survey)")
     ap.add_argument("--batch-nt", type=int, default=4000, help="time steps of the batch8 surveys")
-    ap.add_argument("--staging-gb", type=float, default=64.0,
+    ap.add_argument("--staging-gb", type=float, default=32.0,
                     help="batch8: staging budget per survey (sets the receivers stepped together)")
-    ap.add_argument("--batch-chunk", type=int, default=256, choices=[256, 512, 1024],
-                    help="batch8: time samples per staging window")
+    ap.add_argument("--batch-chunk", type=int, default=512, choices=[256, 512, 1024],
+                    help="batch8: time samples per staging window (the spectra are read and written "
+                         "once per window: 512 samples with 32 GB per survey measured 4-6 %% faster "
+                         "than 256 samples with every receiver at once, or 1024 with fewer)")
     ap.add_argument("--precision", default="split_bf16", choices=["split_bf16", "plain_fp32"])
     ap.add_argument("--weighting", default="long_record", choices=["long_record", "finite_record"],
                     help="Fourier-diagonal weighting: final-spectrum Gram (default) or the finite-record W")
