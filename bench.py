@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -34,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_SOURCE = ("not measured in this run: the counters of a separate rocprofv3 --pmc collection of "
                   "the same launch shape, profiles/survey_layered-1000x300_pmc.md")
 MEASURED_TRAFFIC = {
-    ("layered-1000x300-nr200-nt4000-nf30-ns200", "split_bf16", 8, 256, 256, 200): (417499.0 * 2 + 1150910.0) * 1024,
+    ("layered-1000x300-nr200-nt4000-nf30-ns200", "split_bf16", 8, 256, 256, 200): (417525.2 * 2 + 1151201.7) * 1024,
 }
 
 
@@ -79,8 +81,9 @@ def parse():
     ap.add_argument("--reuse", type=int, default=5, help="randomized: iterations per selection")
     ap.add_argument("--iters", type=int, default=20, help="randomized: timed iterations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2048, help="FD steps in the CPU sample")
-    ap.add_argument("--cpu-receivers", type=int, default=64, help="Green functions in the CPU sample")
+    ap.add_argument("--cpu-receivers", type=int, default=64,
+                    help="Green functions in the CPU sample (each over the whole record; all of them "
+                         "makes the sample the oracle's whole survey, multipliers compared too)")
     ap.add_argument("--cpu-hessians", type=int, default=3, help="full-size Hessians in the CPU sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (a known-size kernel "
@@ -88,20 +91,45 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(s, fd_steps, n_hess=1, fd_receivers=32):
+def _errors(a, b, rows=False):
+    """Per frequency (axis 0): relative Frobenius error of a against b, the
+    largest element-wise difference against b's largest entry, and (rows) the
+    same per row of axis 1 against that row's largest entry."""
+    fr, el, rw = [], [], []
+    for f in range(b.shape[0]):
+        d = (a[f] - b[f]).reshape(b.shape[1], -1)
+        r = b[f].reshape(b.shape[1], -1)
+        fr.append(float(np.linalg.norm(d) / np.linalg.norm(r)))
+        el.append(float(np.abs(d).max() / np.abs(r).max()))
+        if rows:
+            rw.append(float((np.abs(d).max(axis=1) / np.abs(r).max(axis=1)).max()))
+    out = {"frob": [float(f"{x:.3e}") for x in fr], "elem": [float(f"{x:.3e}") for x in el]}
+    if rows:
+        out["row"] = [float(f"{x:.3e}") for x in rw]
+    return out
+
+
+def cpu_baseline(s, n_hess=3, fd_receivers=32, gpu=None):
     """Time the FP64 oracle on a bounded sample of the survey and scale it to one
-    survey, stage by stage, each on all the host threads it can use.
+    survey, stage by stage, each on all the host threads it can use; compare the
+    sample's results with the GPU's.
 
     FD + DFT: the oracle's C recurrence (OpenMP over grid rows, all receivers of
     the sample stepped together) with the DFT taken window by window as BLAS
-    matrix products, for ``fd_receivers`` Green functions over ``fd_steps``
-    steps on the full grid, scaled to nr receivers x nt steps (the cost is
-    linear in both).  Hessian: the FP64 contraction of ``n_hess`` frequencies
-    (multithreaded BLAS), scaled to nf.  Cholesky and the multi-source solve:
-    all frequencies at full size.
-    """
-    import numpy as np
+    matrix products, for ``fd_receivers`` Green functions spread over the line
+    and the whole record (nt steps) on the full grid, scaled to nr receivers
+    (the cost is linear in them).  Hessian: the FP64 contraction of ``n_hess``
+    frequencies (multithreaded BLAS) from seeded spectra, scaled to nf.
+    Cholesky and the multi-source solve: all frequencies at full size.  With
+    every receiver in the sample the stages are the oracle's whole survey
+    (its own Hessians of every frequency, no scaling).
 
+    ``gpu`` (optional): the GPU run's spectra rows of the sampled receivers
+    ("G", [nf][k][nsub]), its Hessian ("H"), multipliers ("X"), residuals ("R")
+    and mu.  The returned "parity" holds per-frequency errors of the spectra
+    and of the sampled receivers' Hessian block against the oracle's, and,
+    with every receiver sampled, of all multipliers.
+    """
     from oracle import fd, hessian, solve
     try:
         from threadpoolctl import threadpool_info
@@ -111,40 +139,50 @@ def cpu_baseline(s, fd_steps, n_hess=1, fd_receivers=32):
     fd_threads = fd.c_threads()
     v = s.velocity()
     nrs = max(1, min(int(fd_receivers), s.nr))
+    idx = sample_receivers(s.nr, nrs)
+    full = nrs == s.nr
     t0 = time.perf_counter()
-    fd.green_dft_windowed(v, s.nb, s.h, s.dt, fd_steps, s.rec_iz[:nrs], s.rec_ix[:nrs], s.freqs_hz,
-                          s.stride)
+    G = fd.green_dft_windowed(v, s.nb, s.h, s.dt, s.nt, [s.rec_iz[i] for i in idx],
+                              [s.rec_ix[i] for i in idx], s.freqs_hz, s.stride)
     t_fd = time.perf_counter() - t0
-    # n_hess frequencies' Hessians at full size from seeded spectra
-    n_hess = max(1, min(int(n_hess), s.nf))
-    rng = np.random.default_rng(0)
-    G = rng.standard_normal((n_hess, s.nr, s.nsub)) + 1j * rng.standard_normal((n_hess, s.nr, s.nsub))
-    t0 = time.perf_counter()
-    H = hessian.hessian_r1(G)[:1]
-    t_h = (time.perf_counter() - t0) / n_hess
-    del G
-    # all Cholesky factorisations and solves at full size
-    Hs = np.repeat(H, s.nf, axis=0)
+    if full:
+        t0 = time.perf_counter()
+        H = hessian.hessian_r1(G)
+        t_h = (time.perf_counter() - t0) / s.nf
+        n_hess = s.nf
+    else:
+        # n_hess frequencies' Hessians at full size from seeded spectra
+        n_hess = max(1, min(int(n_hess), s.nf))
+        rng = np.random.default_rng(0)
+        Gs = rng.standard_normal((n_hess, s.nr, s.nsub)) + 1j * rng.standard_normal((n_hess, s.nr, s.nsub))
+        t0 = time.perf_counter()
+        H1 = hessian.hessian_r1(Gs)[:1]
+        t_h = (time.perf_counter() - t0) / n_hess
+        del Gs
+        H = np.repeat(H1, s.nf, axis=0)
     R = s.residuals().astype(np.complex128)
+    mu = gpu["mu"] if gpu is not None else 1e-3 * float(np.real(H[0].trace()))
     t0 = time.perf_counter()
-    L = solve.cholesky(solve.penalize(Hs, 1e-3 * float(np.real(H[0].trace()))))
+    L = solve.cholesky(solve.penalize(H, mu))
     t_c = time.perf_counter() - t0
     t0 = time.perf_counter()
-    solve.solve(L, R)
+    Xo = solve.solve(L, R)
     t_s = time.perf_counter() - t0
-    fd_survey = t_fd * (s.nr / nrs) * (s.nt / fd_steps)
+    fd_survey = t_fd * (s.nr / nrs)
     survey_s = fd_survey + t_h * s.nf + t_c
-    return {
+    what = (f"whole survey: all {s.nr} Green functions x {s.nt} steps" if full else
+            f"{nrs} of {s.nr} Green functions (spread over the line) x {s.nt} steps")
+    out = {
         "value": survey_s,
         "unit": "s/survey",
         "cores": int(max(fd_threads, blas_threads)),
         "kind": "oracle",
-        "sample": (f"FP64 oracle: {nrs} Green functions x {fd_steps} steps of FD+DFT on the full grid "
-                   f"({t_fd:.2f} s, C recurrence on {fd_threads} OpenMP threads, DFT by BLAS on "
-                   f"{blas_threads} threads), {n_hess} of {s.nf} Hessians at full size ({t_h * n_hess:.2f} s, "
-                   f"BLAS on {blas_threads} threads), all {s.nf} Cholesky factorisations ({t_c:.2f} s); "
-                   f"scaled to {s.nr} Green functions x {s.nt} steps and {s.nf} Hessians. Multi-source "
-                   f"solve {t_s:.3f} s ({s.nf * s.ns / t_s:.0f} solves/s)"),
+        "sample": (f"FP64 oracle, {what} of FD+DFT on the full grid ({t_fd:.2f} s, C recurrence on "
+                   f"{fd_threads} OpenMP threads, DFT by BLAS on {blas_threads} threads), {n_hess} of "
+                   f"{s.nf} Hessians at full size ({t_h * n_hess:.2f} s, BLAS on {blas_threads} threads), "
+                   f"all {s.nf} Cholesky factorisations ({t_c:.2f} s)"
+                   + ("" if full else f"; scaled to {s.nr} Green functions and {s.nf} Hessians")
+                   + f". Multi-source solve {t_s:.3f} s ({s.nf * s.ns / t_s:.0f} solves/s)"),
         "stages": {
             "fd_dft": {"s_per_survey": round(fd_survey, 2), "threads": int(fd_threads),
                        "sampled_s": round(t_fd, 3)},
@@ -154,6 +192,24 @@ def cpu_baseline(s, fd_steps, n_hess=1, fd_receivers=32):
         },
         "solves_per_s": s.nf * s.ns / t_s,
     }
+    if gpu is not None:
+        Hb = np.stack([G[f] @ G[f].conj().T for f in range(s.nf)])     # the sampled block
+        Hg = gpu["H"][:, idx][:, :, idx]
+        par = {"scope": (f"all {s.nr} receivers" if full else
+                         f"receivers {idx[0]}, {idx[1]}, ..., {idx[-1]} ({nrs} of {s.nr})"),
+               "ghat": _errors(gpu["G"], G, rows=True),
+               "hhat": _errors(Hg, Hb, rows=True)}
+        if full:
+            par["x"] = _errors(gpu["X"], Xo, rows=True)
+        out["parity"] = par
+    return out
+
+
+def sample_receivers(nr, k):
+    """k receiver indices spread evenly over 0..nr-1 (both ends included)."""
+    if k >= nr:
+        return list(range(nr))
+    return sorted({int(round(i * (nr - 1) / max(k - 1, 1))) for i in range(k)})
 
 
 def run_batch(args):
@@ -799,8 +855,20 @@ def main():
                                    "bytes_per_survey": dft_bytes, "useful_tflops": round(dft_tf, 2),
                                    "bf16_mfma_frac": round(dft_tf * 6 / 2500.0, 4)}
     if not args.no_cpu_baseline:
+        gpu = None
+        if args.weighting == "long_record" and not compressed:
+            # the GPU's results the oracle's sample is compared with
+            idx = sample_receivers(s.nr, max(1, min(args.cpu_receivers, s.nr)))
+            it = torch.tensor(idx, device=dev)
+            G = sv.copy_green_dft().reshape(s.nf, s.nr, -1)
+            gpu = {"G": G.index_select(1, it).cpu().numpy().astype(np.complex128),
+                   "H": sv.copy_hessian().cpu().numpy(),
+                   "X": X.cpu().numpy().astype(np.complex128), "mu": mu}
+            del G
         print("# timing the oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(s, args.cpu_steps, args.cpu_hessians, args.cpu_receivers)
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_hessians, args.cpu_receivers, gpu)
+        if "parity" in out["cpu_baseline"]:
+            out["parity"] = out["cpu_baseline"].pop("parity")
     sv.close()
     print(json.dumps(out), flush=True)
 
