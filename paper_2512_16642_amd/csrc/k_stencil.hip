@@ -485,15 +485,24 @@ typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 constexpr int kDft3Ks = 128;            // samples per LDS twiddle stage
 constexpr int kDft3Kp = kDft3Ks + 8;    // padded row (bf16 elements)
 
-__device__ __forceinline__ void split3(float x, __bf16& h, __bf16& m, __bf16& l) {
-  h = (__bf16)x;
-  const float r = x - (float)h;
-  m = (__bf16)r;
-  l = (__bf16)(r - (float)m);
+// The low BF16 of a packed pair widened to FP32 (its bits moved to the top
+// half by a byte permute: the compiler would otherwise convert the FP32 value a
+// second time), and the high one (a mask).
+__device__ __forceinline__ float bf16_lo(unsigned p) { return __uint_as_float(__builtin_amdgcn_perm(0u, p, 0x01000c0cu)); }
+__device__ __forceinline__ float bf16_hi(unsigned p) { return __uint_as_float(p & 0xffff0000u); }
+
+// Three-part split of two FP32 values into packed BF16 pairs (element 0 in the
+// low half): hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid), each
+// conversion round-to-nearest-even and taken for both values at once.
+__device__ __forceinline__ void split3_pair(float x0, float x1, unsigned& h, unsigned& m, unsigned& l) {
+  h = __builtin_bit_cast(unsigned, bf16x2_t{(__bf16)x0, (__bf16)x1});
+  const float r0 = x0 - bf16_lo(h), r1 = x1 - bf16_hi(h);
+  m = __builtin_bit_cast(unsigned, bf16x2_t{(__bf16)r0, (__bf16)r1});
+  l = __builtin_bit_cast(unsigned, bf16x2_t{(__bf16)(r0 - bf16_lo(m)), (__bf16)(r1 - bf16_hi(m))});
 }
 
 template <int MT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT <= 2 ? 3 : 2)))
     k_dft_bf16x3(Geometry g, const float* __restrict__ stage, const float2* __restrict__ tw, int n0,
                  int cnt, int first, int r0, float2* __restrict__ ghat) {
   constexpr int MP = 16 * MT;
@@ -513,54 +522,74 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[mt][j] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int twoF = 2 * g.nf;
+  // twiddles through a buffer resource over this window's rows of the table
+  // (samples n0 .. n0 + cnt - 1): a load at an offset beyond it (samples past
+  // the window, rows past 2 nf) reads zero, so no select follows a load and a
+  // batch's loads issue back to back
+  const __amdgpu_buffer_rsrc_t rt = make_rsrc(tw + (size_t)(n0 - 1) * g.nf, (size_t)cnt * g.nf * sizeof(float2));
   // the lane's eight samples (rows k32 + 8 kg + e) of its four points
   auto load_b = [&](floatx4* b, int k32) {
 #pragma unroll
     for (int e = 0; e < 8; ++e)
       b[e] = __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, (k32 + e) * pitch, 0));
   };
+  // Twiddle stage of 128 samples: thread items are (row m, sample pair t, t + 1),
+  // eight (or four) per batch with all their loads issued before the first is
+  // used; each pair is split into packed words and stored as one 4-byte write
+  // per plane.
+  constexpr int kPer = MP * kDft3Ks / 2 / 256;  // pairs per thread and stage (4 MT)
+  constexpr int kBatch = kPer % 8 == 0 ? 8 : 4;  // divides kPer
+  static_assert(kPer * 256 * 2 == MP * kDft3Ks && kPer % kBatch == 0, "stage items");
+  auto stage_tw = [&](int k32) {
+#pragma unroll 1
+    for (int b0 = 0; b0 < kPer; b0 += kBatch) {
+      float v0[kBatch], v1[kBatch];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        const int e = threadIdx.x + 256 * (b0 + i);
+        const int m = e / (kDft3Ks / 2), t = 2 * (e % (kDft3Ks / 2));
+        // byte offset of (window sample k32 + t, row m); rows past 2 nf are sent past the table
+        const unsigned o = m < twoF ? (unsigned)((((k32 + t) * g.nf + (m >> 1)) * 2 + (m & 1)) * 4) : kDrop;
+        v0[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rt, (int)o, 0, 0));
+        v1[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rt, (int)o, 8 * g.nf, 0));
+      }
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        const int e = threadIdx.x + 256 * (b0 + i);
+        const int m = e / (kDft3Ks / 2), t = 2 * (e % (kDft3Ks / 2));
+        unsigned h, mm, l;
+        split3_pair(v0[i], v1[i], h, mm, l);
+        *reinterpret_cast<unsigned*>(&As[0][m][t]) = h;
+        *reinterpret_cast<unsigned*>(&As[1][m][t]) = mm;
+        *reinterpret_cast<unsigned*>(&As[2][m][t]) = l;
+      }
+    }
+  };
+  // One 32-sample group: stage the twiddles at a stage boundary, split the
+  // group's samples b into the three B planes, load the next group's samples
+  // into b (in flight during the products), then the products.
   const int ngrp = (cnt + 31) / 32;
-  floatx4 bnext[8];
-  load_b(bnext, 0);
+  floatx4 b[8];
+  load_b(b, 0);
   for (int gi = 0; gi < ngrp; ++gi) {
     const int k32 = gi * 32;
     const int kl = k32 % kDft3Ks;
     if (kl == 0) {
       __syncthreads();
-      for (int e = threadIdx.x; e < kDft3Ks * MP; e += 256) {
-        const int m = e / kDft3Ks, t = e % kDft3Ks;
-        float v = 0.f;
-        if (k32 + t < cnt && m < twoF) {
-          const float2 z = tw[(size_t)(n0 - 1 + k32 + t) * g.nf + (m >> 1)];
-          v = (m & 1) ? z.y : z.x;
-        }
-        __bf16 h, mm, l;
-        split3(v, h, mm, l);
-        As[0][m][t] = h;
-        As[1][m][t] = mm;
-        As[2][m][t] = l;
-      }
+      stage_tw(k32);
       __syncthreads();
     }
     // B fragments per tile j and plane: the lane's eight samples of point 4i + j
-    // (split before the next group's loads reuse the sample registers)
     bf16x8_t B[3][4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       unsigned w[3][4];
 #pragma unroll
-      for (int e = 0; e < 8; e += 2) {
-        __bf16 h0, m0, l0, h1, m1, l1;
-        split3(bnext[e][j], h0, m0, l0);
-        split3(bnext[e + 1][j], h1, m1, l1);
-        w[0][e >> 1] = __builtin_bit_cast(unsigned, bf16x2_t{h0, h1});
-        w[1][e >> 1] = __builtin_bit_cast(unsigned, bf16x2_t{m0, m1});
-        w[2][e >> 1] = __builtin_bit_cast(unsigned, bf16x2_t{l0, l1});
-      }
+      for (int e = 0; e < 8; e += 2) split3_pair(b[e][j], b[e + 1][j], w[0][e >> 1], w[1][e >> 1], w[2][e >> 1]);
 #pragma unroll
       for (int q = 0; q < 3; ++q) B[q][j] = __builtin_bit_cast(bf16x8_t, u32x4_t{w[q][0], w[q][1], w[q][2], w[q][3]});
     }
-    if (gi + 1 < ngrp) load_b(bnext, k32 + 32);
+    if (gi + 1 < ngrp) load_b(b, k32 + 32);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const int row = 16 * mt + (lane & 15);
