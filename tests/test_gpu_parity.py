@@ -312,3 +312,33 @@ def test_refinement_steps(ehi, tiny_ref):
     with pytest.raises(ehi.EhiError):
         sp.set_refinement(1)
     sp.close()
+
+
+@pytest.fixture(scope="module")
+def many_freq_ref():
+    # 4 receivers on a 48 x 64 grid, 300 steps: with 256-sample windows the
+    # second window is partial (44 samples: a partial 32-sample group and a
+    # partial twiddle stage); up to 64 frequencies over 2-60 Hz
+    base = synth.micro(nz=48, nx=64, nb=8, nt=300, nr=4)
+    v = base.velocity()
+    out = {}
+    for nf in (10, 20, 30, 36, 64):
+        s = base.with_(freqs_hz=tuple(2.0 + 58.0 * k / (nf - 1) for k in range(nf)))
+        out[nf] = (s, fd.green_dft(s, v))
+    return v, out
+
+
+@pytest.mark.parametrize("form", [1, 0])
+@pytest.mark.parametrize("nf", [10, 20, 30, 36, 64])
+def test_green_dft_row_tiles(ehi, many_freq_ref, monkeypatch, nf, form):
+    # 2 nf rows of twiddles make 2, 3, 4, 6 (5 rounded up) and 8 row tiles of 16
+    # in the DFT kernels: every instantiation of both forms (three-part BF16 on
+    # the BF16 matrix cores, and FP32 matrix cores) against the oracle
+    monkeypatch.setenv("EHI_DFT_FORM", str(form))
+    v, refs = many_freq_ref
+    s, ref = refs[nf]
+    sv = ehi.survey_from(s, chunk=256)
+    sv.build_green(dev(v))
+    G = sv.copy_green_dft().reshape(s.nf, s.nr, -1).cpu().numpy()
+    sv.close()
+    check(G, ref, 5e-6, 5e-6, 2e-5, f"nf={nf} form {form} ghat")
