@@ -4,8 +4,9 @@ Hhat_W(w) = (1/Nt) sum_p Ghat_p Ghat_p^H with Ghat_p the DFT truncated after
 sample p (the paper's weighting function W(m, n) = min(Nt - m, Nt - n) kept
 exactly, as the oracle's running-DFT Gram, pinned against the literal
 algorithm).  Cases: tiny with nt = 300 (one full 256-sample window and a
-partial one), ragged with stride 2 and odd sizes, and tiny end to end with the
-1e-5 multiplier target.
+partial one), ragged with stride 2 and odd sizes, 70 receivers (several
+32-row blocks and block pairs), and tiny end to end with the 1e-5 multiplier
+target.
 """
 import numpy as np
 import pytest
@@ -40,9 +41,15 @@ def _gpu_r2(ehi, s, v):
     return sv, H
 
 
-@pytest.mark.parametrize("case", ["tiny_nt300", "ragged"])
+def _wide():
+    # 70 receivers: three 32-row blocks, six block pairs (two workgroups, the
+    # second partial), a partial last block
+    return synth.micro(nz=40, nx=80, nb=6, nt=300, nr=70)
+
+
+@pytest.mark.parametrize("case", ["tiny_nt300", "ragged", "wide"])
 def test_finite_record_hessian(ehi, case):
-    s = synth.tiny().with_(nt=300) if case == "tiny_nt300" else synth.ragged()
+    s = {"tiny_nt300": lambda: synth.tiny().with_(nt=300), "ragged": synth.ragged, "wide": _wide}[case]()
     v = s.velocity()
     ref = _oracle_r2(s, v)
     sv, H = _gpu_r2(ehi, s, v)
@@ -96,7 +103,7 @@ def _gpu_r2_dec(ehi, s, v, D, chunk=256):
 
 
 @pytest.mark.parametrize("case,D,chunk", [("tiny", 10, 256), ("tiny", 4, 512), ("ragged", 3, 256),
-                                          ("ragged_long", 8, 256)])
+                                          ("ragged_long", 8, 256), ("wide", 5, 256)])
 def test_resampled_finite_record_hessian(ehi, case, D, chunk):
     # against the oracle's finite-record Hessian on the same resampled record
     # (same filter design, kept times and D / H(w) correction); several
@@ -105,6 +112,8 @@ def test_resampled_finite_record_hessian(ehi, case, D, chunk):
         s = synth.tiny()
     elif case == "ragged":
         s = synth.ragged()
+    elif case == "wide":
+        s = _wide()
     else:
         s = synth.ragged(nt=1157)
     v = s.velocity()
