@@ -477,7 +477,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT <= 
 // samples of four consecutive points as eight 16-byte loads.  The twiddle
 // stage in LDS holds the three BF16 planes [plane][row][sample] with rows
 // padded by 8 samples (16 B), so the 16 rows a half-wave reads land on
-// different banks.
+// different banks.  A workgroup of NW waves covers 64 NW consecutive grid
+// points of one receiver, so each sample row is read in 256 NW-byte runs.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
@@ -501,17 +502,18 @@ __device__ __forceinline__ void split3_pair(float x0, float x1, unsigned& h, uns
   l = __builtin_bit_cast(unsigned, bf16x2_t{(__bf16)(r0 - bf16_lo(m)), (__bf16)(r1 - bf16_hi(m))});
 }
 
-template <int MT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT <= 2 ? 3 : 2)))
+template <int MT, int NW>  // NW waves per workgroup, 64 grid points each
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(MT <= 2 ? 3 : 2)))
     k_dft_bf16x3(Geometry g, const float* __restrict__ stage, const float2* __restrict__ tw, int n0,
                  int cnt, int first, int r0, float2* __restrict__ ghat) {
   constexpr int MP = 16 * MT;
+  constexpr int NT = 64 * NW;  // threads
   __shared__ __bf16 As[3][MP][kDft3Kp];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int r = blockIdx.y;
-  const int col = blockIdx.x * 256 + wave * 64 + 4 * (lane & 15);  // this lane's 4 grid points
-  const int kg = lane >> 4;                                          // sample octet of the lane
+  const int col = blockIdx.x * NT + wave * 64 + 4 * (lane & 15);  // this lane's 4 grid points
+  const int kg = lane >> 4;                                         // sample octet of the lane
   const __amdgpu_buffer_rsrc_t rs =
       make_rsrc(stage + (size_t)r * g.chunk * g.nsub_p, (size_t)cnt * g.nsub_p * sizeof(float));
   const int pitch = g.nsub_p * 4;
@@ -537,16 +539,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT <= 
   // eight (or four) per batch with all their loads issued before the first is
   // used; each pair is split into packed words and stored as one 4-byte write
   // per plane.
-  constexpr int kPer = MP * kDft3Ks / 2 / 256;  // pairs per thread and stage (4 MT)
-  constexpr int kBatch = kPer % 8 == 0 ? 8 : 4;  // divides kPer
-  static_assert(kPer * 256 * 2 == MP * kDft3Ks && kPer % kBatch == 0, "stage items");
+  constexpr int kPer = MP * kDft3Ks / 2 / NT;  // pairs per thread and stage
+  constexpr int kBatch = kPer % 8 == 0 ? 8 : kPer % 4 == 0 ? 4 : 2;  // divides kPer
+  static_assert(kPer * NT * 2 == MP * kDft3Ks && kPer % kBatch == 0, "stage items");
   auto stage_tw = [&](int k32) {
 #pragma unroll 1
     for (int b0 = 0; b0 < kPer; b0 += kBatch) {
       float v0[kBatch], v1[kBatch];
 #pragma unroll
       for (int i = 0; i < kBatch; ++i) {
-        const int e = threadIdx.x + 256 * (b0 + i);
+        const int e = threadIdx.x + NT * (b0 + i);
         const int m = e / (kDft3Ks / 2), t = 2 * (e % (kDft3Ks / 2));
         // byte offset of (window sample k32 + t, row m); rows past 2 nf are sent past the table
         const unsigned o = m < twoF ? (unsigned)((((k32 + t) * g.nf + (m >> 1)) * 2 + (m & 1)) * 4) : kDrop;
@@ -555,7 +557,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT <= 
       }
 #pragma unroll
       for (int i = 0; i < kBatch; ++i) {
-        const int e = threadIdx.x + 256 * (b0 + i);
+        const int e = threadIdx.x + NT * (b0 + i);
         const int m = e / (kDft3Ks / 2), t = 2 * (e % (kDft3Ks / 2));
         unsigned h, mm, l;
         split3_pair(v0[i], v1[i], h, mm, l);
@@ -758,18 +760,23 @@ hipError_t launch_dft_chunk(const Geometry& g, const float* stage, const float2*
   const int fi = first ? 1 : 0;
   const int mt = cdiv(2 * g.nf, 16);
   if (g.dft_form == 1) {
-#define EHI_DFT3(M)                                                                                \
-  hipLaunchKernelGGL(k_dft_bf16x3<M>, grid, dim3(256), 0, st, g, stage, tw, n0, cnt, fi, r0, ghat); \
+    // 512-thread workgroups over 512 grid points (each sample row read in 2 KB
+    // runs, twiddle stages shared by eight waves) where the registers allow
+    // two waves per SIMD anyway; 256 threads at 2 and 3 row tiles, which fit
+    // three waves per SIMD
+#define EHI_DFT3(M, NW)                                                                                \
+  hipLaunchKernelGGL((k_dft_bf16x3<M, NW>), dim3(cdiv(g.nsub, 64 * (NW)), nrb_now), dim3(64 * (NW)), 0, st, g, \
+                     stage, tw, n0, cnt, fi, r0, ghat);                                                \
   break;
     switch (mt) {
-      case 1: EHI_DFT3(1)
-      case 2: EHI_DFT3(2)
-      case 3: EHI_DFT3(3)
-      case 4: EHI_DFT3(4)
+      case 1: EHI_DFT3(1, 8)
+      case 2: EHI_DFT3(2, 4)
+      case 3: EHI_DFT3(3, 4)
+      case 4: EHI_DFT3(4, 8)
       case 5:
-      case 6: EHI_DFT3(6)
+      case 6: EHI_DFT3(6, 8)
       case 7:
-      case 8: EHI_DFT3(8)
+      case 8: EHI_DFT3(8, 8)
       default:
         return hipErrorInvalidValue;
     }
