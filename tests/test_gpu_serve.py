@@ -80,3 +80,52 @@ def test_one_served_request_matches_oracle(served):
     Xr = solve.multipliers(H, mu, R)
     X = srv.results[r.rid].cpu().numpy()
     check(X, Xr, 1e-5, 1e-5, 2e-5, "served request vs oracle")
+
+
+@pytest.fixture(scope="module")
+def served_tight():
+    # a budget that holds exactly the three resident surveys: every rebuild must
+    # evict the least recently used factors (its own old ones included), and
+    # deblurs for a survey that is neither resident nor being rebuilt are
+    # rejected
+    from paper_2512_16642_amd import ehi, serve
+    ehi.lib()
+    specs = _specs()
+    eng = serve.EhiEngine(specs, build_slots=2, max_batch_sources=256)
+    budget = sum(eng.workspace_bytes(k) for k in range(len(specs)))
+    srv = serve.Server(eng, budget_bytes=budget, build_slots=2, keep_results=True)
+    srv.preload(range(len(specs)))
+    reqs = serve.poisson_requests(2.0, 40.0, 0.15, len(specs), ns_max=64, seed=2401)
+    srv.run(reqs)
+    torch.cuda.synchronize()
+    yield specs, eng, srv, reqs
+    srv.close()
+
+
+def test_tight_budget_evicts_and_stays_within_it(served_tight):
+    specs, eng, srv, reqs = served_tight
+    assert srv.evictions > 0
+    assert srv.adm.peak <= srv.adm.budget
+    assert all(r.status in ("done", "rejected") for r in reqs), [(r.rid, r.kind, r.status) for r in reqs]
+    assert all(r.status == "done" for r in reqs if r.kind == "build")
+    done = [r for r in reqs if r.kind == "deblur" and r.status == "done"]
+    assert len(done) >= 20
+    print("tight budget:", srv.evictions, "evictions,",
+          sum(1 for r in reqs if r.status == "rejected"), "rejected deblurs")
+
+
+def test_tight_budget_results_same_as_fresh_factors(served_tight):
+    # the build is deterministic, so factors built afresh are bitwise those
+    # every served deblur used, whether or not they were evicted since
+    specs, eng, srv, reqs = served_tight
+    fresh = {}
+    try:
+        for r in reqs:
+            if r.kind != "deblur" or r.status != "done":
+                continue
+            if r.key not in fresh:
+                fresh[r.key] = eng.build(r.key, 0)
+            assert torch.equal(eng.alone(fresh[r.key], r), srv.results[r.rid]), r
+    finally:
+        for sv in fresh.values():
+            sv.close()
