@@ -342,3 +342,35 @@ def test_green_dft_row_tiles(ehi, many_freq_ref, monkeypatch, nf, form):
     G = sv.copy_green_dft().reshape(s.nf, s.nr, -1).cpu().numpy()
     sv.close()
     check(G, ref, 5e-6, 5e-6, 2e-5, f"nf={nf} form {form} ghat")
+
+
+@pytest.mark.parametrize("nt", [1, 2, 7, 9])
+def test_green_dft_short_records(ehi, nt):
+    # records shorter than one 8-level launch, or one level past it: the first
+    # launch advances fewer levels than it holds, and nt = 1 is the impulse alone
+    s = synth.ragged(nt=nt)
+    v = s.velocity()
+    sv, G = _gpu_green(ehi, s, v)
+    sv.close()
+    check(G, fd.green_dft(s, v), 5e-6, 5e-6, 2e-5, f"nt={nt} ghat")
+
+
+def test_single_receiver_end_to_end(ehi):
+    # one receiver: one 32-row block of one row in the contraction, 1 x 1
+    # factors, every source's multiplier a scalar division per frequency
+    s = synth.ragged(nr=1)
+    v = s.velocity()
+    G = fd.green_dft(s, v)
+    H = hessian.hessian_r1(G)
+    mu = 1e-3 * solve.lambda_max(H)
+    R = s.residuals()
+    X = solve.multipliers(H, mu, R.astype(np.complex128))
+    sv = ehi.survey_from(s)
+    sv.build_green(dev(v))
+    sv.build_hessian()
+    sv.factor(mu)
+    Xg = sv.apply_multipliers(dev(R)).cpu().numpy()
+    Hg = sv.copy_hessian().cpu().numpy()
+    sv.close()
+    check(Hg, H, 1e-5, 1e-5, 1e-5, "one receiver Hhat")
+    check(Xg, X, 1e-5, 1e-5, 1e-5, "one receiver multipliers")

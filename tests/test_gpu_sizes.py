@@ -5,15 +5,16 @@ Seeded spectra (synth.spectra: rows mixed by a random unitary matrix, singular
 values over four decades, so the Hessians' eigenvalues span eight) are loaded
 through ehi_load_green_dft; the Hessian comes back through ehi_copy_hessian and
 is compared with the oracle's FP64 contraction of the same complex64 values.
-The receiver counts cover every form of the kernel: one 32 x 32 block (16), a
-ragged block count (33), the whole-matrix split-BF16 form up to its limit (200,
-224) and the tile-pair form past it (225, 256, 400, the largest batch survey),
-in both precision modes.  The subgrid (61 x 203 = 12,383 points) spans several
+The receiver counts cover every form of the kernel: a single receiver (1), one
+32 x 32 block (16), a ragged block count (33), the whole-matrix split-BF16 form
+up to its limit (200, 224) and the tile-pair form past it (225, 256, 400, the
+largest batch survey, and 1024, the descriptor's limit), in both precision
+modes.  The subgrid (61 x 203 = 12,383 points) spans several
 grid partitions and ends on a ragged tail.
 
 Factor + solve from a given Hessian (the oracle's FP64 Hhat of the same
 spectra, mu = 1e-3 lambda_max, so cond(Qhat) ~ 1e3 as in the surveys' low
-frequencies) at 200 and 400 receivers: the FP64 factor against scipy's, the
+frequencies) at 1, 33, 200, 400 and 1024 receivers: the FP64 factor against scipy's, the
 multipliers of 64 sources against the oracle's solve.
 
 Tolerances as for the tiny survey (tests/test_gpu_parity.py): 2e-6 per
@@ -57,7 +58,7 @@ def _spectra(nr):
 
 
 @pytest.mark.parametrize("prec", ["split_bf16", "plain_fp32"])
-@pytest.mark.parametrize("nr", [16, 33, 200, 224, 225, 256, 400])
+@pytest.mark.parametrize("nr", [1, 16, 33, 200, 224, 225, 256, 400, 1024])
 def test_hessian_from_given_spectra_sizes(ehi, nr, prec):
     s = _survey(nr)
     G, ref = _spectra(nr)
@@ -73,7 +74,7 @@ def test_hessian_from_given_spectra_sizes(ehi, nr, prec):
         assert np.all(d.imag == 0) and np.all(d.real > 0)
 
 
-@pytest.mark.parametrize("nr", [33, 200, 400])
+@pytest.mark.parametrize("nr", [1, 33, 200, 400, 1024])
 def test_factor_and_solve_from_given_hessian_sizes(ehi, nr):
     s = _survey(nr)
     _, H = _spectra(nr)
