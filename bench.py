@@ -781,10 +781,9 @@ def main():
         # the contraction runs over the kept coefficients instead of the grid points
         herk_flops *= keep[0] * keep[1] / s.nsub
     herk_ms = prof["herk"][0] / K
-    # 32 x 32 block pairs in the whole-matrix contraction (up to 224 receivers,
-    # final-spectrum form) and in the finite-record contraction, 64 x 64 tile
-    # pairs otherwise
-    whole = (args.precision == "split_bf16" and args.weighting == "long_record" and s.nr <= 224
+    # 32 x 32 block pairs in the whole-matrix contraction (final-spectrum form)
+    # and in the finite-record contraction, 64 x 64 tile pairs otherwise
+    whole = (args.precision == "split_bf16" and args.weighting == "long_record"
              and os.environ.get("EHI_HERK_WHOLE", "1") != "0")
     herk_tile = 32 if (whole or args.weighting == "finite_record") else 64
     out = {

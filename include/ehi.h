@@ -137,9 +137,10 @@ typedef enum {
  *             partitions than the default leave a larger rounding error,
  *             which grows about linearly with the stages per partition.
  *   herk_form   final-spectrum contraction: 0 = chosen from the sizes;
- *             split-BF16: 1 = whole-matrix form (every row of a grid stage
- *             staged once per group of block pairs; nr <= 224), 2 = 64 x 64
- *             tile pairs; plain FP32: 0-2 = 64 x 64 tile pairs on the FP32
+ *             split-BF16: 1 = whole-matrix form (the rows of a grid stage
+ *             staged once per group of 32 x 32 block pairs: every row up to
+ *             224 receivers, the eight row blocks of a 4 x 4 tile of block
+ *             pairs above), 2 = 64 x 64 tile pairs; plain FP32: 0-2 = 64 x 64 tile pairs on the FP32
  *             matrix cores, 3 = FP32 products on the vector units.  Ignored by
  *             the other contractions.
  */

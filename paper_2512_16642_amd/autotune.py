@@ -100,18 +100,19 @@ HERK_SPLITS = (2, 4, 8, 12, 17, 24, 32, 48, 64)
 
 def _herk_key(spec, precision: str) -> str:
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "none"
-    return f"{arch}:herk:nr{spec.nr}:nsub{spec.nsub}:nf{spec.nf}:{precision}:v2"
+    return f"{arch}:herk:nr{spec.nr}:nsub{spec.nsub}:nf{spec.nf}:{precision}:v3"
 
 
 def tune_contraction(spec, precision: str = "split_bf16", repeats: int = 3) -> dict:
     """Best (form, partitions) of the final-spectrum contraction for this
-    survey's sizes (cached).  form 1 = whole-matrix (up to 224 receivers),
-    2 = 64 x 64 tile pairs; the plain FP32 form has one kernel."""
+    survey's sizes (cached).  form 1 = whole-matrix (4 x 4 tiles of block
+    pairs above 224 receivers), 2 = 64 x 64 tile pairs; the plain FP32 form
+    has one kernel."""
     key = _herk_key(spec, precision)
     cache = _load()
     if key in cache:
         return cache[key]
-    forms = [0] if precision != "split_bf16" else ([1, 2] if spec.nr <= 224 else [2])
+    forms = [0] if precision != "split_bf16" else [1, 2]
     kmax = max(1, spec.nsub // 1024)
     # the library's accuracy floor: no partition adds more than 40 stages of 32
     # grid points into its FP32 running sums (fewer partitions are faster by a

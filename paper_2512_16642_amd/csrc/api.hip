@@ -134,7 +134,6 @@ bool validate(const ehi_survey_desc* d, std::string* why) {
   if (d->windows < 0 || d->windows > 2) return bad("windows must be 0, 1 or 2");
   if (d->herk_split < 0 || d->herk_split > ehi::kHerkSplitMax) return bad("herk_split must be in [0, 64]");
   if (d->herk_form < 0 || d->herk_form > 3) return bad("herk_form must be 0, 1, 2 or 3");
-  if (d->herk_form == 1 && d->nr > 224) return bad("the whole-matrix contraction holds at most 224 receivers");
   if (d->decim < 0 || d->decim > ehi::kMaxDecim) return bad("decim must be in [0, 64]");
   if (d->decim >= 2) {
     if (d->weighting != EHI_WEIGHT_FINITE_RECORD)
@@ -214,10 +213,10 @@ ehi::Geometry make_geometry(const ehi_survey_desc* d) {
   int ntile = ehi::cdiv(g.nr, (!g.split_bf16 && g.herk_form == 3) ? ehi::kHerkTile : 64);
   int pairs = ntile * (ntile + 1) / 2;
   int want = ehi::cdiv(2048, pairs * g.nf);
-  // the final-spectrum split-BF16 contraction of up to 224 receivers runs one
-  // workgroup per CU per (frequency, partition, pair group): partitions for
-  // about four full rounds of workgroups (a partial last round costs a round)
-  g.herk_whole = (g.split_bf16 && g.weighting == EHI_WEIGHT_LONG_RECORD && g.nr <= 224) ? 1 : 0;
+  // the final-spectrum split-BF16 contraction runs one workgroup per CU per
+  // (frequency, partition, pair group or tile): partitions for about four full
+  // rounds of workgroups (a partial last round costs a round)
+  g.herk_whole = (g.split_bf16 && g.weighting == EHI_WEIGHT_LONG_RECORD) ? 1 : 0;
   if (g.herk_whole) want = std::max(1, 1024 / (g.nf * ehi::herk_whole_groups(g.nr)));
   if (d->herk_form == 2) g.herk_whole = 0;
   if (g.herk_whole == 0 && d->herk_form == 2) want = ehi::cdiv(2048, pairs * g.nf);

@@ -301,20 +301,49 @@ __global__ void __launch_bounds__(256)
 // spectra are read twice instead of about three times, and split once per
 // group instead of once per tile pair.  Output: the upper-triangle blocks of
 // hpart (the reduction reads j >= i only).
-constexpr int kWholeRows = 224;   // rows held in LDS
+//
+// TILED (more than 224 receivers, whose rows do not all fit in LDS): the
+// groups are the tiles of a 4 x 4 tiling of the block-pair triangle.  A tile
+// off the diagonal pairs row blocks 4 ti .. + 3 with row blocks 4 tj .. + 3
+// (16 pairs, eight blocks staged); a tile on it, the upper triangle of its four
+// blocks (10 pairs, four blocks staged).  Every row block is then read by about
+// half as many workgroups as there are tiles in a row of the triangle, instead
+// of once per 64 x 64 tile pair.
+constexpr int kWholeRows = 256;   // rows held in LDS (eight 32-row blocks)
 constexpr int kWholeWaves = 8;
 constexpr int kWholePairs = 2;    // block pairs per wave
 constexpr int kWholeGroup = kWholeWaves * kWholePairs;
+constexpr int kWholeTile = 4;     // blocks per side of a tile (TILED)
+constexpr int kWholeMaxNr = 224;  // receivers of the untiled form (all rows staged)
 
-template <bool VEC>
+template <bool VEC, bool TILED>
 __global__ void __launch_bounds__(512)
     k_herk_bf16_whole(Geometry g, const float2* __restrict__ ghat, float2* __restrict__ hpart, int split) {
   __shared__ u32x4 pl[2][4][kBk / 8][kWholeRows];  // [buffer][plane][group of 8 points][row]
   const int nb = cdiv(g.nr, 32);
-  const int rows = nb * 32;  // rows staged (>= nr, zero beyond)
-  const int npair = nb * (nb + 1) / 2;
-  const int ngroup = cdiv(npair, kWholeGroup);
+  const int ntile = cdiv(nb, kWholeTile);
+  const int ngroup = TILED ? ntile * (ntile + 1) / 2 : cdiv(nb * (nb + 1) / 2, kWholeGroup);
   const int grp_id = blockIdx.x % ngroup;
+  // staged row blocks: s < ni is block i0 + s, s >= ni block j0 + s - ni (TILED);
+  // every block in order otherwise
+  int i0 = 0, ni = nb, j0 = 0, nj = 0, npair = nb * (nb + 1) / 2, nstage = nb;
+  bool diag = true;
+  if constexpr (TILED) {
+    int ti = 0, p = grp_id;
+    while (p >= ntile - ti) {
+      p -= ntile - ti;
+      ++ti;
+    }
+    const int tj = ti + p;
+    i0 = kWholeTile * ti;
+    ni = min(kWholeTile, nb - i0);
+    j0 = kWholeTile * tj;
+    nj = min(kWholeTile, nb - j0);
+    diag = ti == tj;
+    npair = diag ? ni * (ni + 1) / 2 : ni * nj;
+    nstage = diag ? ni : ni + nj;
+  }
+  const int rows = nstage * 32;  // rows staged (zero beyond nr)
   const int ks = (blockIdx.x / ngroup) % split;
   const int f = blockIdx.x / (ngroup * split);
   const int kchunk = cdiv(cdiv(g.nsub, split), kBk) * kBk;
@@ -324,20 +353,32 @@ __global__ void __launch_bounds__(512)
   const int lane = tid & 63, wave = tid >> 6;
   const float2* G = ghat + (size_t)f * g.nr * g.nsub;
 
-  // this wave's block pairs: p = 16 group + wave + 8 m, row-major in the upper triangle
-  int pbi[kWholePairs], pbj[kWholePairs];
-  const int pfirst = grp_id * kWholeGroup + wave;
+  // this wave's block pairs: p = 16 group + wave + 8 m (TILED: p = wave + 8 m of
+  // the tile), row-major in the upper triangle (off-diagonal tiles: row-major
+  // over the ni x nj pairs); pbi/pbj are the staged (LDS) blocks, gbi/gbj the
+  // blocks of the Hessian
+  int pbi[kWholePairs], pbj[kWholePairs], gbi[kWholePairs], gbj[kWholePairs];
+  const int pfirst = (TILED ? 0 : grp_id * kWholeGroup) + wave;
   const int mine = npair > pfirst ? min(kWholePairs, (npair - pfirst + kWholeWaves - 1) / kWholeWaves) : 0;
 #pragma unroll
   for (int m = 0; m < kWholePairs; ++m) {
     int p = pfirst + kWholeWaves * m, i = 0;
     if (p >= npair) p = 0;
-    while (p >= nb - i) {
-      p -= nb - i;
-      ++i;
+    if (diag) {
+      while (p >= ni - i) {
+        p -= ni - i;
+        ++i;
+      }
+      pbi[m] = i;
+      pbj[m] = i + p;
+      gbi[m] = i0 + i;
+      gbj[m] = i0 + i + p;
+    } else {
+      pbi[m] = p / nj;
+      pbj[m] = ni + p % nj;
+      gbi[m] = i0 + p / nj;
+      gbj[m] = j0 + p % nj;
     }
-    pbi[m] = i;
-    pbj[m] = i + p;
   }
   floatx4 re[kWholePairs][2][2], im[kWholePairs][2][2];
 #pragma unroll
@@ -354,9 +395,11 @@ __global__ void __launch_bounds__(512)
     for (int p = 0; p < 2; ++p) {
       const int task = tid + 512 * p;
       const int row = task % rows, grp = task / rows;
-      const bool ok = task < 4 * rows && row < g.nr;
+      const int sb = row >> 5;  // staged block
+      const int grow = (sb < ni ? i0 + sb : j0 + sb - ni) * 32 + (row & 31);
+      const bool ok = task < 4 * rows && grow < g.nr;
       const int k = kb + 8 * grp;
-      const float2* src = G + (size_t)(ok ? row : 0) * g.nsub;
+      const float2* src = G + (size_t)(ok ? grow : 0) * g.nsub;
       if (VEC && ok && k + 8 <= k1) {
         const floatx4* q4 = reinterpret_cast<const floatx4*>(src + k);
 #pragma unroll
@@ -469,8 +512,8 @@ __global__ void __launch_bounds__(512)
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int v4 = 0; v4 < 4; ++v4) {
-          const int i = pbi[m] * 32 + a * 16 + 4 * (lane >> 4) + v4;
-          const int j = pbj[m] * 32 + b * 16 + (lane & 15);
+          const int i = gbi[m] * 32 + a * 16 + 4 * (lane >> 4) + v4;
+          const int j = gbj[m] * 32 + b * 16 + (lane & 15);
           if (i < g.nr && j < g.nr) out[(size_t)i * g.nr + j] = make_float2(re[m][a][b][v4], im[m][a][b][v4]);
         }
   }
@@ -865,6 +908,10 @@ hipError_t launch_herk_fp32(const Geometry& g, const float2* ghat, float2* hpart
 
 int herk_whole_groups(int nr) {
   const int nb = cdiv(nr, 32);
+  if (nr > kWholeMaxNr) {
+    const int nt = cdiv(nb, kWholeTile);
+    return nt * (nt + 1) / 2;
+  }
   return cdiv(nb * (nb + 1) / 2, kWholeGroup);
 }
 
@@ -876,12 +923,21 @@ int herk_bf16_blocks(const Geometry& g) {
 hipError_t launch_herk_split_bf16(const Geometry& g, const float2* ghat, float2* hpart,
                                   hipStream_t st) {
   if (g.herk_whole) {
-    if (g.nr > kWholeRows) return hipErrorInvalidValue;
-    dim3 grid((unsigned)(g.nf * g.herk_split * herk_whole_groups(g.nr)));
-    if (g.nsub % 2 == 0)
-      hipLaunchKernelGGL(k_herk_bf16_whole<true>, grid, dim3(512), 0, st, g, ghat, hpart, g.herk_split);
-    else
-      hipLaunchKernelGGL(k_herk_bf16_whole<false>, grid, dim3(512), 0, st, g, ghat, hpart, g.herk_split);
+    const long long items = (long long)g.nf * g.herk_split * herk_whole_groups(g.nr);
+    if (items > 0x7fffffffLL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)items);
+    const bool tiled = g.nr > kWholeMaxNr;
+    if (g.nsub % 2 == 0) {
+      if (tiled)
+        hipLaunchKernelGGL((k_herk_bf16_whole<true, true>), grid, dim3(512), 0, st, g, ghat, hpart, g.herk_split);
+      else
+        hipLaunchKernelGGL((k_herk_bf16_whole<true, false>), grid, dim3(512), 0, st, g, ghat, hpart, g.herk_split);
+    } else {
+      if (tiled)
+        hipLaunchKernelGGL((k_herk_bf16_whole<false, true>), grid, dim3(512), 0, st, g, ghat, hpart, g.herk_split);
+      else
+        hipLaunchKernelGGL((k_herk_bf16_whole<false, false>), grid, dim3(512), 0, st, g, ghat, hpart, g.herk_split);
+    }
     return hipGetLastError();
   }
   const long long items = (long long)herk_bf16_blocks(g) * g.herk_split * g.nf;

@@ -7,9 +7,9 @@ through ehi_load_green_dft; the Hessian comes back through ehi_copy_hessian and
 is compared with the oracle's FP64 contraction of the same complex64 values.
 The receiver counts cover every form of the kernel: a single receiver (1), one
 32 x 32 block (16), a ragged block count (33), the whole-matrix split-BF16 form
-up to its limit (200, 224) and the tile-pair form past it (225, 256, 400, the
-largest batch survey, and 1024, the descriptor's limit), in both precision
-modes.  The subgrid (61 x 203 = 12,383 points) spans several
+with every row staged (200, 224) and with 4 x 4 tiles of block pairs past it
+(225, 256, 400, the largest batch survey, and 1024, the descriptor's limit),
+in both precision modes; the 64 x 64 tile-pair form at 400 receivers too.  The subgrid (61 x 203 = 12,383 points) spans several
 grid partitions and ends on a ragged tail.
 
 Factor + solve from a given Hessian (the oracle's FP64 Hhat of the same
@@ -92,12 +92,12 @@ def test_factor_and_solve_from_given_hessian_sizes(ehi, nr):
     check(Xg, X, 2e-6, 2e-6, 4e-6, f"nr={nr} solve")
 
 
-@pytest.mark.parametrize("form,split", [(1, 1), (1, 7), (2, 3), (2, 12), (0, 64)])
-def test_hessian_contraction_shapes(ehi, form, split):
+@pytest.mark.parametrize("nr,form,split", [(200, 1, 1), (200, 1, 7), (200, 2, 3), (200, 2, 12), (200, 0, 64),
+                                            (400, 2, 8), (400, 1, 5)])
+def test_hessian_contraction_shapes(ehi, nr, form, split):
     # every form and partition count the autotuner may choose: the same
     # Hessian to rounding (partitions change only the order of FP32 partial
     # sums), within the contraction's tolerance of the oracle
-    nr = 200
     s = _survey(nr)
     G, ref = _spectra(nr)
     sv = ehi.survey_from(s, precision="split_bf16", nr_batch=8, herk_form=form, herk_split=split)
@@ -105,7 +105,7 @@ def test_hessian_contraction_shapes(ehi, form, split):
     sv.build_hessian()
     H = sv.copy_hessian().cpu().numpy()
     sv.close()
-    check(H, ref, 2e-6, 2e-6, 4e-6, f"form {form} split {split} hessian")
+    check(H, ref, 2e-6, 2e-6, 4e-6, f"nr={nr} form {form} split {split} hessian")
     for f in range(NF):
         np.testing.assert_array_equal(H[f], H[f].conj().T)
 
