@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "ehi_internal.h"
 
@@ -366,6 +367,32 @@ template <> struct Mfma<double> {
   }
 };
 
+// The epilogues of the matrix-core products: value (vx, vy) of C(i, j) of
+// frequency f (see GemmArgs).
+template <int EPI>
+__device__ __forceinline__ void epi_store(const GemmArgs& a, int f, int j, int i, double vx, double vy) {
+  if (EPI == kEpiStore) {
+    a.C[(size_t)f * a.sC + (size_t)j * a.ldc + i] = make_float2((float)vx, (float)vy);
+  } else if (EPI == kEpiResid) {
+    const float2 rr = a.R[(size_t)f * a.sR + (size_t)j * a.ldr + i];
+    a.C[(size_t)f * a.sC + (size_t)j * a.ldc + i] =
+        make_float2((float)((double)rr.x - vx), (float)((double)rr.y - vy));
+  } else {
+    double2* xp = a.X + (size_t)f * a.sX + (size_t)j * a.ldx + i;
+    if (EPI == kEpiX64Set) {
+      *xp = make_double2(vx, vy);
+    } else if (EPI == kEpiX64Add) {
+      double2 o = *xp;
+      o.x += vx;
+      o.y += vy;
+      *xp = o;
+    } else {  // kEpiOut
+      const double2 o = *xp;
+      a.C[(size_t)f * a.sC + (size_t)j * a.ldc + i] = make_float2((float)(o.x + vx), (float)(o.y + vy));
+    }
+  }
+}
+
 template <typename T, int MODE, int EPI>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_cgemm_mfma(GemmArgs a) {
   typedef typename Cx<T>::t C2;
@@ -458,27 +485,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         const int j = j0 + wj + 16 * jt + Mfma<T>::row(l4, v);
         const int i = i0 + wi + 16 * it + l16;
         if (j >= a.ns || i >= a.n) continue;
-        const double vx = (double)dr[jt][it][v], vy = (double)di[jt][it][v];
-        if (EPI == kEpiStore) {
-          a.C[(size_t)f * a.sC + (size_t)j * a.ldc + i] = make_float2((float)vx, (float)vy);
-        } else if (EPI == kEpiResid) {
-          const float2 rr = a.R[(size_t)f * a.sR + (size_t)j * a.ldr + i];
-          a.C[(size_t)f * a.sC + (size_t)j * a.ldc + i] =
-              make_float2((float)((double)rr.x - vx), (float)((double)rr.y - vy));
-        } else {
-          double2* xp = a.X + (size_t)f * a.sX + (size_t)j * a.ldx + i;
-          if (EPI == kEpiX64Set) {
-            *xp = make_double2(vx, vy);
-          } else if (EPI == kEpiX64Add) {
-            double2 o = *xp;
-            o.x += vx;
-            o.y += vy;
-            *xp = o;
-          } else {  // kEpiOut
-            const double2 o = *xp;
-            a.C[(size_t)f * a.sC + (size_t)j * a.ldc + i] = make_float2((float)(o.x + vx), (float)(o.y + vy));
-          }
-        }
+        epi_store<EPI>(a, f, j, i, (double)dr[jt][it][v], (double)di[jt][it][v]);
       }
 }
 
@@ -487,6 +494,139 @@ hipError_t run_gemm_mfma(const GemmArgs& a, int nf, hipStream_t st) {
   dim3 grid(cdiv(a.ns, kGn), cdiv(a.n, kGm), nf);
   hipLaunchKernelGGL((k_cgemm_mfma<T, MODE, EPI>), grid, dim3(256), 0, st, a);
   return hipGetLastError();
+}
+
+// Split-K form of the same products for the deblur (C has as many rows as
+// there are receivers, a few hundred): a 32 x 32 tile of C per workgroup, so
+// the grid holds about four times as many workgroups and triangular tiles
+// are skipped at 32-row granularity.  The tile's K range is dealt out to the
+// four waves in slices of 4 (slice m of wave w: k = kbeg + 16 m + 4 w + 0..3),
+// each wave accumulating the whole tile (2 x 2 matrix-core tiles of 16 x 16)
+// over its slices, with operands read straight from memory (M, Qhat and the
+// right-hand sides of one frequency are L2-resident) and kept PF slices
+// ahead in registers.  The four partial tiles are then summed through LDS in
+// a fixed order, wave w finishing tile (w >> 1, w & 1).  The longest chain of
+// dependent matrix-core steps is a quarter of the 64 x 64 form's.
+constexpr int kSkT = 32;
+
+template <typename T, int MODE, int EPI>
+__global__ void __launch_bounds__(256) k_cgemm_sk(GemmArgs a) {
+  typedef typename Cx<T>::t C2;
+  typedef typename Mfma<T>::v4 V4;
+  constexpr int PF = 4;                 // slices in flight per wave
+  __shared__ T red[4][2][2][2][4][64];  // [wave][jt][it][re, im][v][lane]
+  const int f = blockIdx.z;
+  const int i0 = blockIdx.y * kSkT, j0 = blockIdx.x * kSkT;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const C2* A = static_cast<const C2*>(a.A) + (size_t)f * a.sA;
+  const C2* B = static_cast<const C2*>(a.B) + (size_t)f * a.sB;
+  int kbeg = 0, kend = a.kdim;
+  if (MODE == 1) kend = min(kend, i0 + kSkT);  // M(i, k) = 0 for k > i
+  if (MODE == 2) kbeg = i0;                    // conj(M(k, i)) = 0 for k < i
+  const int nsl = kend > kbeg ? cdiv(kend - kbeg, 16) : 0;  // slices per wave
+  V4 dr[2][2], di[2][2];  // [j tile][i tile]
+#pragma unroll
+  for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+    for (int it = 0; it < 2; ++it) dr[jt][it] = di[jt][it] = V4{0, 0, 0, 0};
+  C2 pa[PF][2], pb[PF][2];
+  auto load = [&](int m, C2 (&ra)[2], C2 (&rb)[2]) {
+    const int k = kbeg + 16 * m + 4 * wave + l4;
+    const bool kin = k < kend;
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int gi = i0 + 16 * it + l16;
+      C2 v = C2{0, 0};
+      if (kin && gi < a.arows) {
+        if (MODE == 2) {
+          const C2 mv = A[(size_t)k * a.lda + gi];
+          v = C2{mv.x, -mv.y};
+        } else {
+          v = A[(size_t)gi * a.lda + k];
+        }
+      }
+      ra[it] = v;
+    }
+#pragma unroll
+    for (int jt = 0; jt < 2; ++jt) {
+      const int gj = j0 + 16 * jt + l16;
+      rb[jt] = (kin && gj < a.ns) ? B[(size_t)gj * a.ldb + k] : C2{0, 0};
+    }
+  };
+#pragma unroll
+  for (int p = 0; p < PF; ++p) load(p, pa[p], pb[p]);
+  for (int m = 0; m < nsl; m += PF) {
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      if (m + p < nsl) {
+        const C2 av[2] = {pa[p][0], pa[p][1]};
+        const C2 bv[2] = {pb[p][0], pb[p][1]};
+        load(m + p + PF, pa[p], pb[p]);
+#pragma unroll
+        for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+          for (int it = 0; it < 2; ++it) {
+            dr[jt][it] = Mfma<T>::mac(bv[jt].x, av[it].x, dr[jt][it]);
+            dr[jt][it] = Mfma<T>::mac(-bv[jt].y, av[it].y, dr[jt][it]);
+            di[jt][it] = Mfma<T>::mac(bv[jt].x, av[it].y, di[jt][it]);
+            di[jt][it] = Mfma<T>::mac(bv[jt].y, av[it].x, di[jt][it]);
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+    for (int it = 0; it < 2; ++it)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        red[wave][jt][it][0][v][lane] = dr[jt][it][v];
+        red[wave][jt][it][1][v][lane] = di[jt][it][v];
+      }
+  __syncthreads();
+  // lane holds D(row(lane / 16, v), lane % 16) of tile (jt, it)
+  const int jt = wave >> 1, it = wave & 1;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int j = j0 + 16 * jt + Mfma<T>::row(l4, v);
+    const int i = i0 + 16 * it + l16;
+    if (j >= a.ns || i >= a.n) continue;
+    T sr = red[0][jt][it][0][v][lane], si = red[0][jt][it][1][v][lane];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+      sr += red[w][jt][it][0][v][lane];
+      si += red[w][jt][it][1][v][lane];
+    }
+    epi_store<EPI>(a, f, j, i, (double)sr, (double)si);
+  }
+}
+
+template <typename T, int MODE, int EPI>
+hipError_t run_gemm_sk(const GemmArgs& a, int nf, hipStream_t st) {
+  dim3 grid(cdiv(a.ns, kSkT), cdiv(a.n, kSkT), nf);
+  hipLaunchKernelGGL((k_cgemm_sk<T, MODE, EPI>), grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// The deblur's products: the split-K 32 x 32 form where the 64 x 64 form
+// would leave CUs idle (fewer workgroups than CUs) or, with fewer than 2048
+// workgroups, pad a dimension further than 32-row tiles do (200 receivers:
+// 256 against 224); the 64 x 64 form otherwise (measured at 16-256 receivers
+// and sources and at 200 receivers x 2000 sources, 30 frequencies).
+// EHI_SOLVE_TILE = 32 or 64 forces a form (tuning and measurement only).
+template <typename T, int MODE, int EPI>
+hipError_t run_solve_gemm(const GemmArgs& a, int nf, hipStream_t st) {
+  static const int forced = [] {
+    const char* e = std::getenv("EHI_SOLVE_TILE");
+    const int v = e ? std::atoi(e) : 0;
+    return v == 32 || v == 64 ? v : 0;
+  }();
+  const long long g64 = (long long)cdiv(a.ns, kGn) * cdiv(a.n, kGm) * nf;
+  const bool pads = cdiv(a.n, kGm) * kGm > cdiv(a.n, kSkT) * kSkT || cdiv(a.ns, kGn) * kGn > cdiv(a.ns, kSkT) * kSkT;
+  bool sk = g64 < 256 || (g64 < 2048 && pads);
+  if (forced) sk = forced == 32;
+  return sk ? run_gemm_sk<T, MODE, EPI>(a, nf, st) : run_gemm_mfma<T, MODE, EPI>(a, nf, st);
 }
 
 // Largest eigenvalue of each Hhat(w) by power iteration in FP64 (one workgroup
@@ -585,16 +725,16 @@ hipError_t launch_apply(const Geometry& g, const float2* m32, const double2* qha
   a.A = m32; a.sA = npp; a.lda = np; a.arows = np; a.kdim = n;
   a.B = R + (size_t)s0 * n; a.sB = (size_t)rld * n; a.ldb = n;
   a.C = y32; a.sC = sv; a.ldc = n;
-  hipError_t e = run_gemm_mfma<float, 1, kEpiStore>(a, g.nf, st);
+  hipError_t e = run_solve_gemm<float, 1, kEpiStore>(a, g.nf, st);
   if (e != hipSuccess) return e;
   // X = M^H Y
   a.B = y32; a.sB = sv; a.ldb = n;
   if (refine == 0) {
     a.C = out + (size_t)s0 * n; a.sC = (size_t)rld * n; a.ldc = n;
-    return run_gemm_mfma<float, 2, kEpiStore>(a, g.nf, st);
+    return run_solve_gemm<float, 2, kEpiStore>(a, g.nf, st);
   }
   a.X = x64; a.sX = sv; a.ldx = n;
-  e = run_gemm_mfma<float, 2, kEpiX64Set>(a, g.nf, st);
+  e = run_solve_gemm<float, 2, kEpiX64Set>(a, g.nf, st);
   if (e != hipSuccess) return e;
   for (int it = 0; it < refine; ++it) {
     // r = R - Qhat X (FP64)
@@ -603,23 +743,23 @@ hipError_t launch_apply(const Geometry& g, const float2* m32, const double2* qha
     q.B = x64; q.sB = sv; q.ldb = n;
     q.R = R + (size_t)s0 * n; q.sR = (size_t)rld * n; q.ldr = n;
     q.C = r32; q.sC = sv; q.ldc = n;
-    e = run_gemm_mfma<double, 0, kEpiResid>(q, g.nf, st);
+    e = run_solve_gemm<double, 0, kEpiResid>(q, g.nf, st);
     if (e != hipSuccess) return e;
     // Y = M r
     GemmArgs y = a;
     y.A = m32; y.sA = npp; y.lda = np; y.arows = np; y.kdim = n;
     y.B = r32; y.sB = sv; y.ldb = n;
     y.C = y32; y.sC = sv; y.ldc = n;
-    e = run_gemm_mfma<float, 1, kEpiStore>(y, g.nf, st);
+    e = run_solve_gemm<float, 1, kEpiStore>(y, g.nf, st);
     if (e != hipSuccess) return e;
     // X += M^H Y (the last step writes the complex64 result)
     GemmArgs x = y;
     x.B = y32;
     if (it + 1 < refine) {
-      e = run_gemm_mfma<float, 2, kEpiX64Add>(x, g.nf, st);
+      e = run_solve_gemm<float, 2, kEpiX64Add>(x, g.nf, st);
     } else {
       x.C = out + (size_t)s0 * n; x.sC = (size_t)rld * n; x.ldc = n;
-      e = run_gemm_mfma<float, 2, kEpiOut>(x, g.nf, st);
+      e = run_solve_gemm<float, 2, kEpiOut>(x, g.nf, st);
     }
     if (e != hipSuccess) return e;
   }
