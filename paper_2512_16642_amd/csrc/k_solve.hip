@@ -610,10 +610,11 @@ hipError_t run_gemm_sk(const GemmArgs& a, int nf, hipStream_t st) {
 }
 
 // The deblur's products: the split-K 32 x 32 form where the 64 x 64 form
-// would leave CUs idle (fewer workgroups than CUs) or, with fewer than 2048
+// would leave CUs idle (fewer workgroups than CUs) or, with fewer than 640
 // workgroups, pad a dimension further than 32-row tiles do (200 receivers:
-// 256 against 224); the 64 x 64 form otherwise (measured at 16-256 receivers
-// and sources and at 200 receivers x 2000 sources, 30 frequencies).
+// 256 against 224); the 64 x 64 form otherwise (measured from 16 to 400
+// receivers and sources, 200 receivers x 2000 sources, and the sizes of the
+// batched surveys: the 64 x 64 form is ahead from about 750 workgroups).
 // EHI_SOLVE_TILE = 32 or 64 forces a form (tuning and measurement only).
 template <typename T, int MODE, int EPI>
 hipError_t run_solve_gemm(const GemmArgs& a, int nf, hipStream_t st) {
@@ -624,7 +625,7 @@ hipError_t run_solve_gemm(const GemmArgs& a, int nf, hipStream_t st) {
   }();
   const long long g64 = (long long)cdiv(a.ns, kGn) * cdiv(a.n, kGm) * nf;
   const bool pads = cdiv(a.n, kGm) * kGm > cdiv(a.n, kSkT) * kSkT || cdiv(a.ns, kGn) * kGn > cdiv(a.ns, kSkT) * kSkT;
-  bool sk = g64 < 256 || (g64 < 2048 && pads);
+  bool sk = g64 < 256 || (g64 < 640 && pads);
   if (forced) sk = forced == 32;
   return sk ? run_gemm_sk<T, MODE, EPI>(a, nf, st) : run_gemm_mfma<T, MODE, EPI>(a, nf, st);
 }

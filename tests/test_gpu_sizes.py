@@ -14,8 +14,10 @@ grid partitions and ends on a ragged tail.
 
 Factor + solve from a given Hessian (the oracle's FP64 Hhat of the same
 spectra, mu = 1e-3 lambda_max, so cond(Qhat) ~ 1e3 as in the surveys' low
-frequencies) at 1, 33, 200, 400 and 1024 receivers: the FP64 factor against scipy's, the
-multipliers of 64 sources against the oracle's solve.
+frequencies) at 1, 33, 200, 256, 400 and 1024 receivers: the FP64 factor against scipy's, the
+multipliers of 64 sources against the oracle's solve (the split-K 32 x 32 deblur
+products), and of 1408 sources at 256 receivers (enough right-hand sides for
+the 64 x 64 products).
 
 Tolerances as for the tiny survey (tests/test_gpu_parity.py): 2e-6 per
 frequency for the Hessian and the solve, 1e-12 for the FP64 factor; the
@@ -74,9 +76,9 @@ def test_hessian_from_given_spectra_sizes(ehi, nr, prec):
         assert np.all(d.imag == 0) and np.all(d.real > 0)
 
 
-@pytest.mark.parametrize("nr", [1, 33, 200, 400, 1024])
-def test_factor_and_solve_from_given_hessian_sizes(ehi, nr):
-    s = _survey(nr)
+@pytest.mark.parametrize("nr,ns", [(1, 64), (33, 64), (200, 64), (256, 64), (256, 1408), (400, 64), (1024, 64)])
+def test_factor_and_solve_from_given_hessian_sizes(ehi, nr, ns):
+    s = _survey(nr, ns)
     _, H = _spectra(nr)
     mu = 1e-3 * solve.lambda_max(H)
     R = synth.residuals(NF, s.ns, nr, seed=900 + nr)
@@ -89,7 +91,7 @@ def test_factor_and_solve_from_given_hessian_sizes(ehi, nr):
     Xg = sv.apply_multipliers(torch.from_numpy(R).cuda()).cpu().numpy()
     sv.close()
     check(Lg, L, 1e-12, 1e-12, 1e-11, f"nr={nr} FP64 factor")
-    check(Xg, X, 2e-6, 2e-6, 4e-6, f"nr={nr} solve")
+    check(Xg, X, 2e-6, 2e-6, 4e-6, f"nr={nr} ns={ns} solve")
 
 
 @pytest.mark.parametrize("nr,form,split", [(200, 1, 1), (200, 1, 7), (200, 2, 3), (200, 2, 12), (200, 0, 64),
