@@ -1,6 +1,6 @@
 // HBM probe: plain streaming kernels with a chosen mix of reads and writes, to
 // measure the rate the memory system delivers for a kernel's access mix (the
-// ceiling against which the marching kernel's measured traffic is judged).
+// ceiling that the marching kernel's measured traffic is compared with).
 // Each thread handles 16-byte vectors in a grid-stride loop; reads are used
 // in the values written, so none can be elided.
 #include <hip/hip_runtime.h>
