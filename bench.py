@@ -48,9 +48,13 @@ def parse():
     ap.add_argument("--workload", default="layered_1000x300",
                     help="layered_1000x300 (default), tiny, batch8 (the eight uneven surveys), serve "
                          "(Poisson request mix over the eight surveys), accuracy (the Hessian "
-                         "accuracy test on the 1000 x 300 survey) or randomized (one receiver per "
-                         "subset, factors reused over iterations, on the 1000 x 300 survey)")
+                         "accuracy test on the 1000 x 300 survey), randomized (one receiver per "
+                         "subset, factors reused over iterations, on the 1000 x 300 survey), "
+                         "deblur (the multi-source solve alone, by size), compare (both precision "
+                         "forms on one workspace) or hbm_probe (streaming rates by access mix)")
     ap.add_argument("--batch-nt", type=int, default=4000, help="time steps of the batch8 surveys")
+    ap.add_argument("--deblur-sizes", default="16x16,64x64,128x128,200x200,256x256,300x300,400x400,200x2000",
+                    help="deblur: receivers x sources per size (comma separated)")
     ap.add_argument("--staging-gb", type=float, default=32.0,
                     help="batch8: staging budget per survey (sets the receivers stepped together)")
     ap.add_argument("--batch-chunk", type=int, default=512, choices=[256, 512, 1024],
@@ -523,6 +527,60 @@ def run_randomized(args):
     print(json.dumps(out), flush=True)
 
 
+def run_deblur(args):
+    """The deblur alone (ehi_apply_multipliers) at a list of sizes: seeded
+    Hermitian positive definite Hessians H = A A^H / nr (A complex Gaussian,
+    FP64), mu = 1e-3 lambda_max, the 1000 x 300 survey's 30 frequencies, both
+    precision forms; every size's right-hand sides deblurred 10 x steps times
+    between two events on the survey's stream."""
+    import torch
+
+    import synth
+    from paper_2512_16642_amd import ehi
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    base = synth.layered_1000x300()
+    sizes = [tuple(int(v) for v in x.split("x")) for x in args.deblur_sizes.split(",")]
+    reps = 10 * max(1, args.steps)
+    rows = []
+    for nr, ns in sizes:
+        if not (1 <= nr <= 500 and ns >= 1):
+            raise SystemExit(f"deblur size {nr}x{ns}: receivers must be in [1, 500]")
+        s = base.with_(nt=8, ns=ns, rec_iz=(2,) * nr, rec_ix=tuple(2 + 2 * k for k in range(nr)))
+        g = torch.Generator(device="cpu").manual_seed(3100 + nr)
+        A = torch.randn((s.nf, nr, nr), dtype=torch.complex128, generator=g)
+        H = (A @ A.conj().transpose(1, 2).contiguous() / nr).to(dev)
+        R = torch.randn((s.nf, ns, nr), dtype=torch.complex64, generator=g).to(dev)
+        row = {"nr": nr, "ns": ns, "nf": s.nf}
+        for prec in ("split_bf16", "plain_fp32"):
+            sv = ehi.survey_from(s, precision=prec, max_ns=ns)
+            sv.load_hessian(H)
+            sv.factor(1e-3 * sv.lambda_max())
+            X = sv.apply_multipliers(R)
+            for _ in range(max(0, args.warmup)):
+                sv.apply_multipliers(R, out=X)
+            st = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(reps):
+                sv.apply_multipliers(R, out=X)
+            e1.record(st)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            row[prec] = {"ms": round(ms, 4), "solves_per_s": round(s.nf * ns / (ms / 1e3), 1)}
+            sv.close()
+        rows.append(row)
+        print(f"# deblur {nr} x {ns}: split {row['split_bf16']['ms']:.4f} ms, "
+              f"plain {row['plain_fp32']['ms']:.4f} ms", file=sys.stderr, flush=True)
+    head = next((r for r in rows if r["nr"] == 200 and r["ns"] == 200), rows[0])
+    out = {"metric": "deblur alone: multiplier solves/s by size", "value": head["split_bf16"]["solves_per_s"],
+           "unit": "solves/s", "n_gpus": 1, "steps": reps, "warmup": args.warmup, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"deblur-{head['nr']}x{head['ns']}-nf{head['nf']}"}, "sizes": rows}
+    print(json.dumps(out), flush=True)
+
+
 def run_accuracy(args):
     """The Hessian accuracy test on the 1000 x 300 layered survey: frequencies
     moved to the nearest bins of the 2nt-point transform, factors of the
@@ -665,12 +723,13 @@ def run_accuracy(args):
 
 def main():
     args = parse()
-    if args.workload in ("batch8", "serve", "accuracy", "randomized", "compare", "hbm_probe"):
+    if args.workload in ("batch8", "serve", "accuracy", "randomized", "compare", "hbm_probe", "deblur"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
         {"batch8": run_batch, "serve": run_serve, "accuracy": run_accuracy,
-         "randomized": run_randomized, "compare": run_compare, "hbm_probe": run_hbm_probe}[args.workload](args)
+         "randomized": run_randomized, "compare": run_compare, "hbm_probe": run_hbm_probe,
+         "deblur": run_deblur}[args.workload](args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "

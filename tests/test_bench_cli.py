@@ -15,13 +15,15 @@ def run(*args):
 def test_help_lists_workloads_and_options():
     r = run("--help")
     assert r.returncode == 0
-    for opt in ("--workload", "--keep", "--subsets", "--reuse", "--windows", "--chunk", "--weighting"):
+    for opt in ("--workload", "--keep", "--subsets", "--reuse", "--windows", "--chunk", "--weighting",
+                "--deblur-sizes"):
         assert opt in r.stdout
-    assert "randomized" in r.stdout
+    for w in ("randomized", "deblur", "compare", "hbm_probe"):
+        assert w in r.stdout
 
 
 def test_more_than_one_gpu_is_refused():
-    for extra in ([], ["--workload", "batch8"], ["--workload", "randomized"]):
+    for extra in ([], ["--workload", "batch8"], ["--workload", "randomized"], ["--workload", "deblur"]):
         r = run("--gpus", "2", *extra)
         assert r.returncode == 2, (extra, r.stderr)
         assert "one GPU" in r.stderr
