@@ -16,8 +16,8 @@ Factor + solve from a given Hessian (the oracle's FP64 Hhat of the same
 spectra, mu = 1e-3 lambda_max, so cond(Qhat) ~ 1e3 as in the surveys' low
 frequencies) at 1, 33, 200, 256, 400 and 1024 receivers: the FP64 factor against scipy's, the
 multipliers of 64 sources against the oracle's solve (the split-K 32 x 32 deblur
-products), and of 1408 sources at 256 receivers (enough right-hand sides for
-the 64 x 64 products).
+products; 47 sources at 200 receivers for a ragged source tile), and of 1408
+sources at 256 receivers (enough right-hand sides for the 64 x 64 products).
 
 Tolerances as for the tiny survey (tests/test_gpu_parity.py): 2e-6 per
 frequency for the Hessian and the solve, 1e-12 for the FP64 factor; the
@@ -76,7 +76,8 @@ def test_hessian_from_given_spectra_sizes(ehi, nr, prec):
         assert np.all(d.imag == 0) and np.all(d.real > 0)
 
 
-@pytest.mark.parametrize("nr,ns", [(1, 64), (33, 64), (200, 64), (256, 64), (256, 1408), (400, 64), (1024, 64)])
+@pytest.mark.parametrize("nr,ns", [(1, 64), (33, 64), (200, 64), (200, 47), (256, 64), (256, 1408), (400, 64),
+                                   (1024, 64)])
 def test_factor_and_solve_from_given_hessian_sizes(ehi, nr, ns):
     s = _survey(nr, ns)
     _, H = _spectra(nr)
