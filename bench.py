@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_SOURCE = ("not measured in this run: the counters of a separate rocprofv3 --pmc collection of "
                   "the same launch shape, profiles/survey_layered-1000x300_pmc.md")
 MEASURED_TRAFFIC = {
-    ("layered-1000x300-nr200-nt4000-nf30-ns200", "split_bf16", 8, 256, 256, 200): (417170.5 * 2 + 1150953.0) * 1024,
+    ("layered-1000x300-nr200-nt4000-nf30-ns200", "split_bf16", 8, 256, 256, 200): (417482.5 * 2 + 1150948.6) * 1024,
 }
 
 
