@@ -76,8 +76,10 @@ def parse():
     ap.add_argument("--cg-iters", type=int, default=60, help="accuracy: cap on the CG baseline's iterations")
     ap.add_argument("--chunk", type=int, default=1024, choices=[256, 512, 1024],
                     help="time samples per DFT staging window")
-    ap.add_argument("--windows", type=int, default=1, choices=[1, 2],
-                    help="staging windows (2: the DFT of one overlaps the stepping of the next)")
+    ap.add_argument("--windows", type=int, default=2, choices=[1, 2],
+                    help="staging windows (2, the default: the DFT of one window runs on a second "
+                         "stream beside the stepping of the next, 5-6 %% faster per survey for twice "
+                         "the staging memory; 1: one window, DFT after stepping)")
     ap.add_argument("--keep", type=int, nargs=2, default=[0, 0], metavar=("KZ", "KX"),
                     help="contract the leading KZ x KX 2D DCT-II coefficients of the subgrid "
                          "instead of the grid points (0 0: no transform)")
