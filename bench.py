@@ -306,7 +306,7 @@ def run_compare(args):
     vel = torch.from_numpy(s.velocity()).to(dev)
     R = torch.from_numpy(s.residuals()).to(dev)
     X = torch.empty_like(R)
-    kw = dict(max_ns=s.ns, chunk=args.chunk)
+    kw = dict(max_ns=s.ns, chunk=args.chunk, windows=args.windows)
     need = max(ehi.workspace_bytes(nz=s.nz, nx=s.nx, nb=s.nb, h=s.h, dt=s.dt, nt=s.nt, stride=s.stride,
                                    rec_iz=s.rec_iz, rec_ix=s.rec_ix, freqs_hz=s.freqs_hz, precision=p,
                                    nr_batch=0, **kw)
@@ -350,7 +350,8 @@ def run_compare(args):
     out = {"metric": "chosen vs plain FP32 form on one workspace: s/survey and multiplier solves/s",
            "value": res["split_bf16"]["s_per_survey"], "unit": "s/survey", "n_gpus": 1, "steps": args.steps,
            "warmup": 1, "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-           "data": "synthetic", "config": {"workload": s.name, "chunk": args.chunk}, "forms": res}
+           "data": "synthetic", "config": {"workload": s.name, "chunk": args.chunk, "windows": args.windows},
+           "forms": res}
     print(json.dumps(out), flush=True)
 
 
