@@ -2,8 +2,9 @@
 
 Workload: layered 1000 x 300 grid (h = 10 m, 40-cell sponge), 200 receivers,
 nt = 4000 at 0.8 ms, 30 frequencies over 3-15 Hz, 200 sources, stride 2,
-split-BF16 form, default launch shapes, 1024-sample staging window and the
-whole-matrix contraction (as bench.py times them).
+split-BF16 form, default launch shapes, two 1024-sample staging windows (the
+DFT of one beside the stepping of the next) and the whole-matrix contraction
+(as bench.py times them); one window gives the same bits.
 
 The FP64 oracle builds all 200 Green functions on the host (the C recurrence,
 OpenMP over grid rows, the DFT taken window by window so the time history is
@@ -79,7 +80,7 @@ def full(ehi, oracle_full):
     s = oracle_full["s"]
     v = oracle_full["v"]
     mu = oracle_full["mu"]
-    sv = ehi.survey_from(s, precision="split_bf16", chunk=1024)   # the benchmark's window
+    sv = ehi.survey_from(s, precision="split_bf16", chunk=1024, windows=2)   # the benchmark's windows
     vel = torch.from_numpy(v).cuda()
     sv.build_green(vel)
     sv.build_hessian()
@@ -116,6 +117,18 @@ def test_full_multipliers_all_sources(full, oracle_full):
     X = full["X"].cpu().numpy()
     e = check(X, oracle_full["X"], 1e-5, 1e-5, 1e-5, "full-size multipliers, all sources")
     _report("x", e)
+
+
+def test_full_one_window_same_bits(ehi, full):
+    # one staging window (the DFT after the steps, on the survey's stream)
+    # against the two overlapped windows of the fixture: the same kernels in
+    # the same order of accumulation
+    s = full["s"]
+    sv = ehi.survey_from(s, precision="split_bf16", chunk=1024, windows=1)
+    sv.build_green(torch.from_numpy(full["v"]).cuda())
+    G1 = sv.copy_green_dft()
+    sv.close()
+    assert torch.equal(G1, full["G"])
 
 
 def test_full_reciprocity(full):
