@@ -886,6 +886,17 @@ def main():
         "dft_tflops": round(dft_flops / (dft_ms / 1e3) / 1e12, 2) if dft_ms > 0 else None,
         "roofline": roof,
     }
+    # the Green-function stage as a whole: the stepping's and the DFT's
+    # algorithmic bytes over the stage's own time (with two staging windows the
+    # two kernels run side by side, so neither one's average duration shows the
+    # stage's use of HBM)
+    if dft_ms > 0 and stage_ms["build_green"] > 0 and args.weighting == "long_record" and not compressed:
+        stage_bytes = bytes_total / K + dft_bytes
+        stage_gbs = stage_bytes / (stage_ms["build_green"] / 1e3) / 1e9
+        out["roofline_green_stage"] = {"kernels": "k_march + k_dft_bf16x3", "bound": "hbm",
+                                       "achieved": round(stage_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": round(stage_gbs / HBM_PEAK_GBS, 4),
+                                       "bytes_per_survey": round(stage_bytes), "stage_ms": round(stage_ms["build_green"], 3)}
     # the two other hot kernels against their own peaks (the contraction on the
     # BF16 matrix cores; the DFT on the FP32 matrix cores, its bytes beside)
     herk_exec = out["herk_mfma_bf16_tflops"]
