@@ -89,3 +89,28 @@ def test_factor_batch_reports_failing_survey(mods):
         hs[1].apply_multipliers(torch.from_numpy(specs[1].residuals()).cuda())
     for sv in hs:
         sv.close()
+
+
+def test_largest_batch_survey_sampled_against_oracle(mods):
+    # the batch's largest survey (1700 x 350 grid, 400 receivers, 40
+    # frequencies over 3-20 Hz) on a short record: every stage at its real
+    # size, including the whole-matrix contraction's 4 x 4 tiles of block
+    # pairs (receivers past 224); six receivers spread over different 32-row
+    # blocks and tiles are checked against the oracle's Green functions and the
+    # Hessian block among them
+    ehi, _ = mods
+    s = synth.batch_survey(1, nt=64)
+    v = s.velocity()
+    sample = [0, 57, 130, 229, 311, 399]
+    sv = ehi.survey_from(s, precision="split_bf16", max_ns=1)
+    sv.build_green(torch.from_numpy(v).cuda())
+    sv.build_hessian()
+    G = sv.copy_green_dft().reshape(s.nf, s.nr, -1)
+    H = sv.copy_hessian()
+    sv.close()
+    Gs = G[:, sample].cpu().numpy()
+    Hs = H[:, sample][:, :, sample].cpu().numpy()
+    Go = fd.green_dft(s, v, receivers=sample)
+    Ho = np.stack([Go[f] @ Go[f].conj().T for f in range(s.nf)])
+    check(Gs, Go, 5e-6, 5e-6, 2e-5, "batch survey 1 (400 receivers) sampled ghat")
+    check(Hs, Ho, 1e-5, 1e-5, 2e-5, "batch survey 1 (400 receivers) sampled Hhat block")
