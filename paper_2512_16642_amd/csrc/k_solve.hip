@@ -510,10 +510,15 @@ hipError_t run_gemm_mfma(const GemmArgs& a, int nf, hipStream_t st) {
 constexpr int kSkT = 32;
 
 template <typename T, int MODE, int EPI>
-__global__ void __launch_bounds__(256) k_cgemm_sk(GemmArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_cgemm_sk(GemmArgs a) {
   typedef typename Cx<T>::t C2;
   typedef typename Mfma<T>::v4 V4;
-  constexpr int PF = 4;                 // slices in flight per wave
+  // FP64 (the refinement residual): each complex product as three real ones,
+  // P1 = Br Ar, P2 = Bi Ai, P3 = (Br + Bi)(Ar + Ai), Re = P1 - P2,
+  // Im = P3 - P1 - P2 (the cancellation costs a bit or two of FP64's 53);
+  // FP32: the four real products
+  constexpr bool G3 = sizeof(T) == 8;
+  constexpr int PF = G3 ? 2 : 4;        // slices in flight per wave
   __shared__ T red[4][2][2][2][4][64];  // [wave][jt][it][re, im][v][lane]
   const int f = blockIdx.z;
   const int i0 = blockIdx.y * kSkT, j0 = blockIdx.x * kSkT;
@@ -525,11 +530,16 @@ __global__ void __launch_bounds__(256) k_cgemm_sk(GemmArgs a) {
   if (MODE == 1) kend = min(kend, i0 + kSkT);  // M(i, k) = 0 for k > i
   if (MODE == 2) kbeg = i0;                    // conj(M(k, i)) = 0 for k < i
   const int nsl = kend > kbeg ? cdiv(kend - kbeg, 16) : 0;  // slices per wave
-  V4 dr[2][2], di[2][2];  // [j tile][i tile]
+  V4 dr[2][2], di[2][2];          // [j tile][i tile]; FP64: P1, P2
+  V4 d3[G3 ? 2 : 1][G3 ? 2 : 1];  // FP64: P3
 #pragma unroll
   for (int jt = 0; jt < 2; ++jt)
 #pragma unroll
     for (int it = 0; it < 2; ++it) dr[jt][it] = di[jt][it] = V4{0, 0, 0, 0};
+#pragma unroll
+  for (int jt = 0; jt < (G3 ? 2 : 1); ++jt)
+#pragma unroll
+    for (int it = 0; it < (G3 ? 2 : 1); ++it) d3[jt][it] = V4{0, 0, 0, 0};
   C2 pa[PF][2], pb[PF][2];
   auto load = [&](int m, C2 (&ra)[2], C2 (&rb)[2]) {
     const int k = kbeg + 16 * m + 4 * wave + l4;
@@ -563,15 +573,28 @@ __global__ void __launch_bounds__(256) k_cgemm_sk(GemmArgs a) {
         const C2 av[2] = {pa[p][0], pa[p][1]};
         const C2 bv[2] = {pb[p][0], pb[p][1]};
         load(m + p + PF, pa[p], pb[p]);
+        if constexpr (G3) {
+          const T as[2] = {av[0].x + av[0].y, av[1].x + av[1].y};
+          const T bs[2] = {bv[0].x + bv[0].y, bv[1].x + bv[1].y};
 #pragma unroll
-        for (int jt = 0; jt < 2; ++jt)
+          for (int jt = 0; jt < 2; ++jt)
 #pragma unroll
-          for (int it = 0; it < 2; ++it) {
-            dr[jt][it] = Mfma<T>::mac(bv[jt].x, av[it].x, dr[jt][it]);
-            dr[jt][it] = Mfma<T>::mac(-bv[jt].y, av[it].y, dr[jt][it]);
-            di[jt][it] = Mfma<T>::mac(bv[jt].x, av[it].y, di[jt][it]);
-            di[jt][it] = Mfma<T>::mac(bv[jt].y, av[it].x, di[jt][it]);
-          }
+            for (int it = 0; it < 2; ++it) {
+              dr[jt][it] = Mfma<T>::mac(bv[jt].x, av[it].x, dr[jt][it]);
+              di[jt][it] = Mfma<T>::mac(bv[jt].y, av[it].y, di[jt][it]);
+              d3[jt][it] = Mfma<T>::mac(bs[jt], as[it], d3[jt][it]);
+            }
+        } else {
+#pragma unroll
+          for (int jt = 0; jt < 2; ++jt)
+#pragma unroll
+            for (int it = 0; it < 2; ++it) {
+              dr[jt][it] = Mfma<T>::mac(bv[jt].x, av[it].x, dr[jt][it]);
+              dr[jt][it] = Mfma<T>::mac(-bv[jt].y, av[it].y, dr[jt][it]);
+              di[jt][it] = Mfma<T>::mac(bv[jt].x, av[it].y, di[jt][it]);
+              di[jt][it] = Mfma<T>::mac(bv[jt].y, av[it].x, di[jt][it]);
+            }
+        }
       }
     }
   }
@@ -581,8 +604,13 @@ __global__ void __launch_bounds__(256) k_cgemm_sk(GemmArgs a) {
     for (int it = 0; it < 2; ++it)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        red[wave][jt][it][0][v][lane] = dr[jt][it][v];
-        red[wave][jt][it][1][v][lane] = di[jt][it][v];
+        if constexpr (G3) {
+          red[wave][jt][it][0][v][lane] = dr[jt][it][v] - di[jt][it][v];
+          red[wave][jt][it][1][v][lane] = d3[jt][it][v] - dr[jt][it][v] - di[jt][it][v];
+        } else {
+          red[wave][jt][it][0][v][lane] = dr[jt][it][v];
+          red[wave][jt][it][1][v][lane] = di[jt][it][v];
+        }
       }
   __syncthreads();
   // lane holds D(row(lane / 16, v), lane % 16) of tile (jt, it)
@@ -610,11 +638,12 @@ hipError_t run_gemm_sk(const GemmArgs& a, int nf, hipStream_t st) {
 }
 
 // The deblur's products: the split-K 32 x 32 form where the 64 x 64 form
-// would leave CUs idle (fewer workgroups than CUs) or, with fewer than 640
+// would leave CUs idle (fewer workgroups than CUs) or, with fewer than 2048
 // workgroups, pad a dimension further than 32-row tiles do (200 receivers:
 // 256 against 224); the 64 x 64 form otherwise (measured from 16 to 400
 // receivers and sources, 200 receivers x 2000 sources, and the sizes of the
-// batched surveys: the 64 x 64 form is ahead from about 750 workgroups).
+// batched surveys: the 64 x 64 form is ahead without the extra padding, at
+// 256 receivers and sources, and with 3840 of its workgroups).
 // EHI_SOLVE_TILE = 32 or 64 forces a form (tuning and measurement only).
 template <typename T, int MODE, int EPI>
 hipError_t run_solve_gemm(const GemmArgs& a, int nf, hipStream_t st) {
@@ -625,7 +654,7 @@ hipError_t run_solve_gemm(const GemmArgs& a, int nf, hipStream_t st) {
   }();
   const long long g64 = (long long)cdiv(a.ns, kGn) * cdiv(a.n, kGm) * nf;
   const bool pads = cdiv(a.n, kGm) * kGm > cdiv(a.n, kSkT) * kSkT || cdiv(a.ns, kGn) * kGn > cdiv(a.ns, kSkT) * kSkT;
-  bool sk = g64 < 256 || (g64 < 640 && pads);
+  bool sk = g64 < 256 || (g64 < 2048 && pads);
   if (forced) sk = forced == 32;
   return sk ? run_gemm_sk<T, MODE, EPI>(a, nf, st) : run_gemm_mfma<T, MODE, EPI>(a, nf, st);
 }
