@@ -305,8 +305,8 @@ def test_refinement_steps(ehi, tiny_ref):
         sv.set_refinement(steps)
         out[steps] = sv.apply_multipliers(dev(tiny_ref["R"])).cpu().numpy()
         sv.close()
-    check(out[1], tiny_ref["X"], 2e-6, 2e-6, 4e-6, "one refinement step")
-    check(out[2], tiny_ref["X"], 2e-6, 2e-6, 4e-6, "two refinement steps")
+    check(out[1], tiny_ref["X"], 1e-7, 1.5e-7, 2e-7, "one refinement step")
+    check(out[2], tiny_ref["X"], 1e-7, 1.5e-7, 2e-7, "two refinement steps")
     check(out[0], tiny_ref["X"], 1e-3, 1e-3, None, "no refinement")
     sp = ehi.survey_from(s, precision="plain_fp32")
     with pytest.raises(ehi.EhiError):
