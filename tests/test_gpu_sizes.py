@@ -19,10 +19,12 @@ multipliers of 64 sources against the oracle's solve (the split-K 32 x 32 deblur
 products; 47 sources at 200 receivers for a ragged source tile), and of 1408
 sources at 256 receivers (enough right-hand sides for the 64 x 64 products).
 
-Tolerances: 2e-6 per frequency for the Hessian (as for the tiny survey,
-tests/test_gpu_parity.py), 1e-12 for the FP64 factor, and for the refined
-solve 1e-7 (the complex64 output's rounding is 6e-8 per element); the
-element-wise and per-row measures of tests/parity.py beside them.
+Tolerances: 1e-6 per frequency for the split-BF16 Hessian at the default
+partition counts (2e-6 for the forms and partition counts the autotuner may
+choose, as for the tiny survey, tests/test_gpu_parity.py), 2.5e-7 for the
+plain FP32 contraction, 1e-12 for the FP64 factor, and for the refined solve
+1e-7 (the complex64 output's rounding is 6e-8 per element); the element-wise
+and per-row measures of tests/parity.py beside them.
 """
 import numpy as np
 import pytest
@@ -70,7 +72,13 @@ def test_hessian_from_given_spectra_sizes(ehi, nr, prec):
     sv.build_hessian()
     H = sv.copy_hessian().cpu().numpy()
     sv.close()
-    check(H, ref, 2e-6, 2e-6, 4e-6, f"nr={nr} {prec} hessian")
+    # split-BF16 (four hi/lo products, FP32 running sums per partition): up to
+    # 3.3e-7 measured at 1024 receivers; FP32 operands on the FP32 matrix
+    # cores: up to 1.3e-7 per row
+    if prec == "split_bf16":
+        check(H, ref, 1e-6, 1e-6, 1.5e-6, f"nr={nr} {prec} hessian")
+    else:
+        check(H, ref, 2.5e-7, 4e-7, 6e-7, f"nr={nr} {prec} hessian")
     for f in range(NF):
         np.testing.assert_array_equal(H[f], H[f].conj().T)
         d = np.diagonal(H[f])
