@@ -509,6 +509,22 @@ hipError_t run_gemm_mfma(const GemmArgs& a, int nf, hipStream_t st) {
 // dependent matrix-core steps is a quarter of the 64 x 64 form's.
 constexpr int kSkT = 32;
 
+// Operand loads of the split-K products through buffer resources: an offset
+// past the resource (rows past the matrix, or kSkDrop for k outside the
+// product's K range) reads zero, and the slice's step is a scalar offset, so
+// a lane computes its offsets once.
+constexpr unsigned kSkDrop = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t sk_rsrc(const void* base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+template <typename C2> __device__ __forceinline__ C2 sk_load(__amdgpu_buffer_rsrc_t r, unsigned vo, int so);
+template <> __device__ __forceinline__ float2 sk_load<float2>(__amdgpu_buffer_rsrc_t r, unsigned vo, int so) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, so, 0));
+}
+template <> __device__ __forceinline__ double2 sk_load<double2>(__amdgpu_buffer_rsrc_t r, unsigned vo, int so) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, so, 0));
+}
+
 template <typename T, int MODE, int EPI>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_cgemm_sk(GemmArgs a) {
   typedef typename Cx<T>::t C2;
@@ -541,28 +557,30 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 #pragma unroll
     for (int it = 0; it < (G3 ? 2 : 1); ++it) d3[jt][it] = V4{0, 0, 0, 0};
   C2 pa[PF][2], pb[PF][2];
+  // resources over this frequency's A (arows x lda) and B (ns x ldb); the
+  // lane's byte offsets at slice 0 and the per-slice steps
+  constexpr int SZ = (int)sizeof(C2);
+  const __amdgpu_buffer_rsrc_t rsa = sk_rsrc(A, (size_t)a.arows * a.lda * SZ);
+  const __amdgpu_buffer_rsrc_t rsb = sk_rsrc(B, (size_t)a.ns * a.ldb * SZ);
+  const int kl = kbeg + 4 * wave + l4;
+  unsigned ao[2], bo[2];
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int gi = i0 + 16 * it + l16;
+    ao[it] = (unsigned)((MODE == 2 ? kl * a.lda + gi : gi * a.lda + kl) * SZ);
+  }
+#pragma unroll
+  for (int jt = 0; jt < 2; ++jt) bo[jt] = (unsigned)(((j0 + 16 * jt + l16) * a.ldb + kl) * SZ);
+  const int astep = (MODE == 2 ? 16 * a.lda : 16) * SZ, bstep = 16 * SZ;
   auto load = [&](int m, C2 (&ra)[2], C2 (&rb)[2]) {
-    const int k = kbeg + 16 * m + 4 * wave + l4;
-    const bool kin = k < kend;
+    const bool kin = kl + 16 * m < kend;
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
-      const int gi = i0 + 16 * it + l16;
-      C2 v = C2{0, 0};
-      if (kin && gi < a.arows) {
-        if (MODE == 2) {
-          const C2 mv = A[(size_t)k * a.lda + gi];
-          v = C2{mv.x, -mv.y};
-        } else {
-          v = A[(size_t)gi * a.lda + k];
-        }
-      }
-      ra[it] = v;
+      const C2 v = sk_load<C2>(rsa, kin ? ao[it] : kSkDrop, m * astep);
+      ra[it] = MODE == 2 ? C2{v.x, -v.y} : v;
     }
 #pragma unroll
-    for (int jt = 0; jt < 2; ++jt) {
-      const int gj = j0 + 16 * jt + l16;
-      rb[jt] = (kin && gj < a.ns) ? B[(size_t)gj * a.ldb + k] : C2{0, 0};
-    }
+    for (int jt = 0; jt < 2; ++jt) rb[jt] = sk_load<C2>(rsb, kin ? bo[jt] : kSkDrop, m * bstep);
   };
 #pragma unroll
   for (int p = 0; p < PF; ++p) load(p, pa[p], pb[p]);
