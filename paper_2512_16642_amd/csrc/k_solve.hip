@@ -12,13 +12,12 @@
 // frequency) with no sequential dependency between rows.  In the split-BF16
 // precision mode refinement steps follow (one by default, 0-3 selectable):
 // r = R - Qhat X in FP64 (X kept in FP64), X += M^H (M r) in FP32.  These products run on the matrix cores
-// (k_cgemm_mfma); k_cgemm, the same tiling on FMAs with a choice of B layout
+// (k_cgemm_sk); k_cgemm, a 64 x 64 tiling on FMAs with a choice of B layout
 // and of the summation type, serves the DCT passes and the compressed
 // contraction.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cstdlib>
 
 #include "ehi_internal.h"
 
@@ -343,10 +342,8 @@ hipError_t run_gemm(const GemmArgs& a, int nf, hipStream_t st) {
 // The matrix cores form the transpose D(j, i) = sum_k B(k, j) op(A)(i, k): row
 // index = source j, column index = i, so the 16 lanes of a result row hold 16
 // consecutive i, the contiguous index of every output.  A complex product is
-// four real ones: Re D = Br Ar - Bi Ai, Im D = Br Ai + Bi Ar.
-// Workgroup: a 64 x 64 tile of C, K in LDS stages of 16 (double-buffered, the
-// next stage prefetched into registers as in k_cgemm); wave w computes the 32
-// (i) x 32 (j) quarter (i-half w & 1, j-half w >> 1) as 2 x 2 tiles of 16 x 16.
+// four real ones: Re D = Br Ar - Bi Ai, Im D = Br Ai + Bi Ar (the FP64 form
+// takes three, below).
 typedef float mf32x4 __attribute__((ext_vector_type(4)));
 typedef double mf64x4 __attribute__((ext_vector_type(4)));
 template <typename T> struct Mfma;
@@ -393,120 +390,18 @@ __device__ __forceinline__ void epi_store(const GemmArgs& a, int f, int j, int i
   }
 }
 
-template <typename T, int MODE, int EPI>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_cgemm_mfma(GemmArgs a) {
-  typedef typename Cx<T>::t C2;
-  typedef typename Mfma<T>::v4 V4;
-  // [stage][k][i or j]; one padding element per row staggers the rows' banks
-  __shared__ C2 As[2][kGk][kGm + 1];
-  __shared__ C2 Bs[2][kGk][kGn + 1];
-  const int f = blockIdx.z;
-  const int i0 = blockIdx.y * kGm, j0 = blockIdx.x * kGn;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wi = (wave & 1) * 32, wj = (wave >> 1) * 32;
-  const int l16 = lane & 15, l4 = lane >> 4;
-  const C2* A = static_cast<const C2*>(a.A) + (size_t)f * a.sA;
-  const C2* B = static_cast<const C2*>(a.B) + (size_t)f * a.sB;
-  V4 dr[2][2], di[2][2];  // [j tile][i tile]
-#pragma unroll
-  for (int jt = 0; jt < 2; ++jt)
-#pragma unroll
-    for (int it = 0; it < 2; ++it) dr[jt][it] = di[jt][it] = V4{0, 0, 0, 0};
-  int kbeg = 0, kend = a.kdim;
-  if (MODE == 1) kend = min(kend, i0 + kGm);  // M(i, k) = 0 for k > i
-  if (MODE == 2) kbeg = i0 / kGk * kGk;       // conj(M(k, i)) = 0 for k < i
-  C2 ra[4], rb[4];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      int kk, ii;
-      if (MODE == 2) { kk = e / kGm; ii = e % kGm; }  // contiguous along i
-      else { ii = e / kGk; kk = e % kGk; }            // contiguous along k
-      const int gk = k0 + kk, gi = i0 + ii;
-      C2 v = C2{0, 0};
-      if (gk < kend && gi < a.arows) {
-        if (MODE == 2) {
-          const C2 m = A[(size_t)gk * a.lda + gi];
-          v = C2{m.x, -m.y};
-        } else {
-          v = A[(size_t)gi * a.lda + gk];
-        }
-      }
-      ra[q] = v;
-      const int jj = e / kGk, kb = e % kGk;  // B source-major: contiguous along k
-      const int hk = k0 + kb, gj = j0 + jj;
-      rb[q] = (hk < kend && gj < a.ns) ? B[(size_t)gj * a.ldb + hk] : C2{0, 0};
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      int kk, ii;
-      if (MODE == 2) { kk = e / kGm; ii = e % kGm; }
-      else { ii = e / kGk; kk = e % kGk; }
-      As[buf][kk][ii] = ra[q];
-      Bs[buf][e % kGk][e / kGk] = rb[q];
-    }
-  };
-  if (kbeg < kend) gload(kbeg);
-  int buf = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += kGk, buf ^= 1) {
-    sstore(buf);
-    __syncthreads();
-    if (k0 + kGk < kend) gload(k0 + kGk);
-#pragma unroll
-    for (int s = 0; s < kGk / 4; ++s) {
-      const int kk = 4 * s + l4;
-      C2 av[2], bv[2];
-#pragma unroll
-      for (int it = 0; it < 2; ++it) av[it] = As[buf][kk][wi + 16 * it + l16];
-#pragma unroll
-      for (int jt = 0; jt < 2; ++jt) bv[jt] = Bs[buf][kk][wj + 16 * jt + l16];
-#pragma unroll
-      for (int jt = 0; jt < 2; ++jt)
-#pragma unroll
-        for (int it = 0; it < 2; ++it) {
-          dr[jt][it] = Mfma<T>::mac(bv[jt].x, av[it].x, dr[jt][it]);
-          dr[jt][it] = Mfma<T>::mac(-bv[jt].y, av[it].y, dr[jt][it]);
-          di[jt][it] = Mfma<T>::mac(bv[jt].x, av[it].y, di[jt][it]);
-          di[jt][it] = Mfma<T>::mac(bv[jt].y, av[it].x, di[jt][it]);
-        }
-    }
-  }
-  // lane holds D(row(lane / 16, v), lane % 16) of tile (jt, it)
-#pragma unroll
-  for (int jt = 0; jt < 2; ++jt)
-#pragma unroll
-    for (int it = 0; it < 2; ++it)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = j0 + wj + 16 * jt + Mfma<T>::row(l4, v);
-        const int i = i0 + wi + 16 * it + l16;
-        if (j >= a.ns || i >= a.n) continue;
-        epi_store<EPI>(a, f, j, i, (double)dr[jt][it][v], (double)di[jt][it][v]);
-      }
-}
-
-template <typename T, int MODE, int EPI>
-hipError_t run_gemm_mfma(const GemmArgs& a, int nf, hipStream_t st) {
-  dim3 grid(cdiv(a.ns, kGn), cdiv(a.n, kGm), nf);
-  hipLaunchKernelGGL((k_cgemm_mfma<T, MODE, EPI>), grid, dim3(256), 0, st, a);
-  return hipGetLastError();
-}
-
-// Split-K form of the same products for the deblur (C has as many rows as
-// there are receivers, a few hundred): a 32 x 32 tile of C per workgroup, so
-// the grid holds about four times as many workgroups and triangular tiles
-// are skipped at 32-row granularity.  The tile's K range is dealt out to the
+// The deblur's products (C has as many rows as there are receivers, a few
+// hundred), split-K: a 32 x 32 tile of C per workgroup, so the grid holds
+// about four times as many workgroups as with 64 x 64 tiles (the form this
+// replaced, measured slower at every size from 16 to 400 receivers) and
+// triangular tiles are skipped at 32-row granularity.  The tile's K range is dealt out to the
 // four waves in slices of 4 (slice m of wave w: k = kbeg + 16 m + 4 w + 0..3),
 // each wave accumulating the whole tile (2 x 2 matrix-core tiles of 16 x 16)
 // over its slices, with operands read straight from memory (M, Qhat and the
 // right-hand sides of one frequency are L2-resident) and kept PF slices
 // ahead in registers.  The four partial tiles are then summed through LDS in
 // a fixed order, wave w finishing tile (w >> 1, w & 1).  The longest chain of
-// dependent matrix-core steps is a quarter of the 64 x 64 form's.
+// dependent matrix-core steps is a quarter of a 64 x 64 tile's.
 constexpr int kSkT = 32;
 
 // Operand loads of the split-K products through buffer resources: an offset
@@ -655,27 +550,6 @@ hipError_t run_gemm_sk(const GemmArgs& a, int nf, hipStream_t st) {
   return hipGetLastError();
 }
 
-// The deblur's products: the split-K 32 x 32 form where the 64 x 64 form
-// would leave CUs idle (fewer workgroups than CUs) or, with fewer than 2048
-// workgroups, pad a dimension further than 32-row tiles do (200 receivers:
-// 256 against 224); the 64 x 64 form otherwise (measured from 16 to 400
-// receivers and sources, 200 receivers x 2000 sources, and the sizes of the
-// batched surveys: the 64 x 64 form is ahead without the extra padding, at
-// 256 receivers and sources, and with 3840 of its workgroups).
-// EHI_SOLVE_TILE = 32 or 64 forces a form (tuning and measurement only).
-template <typename T, int MODE, int EPI>
-hipError_t run_solve_gemm(const GemmArgs& a, int nf, hipStream_t st) {
-  static const int forced = [] {
-    const char* e = std::getenv("EHI_SOLVE_TILE");
-    const int v = e ? std::atoi(e) : 0;
-    return v == 32 || v == 64 ? v : 0;
-  }();
-  const long long g64 = (long long)cdiv(a.ns, kGn) * cdiv(a.n, kGm) * nf;
-  const bool pads = cdiv(a.n, kGm) * kGm > cdiv(a.n, kSkT) * kSkT || cdiv(a.ns, kGn) * kGn > cdiv(a.ns, kSkT) * kSkT;
-  bool sk = g64 < 256 || (g64 < 2048 && pads);
-  if (forced) sk = forced == 32;
-  return sk ? run_gemm_sk<T, MODE, EPI>(a, nf, st) : run_gemm_mfma<T, MODE, EPI>(a, nf, st);
-}
 
 // Largest eigenvalue of each Hhat(w) by power iteration in FP64 (one workgroup
 // per frequency), Rayleigh quotient of the final vector.  Eight lanes per row
@@ -773,16 +647,16 @@ hipError_t launch_apply(const Geometry& g, const float2* m32, const double2* qha
   a.A = m32; a.sA = npp; a.lda = np; a.arows = np; a.kdim = n;
   a.B = R + (size_t)s0 * n; a.sB = (size_t)rld * n; a.ldb = n;
   a.C = y32; a.sC = sv; a.ldc = n;
-  hipError_t e = run_solve_gemm<float, 1, kEpiStore>(a, g.nf, st);
+  hipError_t e = run_gemm_sk<float, 1, kEpiStore>(a, g.nf, st);
   if (e != hipSuccess) return e;
   // X = M^H Y
   a.B = y32; a.sB = sv; a.ldb = n;
   if (refine == 0) {
     a.C = out + (size_t)s0 * n; a.sC = (size_t)rld * n; a.ldc = n;
-    return run_solve_gemm<float, 2, kEpiStore>(a, g.nf, st);
+    return run_gemm_sk<float, 2, kEpiStore>(a, g.nf, st);
   }
   a.X = x64; a.sX = sv; a.ldx = n;
-  e = run_solve_gemm<float, 2, kEpiX64Set>(a, g.nf, st);
+  e = run_gemm_sk<float, 2, kEpiX64Set>(a, g.nf, st);
   if (e != hipSuccess) return e;
   for (int it = 0; it < refine; ++it) {
     // r = R - Qhat X (FP64)
@@ -791,23 +665,23 @@ hipError_t launch_apply(const Geometry& g, const float2* m32, const double2* qha
     q.B = x64; q.sB = sv; q.ldb = n;
     q.R = R + (size_t)s0 * n; q.sR = (size_t)rld * n; q.ldr = n;
     q.C = r32; q.sC = sv; q.ldc = n;
-    e = run_solve_gemm<double, 0, kEpiResid>(q, g.nf, st);
+    e = run_gemm_sk<double, 0, kEpiResid>(q, g.nf, st);
     if (e != hipSuccess) return e;
     // Y = M r
     GemmArgs y = a;
     y.A = m32; y.sA = npp; y.lda = np; y.arows = np; y.kdim = n;
     y.B = r32; y.sB = sv; y.ldb = n;
     y.C = y32; y.sC = sv; y.ldc = n;
-    e = run_solve_gemm<float, 1, kEpiStore>(y, g.nf, st);
+    e = run_gemm_sk<float, 1, kEpiStore>(y, g.nf, st);
     if (e != hipSuccess) return e;
     // X += M^H Y (the last step writes the complex64 result)
     GemmArgs x = y;
     x.B = y32;
     if (it + 1 < refine) {
-      e = run_solve_gemm<float, 2, kEpiX64Add>(x, g.nf, st);
+      e = run_gemm_sk<float, 2, kEpiX64Add>(x, g.nf, st);
     } else {
       x.C = out + (size_t)s0 * n; x.sC = (size_t)rld * n; x.ldc = n;
-      e = run_solve_gemm<float, 2, kEpiOut>(x, g.nf, st);
+      e = run_gemm_sk<float, 2, kEpiOut>(x, g.nf, st);
     }
     if (e != hipSuccess) return e;
   }

@@ -15,9 +15,9 @@ grid partitions and ends on a ragged tail.
 Factor + solve from a given Hessian (the oracle's FP64 Hhat of the same
 spectra, mu = 1e-3 lambda_max, so cond(Qhat) ~ 1e3 as in the surveys' low
 frequencies) at 1, 33, 200, 256, 400 and 1024 receivers: the FP64 factor against scipy's, the
-multipliers of 64 sources against the oracle's solve (the split-K 32 x 32 deblur
-products; 47 sources at 200 receivers for a ragged source tile), and of 1408
-sources at 256 receivers (enough right-hand sides for the 64 x 64 products).
+multipliers of 64 sources against the oracle's solve (47 sources at 200
+receivers for a ragged source tile, 1408 at 256 receivers for a wide grid of
+source tiles).
 
 Tolerances: 1e-6 per frequency for the split-BF16 Hessian at the default
 partition counts (2e-6 for the forms and partition counts the autotuner may
