@@ -10,7 +10,7 @@
 // (block-column recursion below) and kept as a zero-padded complex64 matrix, so
 // every solve is a dense batched product over (row tile, source tile,
 // frequency) with no sequential dependency between rows.  In the split-BF16
-// precision mode refinement steps follow (one by default, 0-3 selectable):
+// precision mode refinement steps follow (one by default, 0-4 selectable):
 // r = R - Qhat X in FP64 (X kept in FP64), X += M^H (M r) in FP32.  These products run on the matrix cores
 // (k_cgemm_sk); k_cgemm, a 64 x 64 tiling on FMAs with a choice of B layout
 // and of the summation type, serves the DCT passes and the compressed
