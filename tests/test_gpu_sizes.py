@@ -15,9 +15,9 @@ grid partitions and ends on a ragged tail.
 Factor + solve from a given Hessian (the oracle's FP64 Hhat of the same
 spectra, mu = 1e-3 lambda_max, so cond(Qhat) ~ 1e3 as in the surveys' low
 frequencies) at 1, 33, 200, 256, 400 and 1024 receivers: the FP64 factor against scipy's, the
-multipliers of 64 sources against the oracle's solve (47 sources at 200
-receivers for a ragged source tile, 1408 at 256 receivers for a wide grid of
-source tiles).
+multipliers of 64 sources against the oracle's solve (a single source at 33
+receivers, 47 sources at 200 receivers for a ragged source tile, 1408 at 256
+receivers for a wide grid of source tiles).
 
 Tolerances: 1e-6 per frequency for the split-BF16 Hessian at the default
 partition counts (2e-6 for the forms and partition counts the autotuner may
@@ -85,8 +85,8 @@ def test_hessian_from_given_spectra_sizes(ehi, nr, prec):
         assert np.all(d.imag == 0) and np.all(d.real > 0)
 
 
-@pytest.mark.parametrize("nr,ns", [(1, 64), (33, 64), (200, 64), (200, 47), (256, 64), (256, 1408), (400, 64),
-                                   (1024, 64)])
+@pytest.mark.parametrize("nr,ns", [(1, 64), (33, 1), (33, 64), (200, 64), (200, 47), (256, 64), (256, 1408),
+                                   (400, 64), (1024, 64)])
 def test_factor_and_solve_from_given_hessian_sizes(ehi, nr, ns):
     s = _survey(nr, ns)
     _, H = _spectra(nr)
