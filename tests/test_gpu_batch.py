@@ -97,17 +97,27 @@ def test_largest_batch_survey_sampled_against_oracle(mods):
     # size, including the whole-matrix contraction's 4 x 4 tiles of block
     # pairs (receivers past 224); six receivers spread over different 32-row
     # blocks and tiles are checked against the oracle's Green functions and the
-    # Hessian block among them
+    # Hessian block among them, and all multipliers against the oracle's solve
+    # of the GPU's Hessian
     ehi, _ = mods
     s = synth.batch_survey(1, nt=64)
     v = s.velocity()
     sample = [0, 57, 130, 229, 311, 399]
-    sv = ehi.survey_from(s, precision="split_bf16", max_ns=1)
+    sv = ehi.survey_from(s, precision="split_bf16")
     sv.build_green(torch.from_numpy(v).cuda())
     sv.build_hessian()
     G = sv.copy_green_dft().reshape(s.nf, s.nr, -1)
     H = sv.copy_hessian()
+    # the deblur of all 400 sources at 40 frequencies from this Hessian,
+    # against the oracle's solve of the same Hessian
+    Hn = H.cpu().numpy()
+    mu = 1e-3 * solve.lambda_max(Hn)
+    sv.factor(mu)
+    R = s.residuals()
+    X = sv.apply_multipliers(torch.from_numpy(R).cuda()).cpu().numpy()
     sv.close()
+    Xo = solve.multipliers(Hn, mu, R.astype(np.complex128))
+    check(X, Xo, 1e-7, 1.5e-7, 2e-7, "batch survey 1 (400 receivers, 400 sources) multipliers from its Hessian")
     Gs = G[:, sample].cpu().numpy()
     Hs = H[:, sample][:, :, sample].cpu().numpy()
     Go = fd.green_dft(s, v, receivers=sample)
